@@ -1,0 +1,289 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector library libsv.so.
+ *
+ * The library applies quantum gates to dense complex64 state vectors held in
+ * GPU memory, reduces them to Pauli expectation values in FP64, computes
+ * adjoint gradients by un-applying gates, and runs batches of uneven-size
+ * circuits in one launch. Everything runs in hand-written HIP kernels.
+ *
+ * Conventions (all entry points):
+ *   - Qubit q is bit q of the amplitude index (qubit 0 = least significant).
+ *     The paper's tensor view (Sec. 4.1.1) holds one tensor dimension per
+ *     qubit; in a flat row-major vector that dimension is one index bit.
+ *   - A state row is 2^n complex64 amplitudes, (re, im) interleaved as two
+ *     floats: the paper's layout with real/imaginary parts as the last tensor
+ *     dimension (Sec. 4.2, Fig. 1). A state holds `batch` rows back to back
+ *     (the batch dimension of Sec. 4.2).
+ *   - A gate is (M, Q) (Sec. 4.1.1): a 2^k x 2^k matrix M and an ordered
+ *     target list Q. Q[0] is the most significant bit of M's row/column index
+ *     (MoveDim moves Q to the front in order; Alg. 1). Matrices are passed
+ *     from the host as complex128, row-major, (re, im) interleaved doubles.
+ *     Controls: the gate acts only on amplitudes whose control bits are all 1.
+ *   - Pauli strings use masks: bit q of x_mask is set for X or Y on qubit q,
+ *     bit q of z_mask for Z or Y (Y = iXZ).
+ *   - Every entry point returns sv_status and never throws or aborts across
+ *     the ABI. Arguments are validated before any GPU work is queued, so a
+ *     validation error leaves the state unchanged. sv_last_error() gives a
+ *     readable detail of the last failure on the calling thread.
+ *   - Host arrays passed in are read (and, where needed, copied) before the
+ *     call returns; the caller may free them at once. Gate calls are
+ *     asynchronous on the state's stream; calls that return host results
+ *     synchronise that stream.
+ *   - A state is not thread-safe: calls on one state must not overlap.
+ */
+#ifndef LIBSV_SV_H_
+#define LIBSV_SV_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sv_status {
+    SV_OK = 0,
+    SV_ERR_INVALID_ARGUMENT = 1,   /* null pointer, bad size or mode */
+    SV_ERR_QUBIT_OUT_OF_RANGE = 2, /* a target/control is < 0 or >= n */
+    SV_ERR_QUBIT_OVERLAP = 3,      /* a qubit is named twice among targets/controls */
+    SV_ERR_UNSUPPORTED = 4,        /* k or control count beyond what the kernels take */
+    SV_ERR_OUT_OF_MEMORY = 5,      /* a device allocation failed */
+    SV_ERR_HIP = 6,                /* a HIP runtime call failed; state contents undefined */
+    SV_ERR_CAPTURE = 7,            /* a synchronising call while the stream is capturing */
+    SV_ERR_NOT_UNITARY = 8         /* SV_FLAG_CHECK_UNITARY and ||M M^* - I||_max > 1e-6 */
+} sv_status;
+
+/* Flags for sv_apply_gate. */
+#define SV_FLAG_ADJOINT 1u        /* apply M^* instead of M (un-apply, Sec. 4.4) */
+#define SV_FLAG_CHECK_UNITARY 2u  /* reject non-unitary M (unitarity is otherwise the caller's duty, Sec. 3) */
+
+/* Limits of the kernels. */
+#define SV_MAX_QUBITS 34          /* 2^34 complex64 = 128 GiB per row */
+#define SV_MAX_GATE_TARGETS 2     /* sv_apply_gate / sv_run: k <= 2 */
+#define SV_MAX_FUSED_TARGETS 5    /* sv_apply_fused: k <= 5 */
+#define SV_MAX_CONTROLS 3
+
+typedef struct sv_state_s* sv_state;
+
+/* --------------------------------------------------------------- states */
+
+/* Create a state of `batch` rows of n_qubits each (Sec. 2.2.1: 2^n complex
+ * amplitudes per state; Sec. 4.2: batch dimension first).
+ *   device_buffer: NULL -> the library allocates batch * 2^n * 8 bytes of
+ *     device memory (256-byte aligned) and frees it in sv_free; otherwise a
+ *     caller-owned device buffer of at least that size (e.g. a torch complex64
+ *     tensor), 16-byte aligned, which must outlive the state.
+ *   stream: a hipStream_t every kernel of this state is queued on (NULL =
+ *     the default stream).
+ * The contents are not initialised; call sv_reset. Errors:
+ * SV_ERR_INVALID_ARGUMENT (n_qubits outside [1, SV_MAX_QUBITS], batch < 1,
+ * out == NULL), SV_ERR_OUT_OF_MEMORY, SV_ERR_HIP. */
+sv_status sv_alloc(int n_qubits, int batch, void* device_buffer, void* stream, sv_state* out);
+
+/* Release the state and everything the library allocated for it (its own
+ * amplitude buffer, the adjoint buffer, reduction scratch). Waits for the
+ * state's stream. NULL is accepted. */
+sv_status sv_free(sv_state s);
+
+/* Device pointer of row 0 (rows follow at a stride of 2^n amplitudes). */
+sv_status sv_device_ptr(sv_state s, void** out);
+
+/* Every row := e_idx (the basis state |idx>; idx = 0 gives |0..0>, the start
+ * state of a circuit). Asynchronous. SV_ERR_INVALID_ARGUMENT if idx >= 2^n. */
+sv_status sv_reset(sv_state s, uint64_t idx);
+
+/* Copy all rows between the state and host memory (complex64, batch * 2^n *
+ * 8 bytes). to_host = 1: device -> host, then the stream is synchronised;
+ * to_host = 0: host -> device, synchronised before return. */
+sv_status sv_copy_state(sv_state s, void* host, int to_host);
+
+/* ---------------------------------------------------------------- gates */
+
+/* psi <- (M on targets, controlled by controls) psi on every row (Alg. 1 /
+ * Alg. 2 of Sec. 4.1.1; both give this result).
+ *   targets[n_targets], 1 <= n_targets <= SV_MAX_GATE_TARGETS, ordered.
+ *   controls[n_controls], 0 <= n_controls <= SV_MAX_CONTROLS (may be NULL if 0).
+ *   matrix: host complex128, row-major 2^k x 2^k, interleaved (re, im).
+ *   matrix_batch_stride: 0 = one matrix for all rows; otherwise row r uses
+ *     matrix + 2 * r * matrix_batch_stride doubles (per-row gates, e.g. an
+ *     angle-encoded input that differs per batch row).
+ *   flags: SV_FLAG_ADJOINT, SV_FLAG_CHECK_UNITARY.
+ * The matrix is rounded to complex64 for the kernel. Diagonal, permutation
+ * and dense matrices take different kernels; the result is the same.
+ * Errors: SV_ERR_QUBIT_OUT_OF_RANGE, SV_ERR_QUBIT_OVERLAP, SV_ERR_UNSUPPORTED
+ * (k or control count too large), SV_ERR_NOT_UNITARY, SV_ERR_HIP. */
+sv_status sv_apply_gate(sv_state s, const int* targets, int n_targets, const int* controls,
+                        int n_controls, const double* matrix, int64_t matrix_batch_stride,
+                        unsigned flags);
+
+/* Named gate kinds for circuits (sv_op.kind). Rotations are
+ * R_P(theta) = exp(-i theta P / 2) (the Pauli rotations of Sec. 3);
+ * U3(theta, phi, lambda) = [[c, -e^{i lambda} s], [e^{i phi} s,
+ * e^{i(phi+lambda)} c]] with c = cos(theta/2), s = sin(theta/2);
+ * P(lambda) = diag(1, e^{i lambda}); RXX/RYY/RZZ = exp(-i theta P(x)P / 2).
+ * CNOT is SV_X with one control, CZ is SV_Z with one control. */
+typedef enum sv_kind {
+    SV_H = 1, SV_X = 2, SV_Y = 3, SV_Z = 4, SV_S = 5, SV_SDG = 6, SV_T = 7, SV_TDG = 8,
+    SV_SX = 9, SV_RX = 10, SV_RY = 11, SV_RZ = 12, SV_P = 13, SV_U3 = 14, SV_SWAP = 15,
+    SV_RXX = 16, SV_RYY = 17, SV_RZZ = 18, SV_MATRIX = 19
+} sv_kind;
+
+/* One gate of a circuit. Unused array slots are ignored. */
+typedef struct sv_op {
+    int32_t kind;                 /* sv_kind */
+    int32_t n_targets;            /* 1 or 2 (must match the kind; SV_MATRIX: 1..2) */
+    int32_t targets[2];
+    int32_t n_controls;           /* 0..SV_MAX_CONTROLS */
+    int32_t controls[SV_MAX_CONTROLS];
+    int32_t param[3];             /* indices into the params vector, -1 = unused */
+    const double* matrix;         /* SV_MATRIX only: host complex128 2^k x 2^k */
+} sv_op;
+
+/* Apply a gate list in order (each op as sv_apply_gate would).
+ *   params: host doubles; row r of the batch reads
+ *     params[r * params_batch_stride + op.param[j]] (stride 0 = shared).
+ *   n_params: length of one row of params (indices are checked against it).
+ * Validates every op before queuing any. Errors as sv_apply_gate. */
+sv_status sv_run(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                 int64_t params_batch_stride, int n_params);
+
+/* ---------------------------------------------------------- fused blocks */
+
+/* A fused gate block: one 2^k x 2^k complex128 matrix on k <= 5 ordered
+ * targets (Alg. 1 with |Q| = k), the product of several gates. */
+typedef struct sv_block {
+    int32_t k;
+    int32_t targets[SV_MAX_FUSED_TARGETS];
+    const double* matrix;         /* host complex128, row-major 2^k x 2^k */
+} sv_block;
+
+/* Arithmetic of sv_apply_fused. */
+#define SV_FUSED_FP32_MFMA 0      /* FP32 MFMA products, FP32 accumulation */
+#define SV_FUSED_BF16X3 1         /* split BF16 (hi + lo) MFMA, 3 products, FP32 accumulation */
+#define SV_FUSED_VALU 2           /* FP32 vector FMAs (no matrix cores) */
+
+/* Apply the blocks in order to every row. Each block is one sweep over the
+ * state: the 2^k amplitudes that differ only in the target bits form a
+ * column, and the block computes Y = M X over all 2^(n-k) columns.
+ * Errors: SV_ERR_INVALID_ARGUMENT (bad mode, k outside 1..5 or n < k + 5
+ * for the MFMA modes), SV_ERR_QUBIT_*, SV_ERR_HIP. */
+sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_blocks, int mode);
+
+/* Host-only fusion planner (no GPU work): group the gates of a circuit, in
+ * order, into blocks of at most max_k qubits (controls count as qubits) and
+ * multiply each block's gates into one complex128 matrix. Gates on disjoint
+ * qubits may move past each other; no gate moves past one it shares a qubit
+ * with, so the block sequence equals the circuit.
+ *   out_blocks[max_blocks]: block descriptors; their matrix pointers point
+ *     into out_matrices.
+ *   out_matrices: room for max_blocks * 4^max_k complex128 (2 doubles each).
+ *   *n_blocks_out: number of blocks written.
+ * Errors: SV_ERR_INVALID_ARGUMENT (max_k outside 1..5, too little room). */
+sv_status sv_fuse_plan(int n_qubits, const sv_op* ops, int n_ops, const double* params,
+                       int n_params, int max_k, sv_block* out_blocks, int max_blocks,
+                       double* out_matrices, int* n_blocks_out);
+
+/* --------------------------------------------------------- expectations */
+
+/* A Pauli term coeff * P with P given by its masks. */
+typedef struct sv_pauli_term {
+    uint64_t x_mask;
+    uint64_t z_mask;
+    double coeff;
+} sv_pauli_term;
+
+/* out[r * n_terms + t] = coeff_t * <psi_r| P_t |psi_r> (Sec. 2.2.1: Z-basis
+ * measurement statistics; general Pauli strings), accumulated in FP64 in a
+ * fixed order (bitwise reproducible run to run). out is host memory; the
+ * stream is synchronised. Errors: SV_ERR_INVALID_ARGUMENT (mask bits >= n,
+ * n_terms < 1), SV_ERR_CAPTURE, SV_ERR_HIP. */
+sv_status sv_expval_pauli(sv_state s, const sv_pauli_term* terms, int n_terms, double* out);
+
+/* All single-qubit Z expectations in one sweep (the paper's measure_allZ,
+ * Appendix A): out[r * (n + 1) + i] = <Z_i> for i < n and out[r * (n + 1) + n]
+ * = ||psi_r||^2. <sum_i Z_i> is the sum of the first n. FP64, fixed order;
+ * host output, stream synchronised. */
+sv_status sv_expval_z_all(sv_state s, double* out);
+
+/* ------------------------------------------------------------- adjoint */
+
+/* Gradient of L_r = <psi_r| O |psi_r>, O = sum_t coeff_t P_t, with respect
+ * to every parameter, for a state that holds the output of sv_run(ops,
+ * params) on every row. Instead of storing intermediate states, each gate's
+ * input is recomputed from its output as x = U^* y (Sec. 4.4):
+ *     lam <- O psi;  for l = L..1: psi <- U_l^* psi;
+ *     g[p] += 2 Re <lam| dU_l/dtheta_p |psi>;  lam <- U_l^* lam.
+ * The inner products are FP64.
+ *   grad_out: host [batch][n_params]; loss_out: host [batch] (may be NULL);
+ *   drift_out: host [batch] (may be NULL) = || psi_recomputed - e_0 ||, the
+ *     distance of the recovered start state from |0..0> (meaningful when the
+ *     forward pass started there).
+ *   lambda_buffer: NULL -> the library allocates (once, cached in the state)
+ *     a second buffer of the state's size; otherwise caller-owned device
+ *     memory of batch * 2^n * 8 bytes.
+ * On return the state holds the recomputed start state. Errors as sv_run,
+ * plus SV_ERR_CAPTURE; SV_ERR_UNSUPPORTED for SV_MATRIX ops carrying params. */
+sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                          int64_t params_batch_stride, int n_params,
+                          const sv_pauli_term* obs, int n_obs, void* lambda_buffer,
+                          double* grad_out, double* loss_out, double* drift_out);
+
+/* -------------------------------------------------------------- batching */
+
+typedef struct sv_batch_plan_s* sv_batch_plan;
+
+/* Plan a batch of independent circuits of uneven size (1 <= n_qubits[c] <=
+ * 24), each started from |0..0> and measured as every <Z_i>, to be run by ONE
+ * persistent kernel launch captured in a hipGraph (the batch dimension of
+ * Sec. 4.2 generalised to different qubit counts).
+ *   ops[c][n_ops[c]]: circuit c. Only the kinds of SV_H..SV_RZZ (no SV_MATRIX).
+ *   n_params[c]: length of circuit c's parameter row.
+ *   stream: the hipStream_t the graph is launched on.
+ * The plan owns device arenas for the states and gate tables. Errors:
+ * SV_ERR_INVALID_ARGUMENT, SV_ERR_QUBIT_*, SV_ERR_UNSUPPORTED, SV_ERR_HIP. */
+sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op* const* ops,
+                               const int* n_ops, const int* n_params, void* stream,
+                               sv_batch_plan* out);
+
+/* Number of doubles in the parameter block the launch reads: circuit c's
+ * parameter j is at offset param_offset[c] + j. */
+sv_status sv_batch_param_layout(sv_batch_plan p, int64_t* param_offsets, int64_t* total);
+
+/* Run every circuit once: one graph launch, asynchronous on the plan's
+ * stream.
+ *   dev_params: device doubles laid out as sv_batch_param_layout says (read
+ *     at launch time, so they may change between launches).
+ *   dev_out: device doubles [n_circuits][SV_BATCH_OUT_STRIDE]: out[c][i] =
+ *     <Z_i> of circuit c for i < n_qubits[c], the rest 0. */
+#define SV_BATCH_OUT_STRIDE 32
+sv_status sv_batch_launch(sv_batch_plan p, const double* dev_params, double* dev_out);
+
+/* Same work as sv_batch_launch without the graph: one kernel launch per gate
+ * per circuit (the plain per-gate form the batched launch is compared with). */
+sv_status sv_batch_launch_pergate(sv_batch_plan p, const double* dev_params, double* dev_out);
+
+sv_status sv_batch_plan_free(sv_batch_plan p);
+
+/* ------------------------------------------------------------- utility */
+
+/* Plain device-to-device copy kernel of `bytes` (multiple of 16, 16-byte
+ * aligned pointers) on `stream`: the measured bandwidth ceiling used to scale
+ * hardware byte counters. Asynchronous. */
+sv_status sv_stream_copy(void* dst, const void* src, uint64_t bytes, void* stream);
+
+/* Static description of a status code. Never NULL. */
+const char* sv_status_string(sv_status st);
+
+/* Detail text of the last failure on this thread ("" if none). Valid until
+ * the next call on this thread. */
+const char* sv_last_error(void);
+
+/* Check gate arguments without a state or GPU (host only): the same checks
+ * sv_apply_gate makes before queuing work. */
+sv_status sv_check_gate(int n_qubits, const int* targets, int n_targets, const int* controls,
+                        int n_controls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBSV_SV_H_ */

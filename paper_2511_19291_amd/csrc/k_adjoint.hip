@@ -1,0 +1,218 @@
+// k_adjoint.hip -- the adjoint backward: un-apply one gate from the state and
+// from the co-state in the same sweep, and accumulate the gradient inner
+// products of that gate's parameters in FP64.
+//
+// Sec. 4.4: for y = U x the backward recomputes the input as x = U^* y
+// instead of storing it. With psi_l = U_l psi_{l-1}, lam_l = U_{l+1}^* ...
+// U_L^* O psi_L, the derivative of L = <psi_L|O|psi_L> with respect to a
+// parameter theta of U_l is 2 Re <lam_l| dU_l/dtheta |psi_{l-1}>
+// = 2 Re <lam_l| G |psi_l> with G = dU_l/dtheta U_l^*. Every quantity is local
+// to the gate's amplitude group, so one sweep reads psi_l and lam_l, adds
+// Re <lam_l|G|psi_l> over the group, and writes psi_{l-1} = U^* psi_l and
+// lam_{l-1} = U^* lam_l back.
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+struct KAdj {
+    Rows psi;
+    Rows lam;
+    uint64_t n_units;
+    uint64_t cmask;
+    uint64_t moff[4];
+    int npos;
+    int pos[6];
+    int nd;
+    float2 uinv[16];
+    double2 g[3][16];
+};
+
+__device__ __forceinline__ float2* mrow(const Rows& r, int row)
+{
+    return row < r.nrow0 ? r.p0 + (uint64_t)row * r.N : r.p1 + (uint64_t)(row - r.nrow0) * r.N;
+}
+
+template <int D>
+__device__ __forceinline__ void adj_group(const KAdj& a, const float2 (&x)[D], const float2 (&l)[D],
+                                          float2 (&xo)[D], float2 (&lo)[D], double (&acc)[3])
+{
+    // gradient terms: Re sum_i conj(l_i) (G_d x)_i in FP64
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d >= a.nd) break;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double mr = 0.0, mi = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const double2 g = a.g[d][i * D + j];
+                mr += g.x * x[j].x - g.y * x[j].y;
+                mi += g.x * x[j].y + g.y * x[j].x;
+            }
+            acc[d] += (double)l[i].x * mr + (double)l[i].y * mi;
+        }
+    }
+    // un-apply
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float2 s = cmul(a.uinv[i * D], x[0]);
+        float2 t = cmul(a.uinv[i * D], l[0]);
+#pragma unroll
+        for (int j = 1; j < D; ++j) {
+            s = cfma(a.uinv[i * D + j], x[j], s);
+            t = cfma(a.uinv[i * D + j], l[j], t);
+        }
+        xo[i] = s;
+        lo[i] = t;
+    }
+}
+
+// VEC = 2: float4 accesses (two neighbouring amplitudes per member; every
+// target/control >= 1). VEC = 1: float2 accesses. Fixed grid with a
+// grid-stride loop so each block's share (and the summation order) is fixed.
+template <int K, int VEC>
+__global__ __launch_bounds__(kBlock) void k_adj(KAdj a, double* part)
+{
+    constexpr int D = 1 << K;
+    const int row = blockIdx.y;
+    float2* psi = mrow(a.psi, row);
+    float2* lam = mrow(a.lam, row);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t u = (uint64_t)blockIdx.x * kBlock + threadIdx.x; u < a.n_units; u += stride) {
+        if constexpr (VEC == 2) {
+            const uint64_t base = insert_zeros(u << 1, a.pos, a.npos) | a.cmask;
+            float4 vx[D], vl[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                vx[j] = *reinterpret_cast<const float4*>(psi + (base | a.moff[j]));
+                vl[j] = *reinterpret_cast<const float4*>(lam + (base | a.moff[j]));
+            }
+            float2 x0[D], l0[D], x1[D], l1[D], xo0[D], lo0[D], xo1[D], lo1[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                x0[j] = lo2(vx[j]); x1[j] = hi2(vx[j]);
+                l0[j] = lo2(vl[j]); l1[j] = hi2(vl[j]);
+            }
+            adj_group<D>(a, x0, l0, xo0, lo0, acc);
+            adj_group<D>(a, x1, l1, xo1, lo1, acc);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                *reinterpret_cast<float4*>(psi + (base | a.moff[j])) = pack4(xo0[j], xo1[j]);
+                *reinterpret_cast<float4*>(lam + (base | a.moff[j])) = pack4(lo0[j], lo1[j]);
+            }
+        } else {
+            const uint64_t base = insert_zeros(u, a.pos, a.npos) | a.cmask;
+            float2 x[D], l[D], xo[D], lo[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                x[j] = psi[base | a.moff[j]];
+                l[j] = lam[base | a.moff[j]];
+            }
+            adj_group<D>(a, x, l, xo, lo, acc);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                psi[base | a.moff[j]] = xo[j];
+                lam[base | a.moff[j]] = lo[j];
+            }
+        }
+    }
+    block_sum<3>(acc);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < a.nd; ++d) part[((uint64_t)row * a.nd + d) * gridDim.x + blockIdx.x] = acc[d];
+}
+
+// lam[c] = sum_t coeff_t i^{y_t} (-1)^{|(c ^ x_t) & z_t|} psi[c ^ x_t]
+// (O psi for O = sum_t coeff_t P_t, written as a gather so every output
+// amplitude is produced by one thread).
+__global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t N, const PauliTermDev* terms, int nt)
+{
+    const int row = blockIdx.y;
+    const float2* psi = mrow(rp, row);
+    float2* lam = mrow(rl, row);
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (uint64_t)gridDim.x * kBlock) {
+        double re = 0.0, im = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            const PauliTermDev tm = terms[t];
+            const uint64_t src = c ^ tm.x_mask;
+            const float2 v = psi[src];
+            double s = (__popcll(src & tm.z_mask) & 1) ? -tm.coeff : tm.coeff;
+            // multiply by i^y
+            double vr = v.x, vi = v.y;
+            switch (tm.y_count & 3) {
+            case 0: break;
+            case 1: { const double t0 = vr; vr = -vi; vi = t0; } break;
+            case 2: vr = -vr; vi = -vi; break;
+            case 3: { const double t0 = vr; vr = vi; vi = -t0; } break;
+            }
+            re += s * vr;
+            im += s * vi;
+        }
+        lam[c] = make_float2((float)re, (float)im);
+    }
+}
+
+}  // namespace
+
+int adj_grid(int n, int k, int nc)
+{
+    const uint64_t units = 1ull << (n - k - nc);
+    const uint64_t want = (units + kBlock - 1) / kBlock;
+    const uint64_t cap = (uint64_t)device_info().cu_count * 8;
+    return (int)std::max<uint64_t>(1, std::min(want, cap));
+}
+
+void launch_adj_step(const AdjLaunch& g, double* part, hipStream_t st)
+{
+    const int n = __builtin_ctzll(g.psi.N);
+    KAdj a{};
+    a.psi = g.psi;
+    a.lam = g.lam;
+    const int D = 1 << g.k;
+    for (int i = 0; i < D * D; ++i) a.uinv[i] = g.uinv[i];
+    a.nd = g.nd;
+    for (int d = 0; d < g.nd; ++d)
+        for (int i = 0; i < D * D; ++i) a.g[d][i] = g.g[d][i];
+    for (int r = 0; r < D; ++r) {
+        uint64_t off = 0;
+        for (int j = 0; j < g.k; ++j)
+            if ((r >> (g.k - 1 - j)) & 1) off |= 1ull << g.targets[j];
+        a.moff[r] = off;
+    }
+    int lowest = 64;
+    for (int j = 0; j < g.k; ++j) { a.pos[a.npos++] = g.targets[j]; lowest = std::min(lowest, g.targets[j]); }
+    for (int j = 0; j < g.nc; ++j) {
+        a.pos[a.npos++] = g.controls[j];
+        a.cmask |= 1ull << g.controls[j];
+        lowest = std::min(lowest, g.controls[j]);
+    }
+    for (int i = 1; i < a.npos; ++i)
+        for (int j = i; j > 0 && a.pos[j - 1] > a.pos[j]; --j) std::swap(a.pos[j - 1], a.pos[j]);
+    const uint64_t groups = 1ull << (n - g.k - g.nc);
+    const int grid = adj_grid(n, g.k, g.nc);
+    const dim3 gd(grid, g.psi.nrows);
+    if (lowest >= 1 && groups >= 2) {
+        a.n_units = groups >> 1;
+        if (g.k == 1) hipLaunchKernelGGL((k_adj<1, 2>), gd, dim3(kBlock), 0, st, a, part);
+        else hipLaunchKernelGGL((k_adj<2, 2>), gd, dim3(kBlock), 0, st, a, part);
+    } else {
+        a.n_units = groups;
+        if (g.k == 1) hipLaunchKernelGGL((k_adj<1, 1>), gd, dim3(kBlock), 0, st, a, part);
+        else hipLaunchKernelGGL((k_adj<2, 1>), gd, dim3(kBlock), 0, st, a, part);
+    }
+    SV_HIP(hipGetLastError());
+}
+
+void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
+                            hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    const uint64_t blocks = std::min<uint64_t>((N + kBlock - 1) / kBlock, (uint64_t)device_info().cu_count * 16);
+    hipLaunchKernelGGL(k_pauli_sum, dim3((unsigned)blocks, psi.nrows), dim3(kBlock), 0, st, psi, lam, N, terms, nt);
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace sv

@@ -1,0 +1,676 @@
+// sv_api.cpp -- host runtime behind the C ABI of include/sv.h: state
+// handles, argument validation, gate classification and kernel dispatch,
+// expectation values and the adjoint driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+[[noreturn]] void fail(sv_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) fail(SV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const DeviceInfo& device_info()
+{
+    static std::mutex mu;
+    static std::map<int, DeviceInfo> cache;
+    int dev = 0;
+    SV_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        DeviceInfo d;
+        d.device = dev;
+        SV_HIP(hipDeviceGetAttribute(&d.cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+        it = cache.emplace(dev, d).first;
+    }
+    return it->second;
+}
+
+namespace {
+
+template <class F>
+sv_status guarded(F&& f)
+{
+    try {
+        f();
+        g_last_error.clear();
+        return SV_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return SV_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SV_ERR_INVALID_ARGUMENT;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return SV_ERR_INVALID_ARGUMENT;
+    }
+}
+
+void need(bool ok, sv_status st, const std::string& msg)
+{
+    if (!ok) fail(st, msg);
+}
+
+// ------------------------------------------------------------ validation
+
+void check_gate(int n, const int* targets, int nt, const int* controls, int nc, int max_k)
+{
+    need(nt >= 1 && nt <= max_k, SV_ERR_UNSUPPORTED, "number of targets must be 1.." + std::to_string(max_k));
+    need(nc >= 0 && nc <= SV_MAX_CONTROLS, SV_ERR_UNSUPPORTED, "at most 3 controls");
+    need(targets != nullptr, SV_ERR_INVALID_ARGUMENT, "targets is NULL");
+    need(nc == 0 || controls != nullptr, SV_ERR_INVALID_ARGUMENT, "controls is NULL");
+    need(nt + nc <= n, SV_ERR_UNSUPPORTED, "more gate qubits than state qubits");
+    uint64_t seen = 0;
+    auto one = [&](int q) {
+        need(q >= 0 && q < n, SV_ERR_QUBIT_OUT_OF_RANGE,
+             "qubit " + std::to_string(q) + " out of range for n=" + std::to_string(n));
+        need(!((seen >> q) & 1), SV_ERR_QUBIT_OVERLAP, "qubit " + std::to_string(q) + " used twice");
+        seen |= 1ull << q;
+    };
+    for (int j = 0; j < nt; ++j) one(targets[j]);
+    for (int j = 0; j < nc; ++j) one(controls[j]);
+}
+
+void check_state(sv_state s)
+{
+    need(s != nullptr && s->psi != nullptr, SV_ERR_INVALID_ARGUMENT, "null state");
+}
+
+void check_not_capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SV_HIP(hipStreamIsCapturing(st, &cs));
+    need(cs == hipStreamCaptureStatusNone, SV_ERR_CAPTURE, "synchronising call on a capturing stream");
+}
+
+// ------------------------------------------------------------ scratch
+
+void ensure_scratch(sv_state s, uint64_t doubles)
+{
+    if (doubles <= s->scratch_cap) return;
+    if (s->scratch) {
+        SV_HIP(hipStreamSynchronize(s->stream));
+        SV_HIP(hipFree(s->scratch));
+        s->scratch = nullptr;
+        s->scratch_cap = 0;
+    }
+    if (hipMalloc(&s->scratch, doubles * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        s->scratch = nullptr;
+        fail(SV_ERR_OUT_OF_MEMORY, "reduction scratch allocation failed");
+    }
+    s->scratch_cap = doubles;
+}
+
+void ensure_dout(sv_state s, uint64_t doubles)
+{
+    if (doubles <= s->dout_cap) return;
+    if (s->dout) {
+        SV_HIP(hipStreamSynchronize(s->stream));
+        SV_HIP(hipFree(s->dout));
+        SV_HIP(hipHostFree(s->hout));
+        s->dout = nullptr;
+        s->hout = nullptr;
+        s->dout_cap = 0;
+    }
+    const uint64_t cap = std::max<uint64_t>(doubles, 1024);
+    if (hipMalloc(&s->dout, cap * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SV_ERR_OUT_OF_MEMORY, "output buffer allocation failed");
+    }
+    SV_HIP(hipHostMalloc(&s->hout, cap * sizeof(double), hipHostMallocDefault));
+    s->dout_cap = cap;
+}
+
+// copy `doubles` results from dout to hout and wait
+void fetch(sv_state s, uint64_t doubles)
+{
+    SV_HIP(hipMemcpyAsync(s->hout, s->dout, doubles * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    SV_HIP(hipStreamSynchronize(s->stream));
+}
+
+Rows all_rows(sv_state s) { return Rows{s->psi, s->psi, s->batch, s->batch, s->N}; }
+Rows one_row(sv_state s, float2* base, int r) { return Rows{base + (uint64_t)r * s->N, base, 1, 1, s->N}; }
+
+// ------------------------------------------------------------ gate dispatch
+
+bool is_exact(cd v, double re) { return v.real() == re && v.imag() == 0.0; }
+
+float2 f2(cd v) { return make_float2((float)v.real(), (float)v.imag()); }
+
+// Apply (M, targets, controls) to the given rows, choosing the kernel by the
+// matrix structure: diagonal -> phase sweep (only the changed subspace when
+// M differs from I in its last entry alone), otherwise dense group update.
+void dispatch(const Rows& rows, int k, const int* targets, int nc, const int* controls, const cd* m,
+              hipStream_t st)
+{
+    const int D = 1 << k;
+    bool diag = true, ident = true, ones = true;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            const cd v = m[r * D + c];
+            if (r != c && v != cd(0.0)) diag = false;
+            if (!is_exact(v, r == c ? 1.0 : 0.0)) ident = false;
+            if (r == c && r != D - 1 && !is_exact(v, 1.0)) ones = false;
+        }
+    if (ident) return;
+    if (diag) {
+        DiagLaunch d{};
+        d.rows = rows;
+        for (int j = 0; j < nc; ++j) d.fixed[d.nfixed++] = controls[j];
+        if (ones) {
+            for (int j = 0; j < k; ++j) d.fixed[d.nfixed++] = targets[j];
+            d.nfree = 0;
+            d.ph[0] = f2(m[(D - 1) * D + D - 1]);
+        } else {
+            d.nfree = k;
+            for (int j = 0; j < k; ++j) d.freeq[j] = targets[j];
+            for (int r = 0; r < D; ++r) d.ph[r] = f2(m[r * D + r]);
+        }
+        launch_diag(d, st);
+        return;
+    }
+    GateLaunch g{};
+    g.rows = rows;
+    g.k = k;
+    for (int j = 0; j < k; ++j) g.targets[j] = targets[j];
+    g.nc = nc;
+    for (int j = 0; j < nc; ++j) g.controls[j] = controls[j];
+    for (int i = 0; i < D * D; ++i) g.m[i] = f2(m[i]);
+    launch_gate(g, st);
+}
+
+void dagger(int k, const cd* m, cd* out)
+{
+    const int D = 1 << k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) out[c * D + r] = std::conj(m[r * D + c]);
+}
+
+void check_unitary(int k, const cd* m)
+{
+    const int D = 1 << k;
+    double worst = 0.0;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            cd acc = 0.0;
+            for (int j = 0; j < D; ++j) acc += m[r * D + j] * std::conj(m[c * D + j]);
+            worst = std::max(worst, std::abs(acc - (r == c ? cd(1.0) : cd(0.0))));
+        }
+    need(worst <= 1e-6, SV_ERR_NOT_UNITARY, "matrix is not unitary (max |M M^* - I| = " + std::to_string(worst) + ")");
+}
+
+// ------------------------------------------------------------ ops
+
+struct OpInfo {
+    int k;
+    int np;
+};
+
+OpInfo check_op(int n, const sv_op& op, int n_params)
+{
+    need(op.kind >= SV_H && op.kind <= SV_MATRIX, SV_ERR_INVALID_ARGUMENT, "unknown gate kind " + std::to_string(op.kind));
+    int k = kind_targets(op.kind);
+    if (op.kind == SV_MATRIX) {
+        need(op.matrix != nullptr, SV_ERR_INVALID_ARGUMENT, "SV_MATRIX op without a matrix");
+        k = op.n_targets;
+    }
+    need(op.n_targets == k, SV_ERR_INVALID_ARGUMENT, "n_targets does not match the gate kind");
+    check_gate(n, op.targets, op.n_targets, op.controls, op.n_controls, SV_MAX_GATE_TARGETS);
+    const int np = op.kind == SV_MATRIX ? 0 : kind_nparams(op.kind);
+    for (int j = 0; j < np; ++j)
+        need(op.param[j] >= 0 && op.param[j] < n_params, SV_ERR_INVALID_ARGUMENT,
+             "parameter index " + std::to_string(op.param[j]) + " out of range");
+    return OpInfo{k, np};
+}
+
+// matrix of op for parameter row `prow`
+void op_matrix(const sv_op& op, const OpInfo& info, const double* prow, cd* m)
+{
+    if (op.kind == SV_MATRIX) {
+        const int D = 1 << info.k;
+        for (int i = 0; i < D * D; ++i) m[i] = cd(op.matrix[2 * i], op.matrix[2 * i + 1]);
+        return;
+    }
+    double prm[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < info.np; ++j) prm[j] = prow[op.param[j]];
+    kind_matrix(op.kind, prm, m);
+}
+
+void op_params(const sv_op& op, const OpInfo& info, const double* prow, double* prm)
+{
+    prm[0] = prm[1] = prm[2] = 0.0;
+    for (int j = 0; j < info.np; ++j) prm[j] = prow[op.param[j]];
+}
+
+void ensure_lambda(sv_state s, void* user, float2** lam)
+{
+    if (user) {
+        need((reinterpret_cast<uintptr_t>(user) & 15) == 0, SV_ERR_INVALID_ARGUMENT, "lambda buffer must be 16-byte aligned");
+        *lam = static_cast<float2*>(user);
+        return;
+    }
+    if (!s->lam) {
+        if (hipMalloc(&s->lam, (uint64_t)s->batch * s->N * sizeof(float2)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->lam = nullptr;
+            fail(SV_ERR_OUT_OF_MEMORY, "adjoint buffer allocation failed");
+        }
+    }
+    *lam = s->lam;
+}
+
+void upload_terms(sv_state s, const sv_pauli_term* obs, int n_obs, PauliTermDev** out)
+{
+    std::vector<PauliTermDev> t(n_obs);
+    for (int i = 0; i < n_obs; ++i) {
+        t[i].x_mask = obs[i].x_mask;
+        t[i].z_mask = obs[i].z_mask;
+        t[i].coeff = obs[i].coeff;
+        t[i].y_count = __builtin_popcountll(obs[i].x_mask & obs[i].z_mask);
+        t[i].pad = 0;
+    }
+    const size_t bytes = t.size() * sizeof(PauliTermDev);
+    if (bytes > s->dterms_cap) {
+        if (s->dterms) {
+            SV_HIP(hipStreamSynchronize(s->stream));
+            SV_HIP(hipFree(s->dterms));
+            s->dterms = nullptr;
+        }
+        SV_HIP(hipMalloc(&s->dterms, bytes));
+        s->dterms_cap = bytes;
+    }
+    SV_HIP(hipMemcpyAsync(s->dterms, t.data(), bytes, hipMemcpyHostToDevice, s->stream));
+    // the host vector dies at return: make the copy complete first
+    SV_HIP(hipStreamSynchronize(s->stream));
+    *out = static_cast<PauliTermDev*>(s->dterms);
+}
+
+void check_terms(int n, const sv_pauli_term* terms, int nt)
+{
+    need(terms != nullptr && nt >= 1, SV_ERR_INVALID_ARGUMENT, "need at least one Pauli term");
+    const uint64_t lim = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    for (int i = 0; i < nt; ++i)
+        need((terms[i].x_mask & ~lim) == 0 && (terms[i].z_mask & ~lim) == 0, SV_ERR_QUBIT_OUT_OF_RANGE,
+             "Pauli mask names a qubit >= n");
+}
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_alloc(int n_qubits, int batch, void* device_buffer, void* stream, sv_state* out)
+{
+    return guarded([&] {
+        need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
+        *out = nullptr;
+        need(n_qubits >= 1 && n_qubits <= SV_MAX_QUBITS, SV_ERR_INVALID_ARGUMENT,
+             "n_qubits must be in [1, 34]");
+        need(batch >= 1, SV_ERR_INVALID_ARGUMENT, "batch must be >= 1");
+        need(device_buffer == nullptr || (reinterpret_cast<uintptr_t>(device_buffer) & 15) == 0,
+             SV_ERR_INVALID_ARGUMENT, "device buffer must be 16-byte aligned");
+        auto* s = new sv_state_s;
+        s->n = n_qubits;
+        s->batch = batch;
+        s->N = 1ull << n_qubits;
+        s->stream = static_cast<hipStream_t>(stream);
+        if (device_buffer) {
+            s->psi = static_cast<float2*>(device_buffer);
+        } else {
+            if (hipMalloc(&s->psi, (uint64_t)batch * s->N * sizeof(float2)) != hipSuccess) {
+                (void)hipGetLastError();
+                delete s;
+                fail(SV_ERR_OUT_OF_MEMORY, "state allocation failed");
+            }
+            s->owns = true;
+        }
+        (void)device_info();
+        *out = s;
+    });
+}
+
+sv_status sv_free(sv_state s)
+{
+    return guarded([&] {
+        if (!s) return;
+        (void)hipStreamSynchronize(s->stream);
+        if (s->owns && s->psi) (void)hipFree(s->psi);
+        if (s->lam) (void)hipFree(s->lam);
+        if (s->scratch) (void)hipFree(s->scratch);
+        if (s->dout) (void)hipFree(s->dout);
+        if (s->hout) (void)hipHostFree(s->hout);
+        if (s->dterms) (void)hipFree(s->dterms);
+        delete s;
+    });
+}
+
+sv_status sv_device_ptr(sv_state s, void** out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
+        *out = s->psi;
+    });
+}
+
+sv_status sv_reset(sv_state s, uint64_t idx)
+{
+    return guarded([&] {
+        check_state(s);
+        need(idx < s->N, SV_ERR_INVALID_ARGUMENT, "basis index out of range");
+        launch_basis(all_rows(s), idx, s->stream);
+    });
+}
+
+sv_status sv_copy_state(sv_state s, void* host, int to_host)
+{
+    return guarded([&] {
+        check_state(s);
+        need(host != nullptr, SV_ERR_INVALID_ARGUMENT, "host is NULL");
+        check_not_capturing(s->stream);
+        const size_t bytes = (size_t)s->batch * s->N * sizeof(float2);
+        if (to_host)
+            SV_HIP(hipMemcpyAsync(host, s->psi, bytes, hipMemcpyDeviceToHost, s->stream));
+        else
+            SV_HIP(hipMemcpyAsync(s->psi, host, bytes, hipMemcpyHostToDevice, s->stream));
+        SV_HIP(hipStreamSynchronize(s->stream));
+    });
+}
+
+sv_status sv_check_gate(int n_qubits, const int* targets, int n_targets, const int* controls, int n_controls)
+{
+    return guarded([&] {
+        need(n_qubits >= 1 && n_qubits <= SV_MAX_QUBITS, SV_ERR_INVALID_ARGUMENT, "n_qubits must be in [1, 34]");
+        check_gate(n_qubits, targets, n_targets, controls, n_controls, SV_MAX_GATE_TARGETS);
+    });
+}
+
+sv_status sv_apply_gate(sv_state s, const int* targets, int n_targets, const int* controls, int n_controls,
+                        const double* matrix, int64_t matrix_batch_stride, unsigned flags)
+{
+    return guarded([&] {
+        check_state(s);
+        check_gate(s->n, targets, n_targets, controls, n_controls, SV_MAX_GATE_TARGETS);
+        need(matrix != nullptr, SV_ERR_INVALID_ARGUMENT, "matrix is NULL");
+        need((flags & ~(SV_FLAG_ADJOINT | SV_FLAG_CHECK_UNITARY)) == 0, SV_ERR_INVALID_ARGUMENT, "unknown flags");
+        need(matrix_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative matrix stride");
+        const int k = n_targets, D = 1 << k;
+        const bool per_row = matrix_batch_stride != 0 && s->batch > 1;
+        const int nm = per_row ? s->batch : 1;
+        std::vector<cd> ms((size_t)nm * D * D);
+        for (int r = 0; r < nm; ++r) {
+            const double* src = matrix + 2 * r * matrix_batch_stride;
+            cd* m = &ms[(size_t)r * D * D];
+            for (int i = 0; i < D * D; ++i) m[i] = cd(src[2 * i], src[2 * i + 1]);
+            if (flags & SV_FLAG_CHECK_UNITARY) check_unitary(k, m);
+            if (flags & SV_FLAG_ADJOINT) {
+                cd t[16];
+                dagger(k, m, t);
+                std::copy(t, t + D * D, m);
+            }
+        }
+        if (!per_row) {
+            dispatch(all_rows(s), k, targets, n_controls, controls, ms.data(), s->stream);
+        } else {
+            for (int r = 0; r < s->batch; ++r)
+                dispatch(one_row(s, s->psi, r), k, targets, n_controls, controls, &ms[(size_t)r * D * D], s->stream);
+        }
+    });
+}
+
+sv_status sv_run(sv_state s, const sv_op* ops, int n_ops, const double* params, int64_t params_batch_stride,
+                 int n_params)
+{
+    return guarded([&] {
+        check_state(s);
+        need(n_ops >= 0 && (n_ops == 0 || ops != nullptr), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
+        need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
+        need(params_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative params stride");
+        std::vector<OpInfo> info(n_ops);
+        for (int i = 0; i < n_ops; ++i) info[i] = check_op(s->n, ops[i], n_params);
+        const bool per_row = params_batch_stride != 0 && s->batch > 1;
+        for (int i = 0; i < n_ops; ++i) {
+            const sv_op& op = ops[i];
+            cd m[16];
+            if (!per_row || info[i].np == 0) {
+                op_matrix(op, info[i], params, m);
+                dispatch(all_rows(s), info[i].k, op.targets, op.n_controls, op.controls, m, s->stream);
+            } else {
+                for (int r = 0; r < s->batch; ++r) {
+                    op_matrix(op, info[i], params + r * params_batch_stride, m);
+                    dispatch(one_row(s, s->psi, r), info[i].k, op.targets, op.n_controls, op.controls, m, s->stream);
+                }
+            }
+        }
+    });
+}
+
+sv_status sv_expval_z_all(sv_state s, double* out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
+        check_not_capturing(s->stream);
+        ensure_scratch(s, zall_parts(s->n, s->batch));
+        const uint64_t nout = (uint64_t)s->batch * (s->n + 1);
+        ensure_dout(s, nout);
+        launch_zall(all_rows(s), s->n, s->scratch, s->dout, s->stream);
+        fetch(s, nout);
+        std::memcpy(out, s->hout, nout * sizeof(double));
+    });
+}
+
+sv_status sv_expval_pauli(sv_state s, const sv_pauli_term* terms, int n_terms, double* out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
+        check_terms(s->n, terms, n_terms);
+        check_not_capturing(s->stream);
+        // group terms by x mask, at most 8 per sweep
+        std::vector<PauliGroup> groups;
+        std::vector<std::vector<int>> members;
+        std::map<uint64_t, std::vector<int>> byx;
+        for (int t = 0; t < n_terms; ++t) byx[terms[t].x_mask].push_back(t);
+        for (auto& kv : byx) {
+            for (size_t i = 0; i < kv.second.size(); i += 8) {
+                PauliGroup g{};
+                g.x_mask = kv.first;
+                std::vector<int> mem;
+                for (size_t j = i; j < std::min(kv.second.size(), i + 8); ++j) {
+                    const int t = kv.second[j];
+                    g.z_mask[g.nt] = terms[t].z_mask;
+                    g.y_count[g.nt] = __builtin_popcountll(terms[t].x_mask & terms[t].z_mask);
+                    ++g.nt;
+                    mem.push_back(t);
+                }
+                groups.push_back(g);
+                members.push_back(mem);
+            }
+        }
+        ensure_scratch(s, pauli_parts(s->n, s->batch, 8));
+        ensure_dout(s, (uint64_t)s->batch * n_terms);
+        uint64_t off = 0;
+        std::vector<uint64_t> offs;
+        for (auto& g : groups) {
+            offs.push_back(off);
+            launch_pauli_group(all_rows(s), s->n, g, s->scratch, s->dout + off, s->stream);
+            off += (uint64_t)s->batch * g.nt;
+        }
+        fetch(s, off);
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            for (int r = 0; r < s->batch; ++r)
+                for (int j = 0; j < groups[gi].nt; ++j) {
+                    const int t = members[gi][j];
+                    out[(size_t)r * n_terms + t] = terms[t].coeff * s->hout[offs[gi] + (uint64_t)r * groups[gi].nt + j];
+                }
+    });
+}
+
+sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                          int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                          void* lambda_buffer, double* grad_out, double* loss_out, double* drift_out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(n_ops >= 0 && (n_ops == 0 || ops != nullptr), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
+        need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
+        need(n_params == 0 || grad_out != nullptr, SV_ERR_INVALID_ARGUMENT, "grad_out is NULL");
+        need(params_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative params stride");
+        check_terms(s->n, obs, n_obs);
+        std::vector<OpInfo> info(n_ops);
+        for (int i = 0; i < n_ops; ++i) info[i] = check_op(s->n, ops[i], n_params);
+        check_not_capturing(s->stream);
+
+        const int B = s->batch;
+        const bool per_row = params_batch_stride != 0 && B > 1;
+        float2* lam = nullptr;
+        ensure_lambda(s, lambda_buffer, &lam);
+        PauliTermDev* dterms = nullptr;
+        upload_terms(s, obs, n_obs, &dterms);
+
+        // slots: one per (parameterised op, row, derivative)
+        struct Slot { int row; int param; };
+        std::vector<Slot> slots;
+        for (int i = 0; i < n_ops; ++i) slots.reserve(slots.size() + (size_t)B * info[i].np);
+        const int G = adj_grid(s->n, 1, 0);
+        uint64_t nslot_max = 0;
+        for (int i = 0; i < n_ops; ++i) nslot_max += (uint64_t)B * info[i].np;
+        const uint64_t red = std::max<uint64_t>(inner_parts(s->n, B), drift_parts(s->n, B));
+        ensure_scratch(s, std::max<uint64_t>(nslot_max * G, 1) + red);
+        double* part = s->scratch;
+        double* rscratch = s->scratch + std::max<uint64_t>(nslot_max * G, 1);
+        const uint64_t nout = std::max<uint64_t>(nslot_max, 1) + 3ull * B;
+        ensure_dout(s, nout + 2ull * B);
+        double* d_slots = s->dout;
+        double* d_loss = s->dout + std::max<uint64_t>(nslot_max, 1);       // [B][2] re, im
+        double* d_drift = d_loss + 2ull * B;                                // [B]
+
+        const Rows prow{s->psi, s->psi, B, B, s->N};
+        const Rows lrow{lam, lam, B, B, s->N};
+        launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, s->stream);
+        launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
+
+        const Rows both{s->psi, lam, B, 2 * B, s->N};
+        uint64_t cur = 0;
+        for (int i = n_ops - 1; i >= 0; --i) {
+            const sv_op& op = ops[i];
+            const OpInfo& oi = info[i];
+            const int D = 1 << oi.k;
+            if (oi.np == 0) {
+                cd m[16], md[16];
+                op_matrix(op, oi, params, m);
+                dagger(oi.k, m, md);
+                dispatch(both, oi.k, op.targets, op.n_controls, op.controls, md, s->stream);
+                continue;
+            }
+            const int nrl = per_row ? B : 1;
+            for (int rl = 0; rl < nrl; ++rl) {
+                const double* pr = params + (per_row ? rl * params_batch_stride : 0);
+                double prm[3];
+                op_params(op, oi, pr, prm);
+                cd m[16], md[16];
+                kind_matrix(op.kind, prm, m);
+                dagger(oi.k, m, md);
+                AdjLaunch a{};
+                if (per_row) {
+                    a.psi = one_row(s, s->psi, rl);
+                    a.lam = one_row(s, lam, rl);
+                } else {
+                    a.psi = prow;
+                    a.lam = lrow;
+                }
+                a.k = oi.k;
+                for (int j = 0; j < oi.k; ++j) a.targets[j] = op.targets[j];
+                a.nc = op.n_controls;
+                for (int j = 0; j < op.n_controls; ++j) a.controls[j] = op.controls[j];
+                for (int q = 0; q < D * D; ++q) a.uinv[q] = f2(md[q]);
+                a.nd = oi.np;
+                for (int d = 0; d < oi.np; ++d) {
+                    cd dm[16];
+                    kind_dmatrix(op.kind, prm, d, dm);
+                    for (int r = 0; r < D; ++r)
+                        for (int c = 0; c < D; ++c) {
+                            cd acc = 0.0;
+                            for (int j = 0; j < D; ++j) acc += dm[r * D + j] * md[j * D + c];
+                            a.g[d][r * D + c] = make_double2(acc.real(), acc.imag());
+                        }
+                }
+                launch_adj_step(a, part + cur * G, s->stream);
+                const int rows_here = per_row ? 1 : B;
+                for (int r = 0; r < rows_here; ++r)
+                    for (int d = 0; d < oi.np; ++d) slots.push_back(Slot{per_row ? rl : r, op.param[d]});
+                cur += (uint64_t)rows_here * oi.np;
+            }
+        }
+        if (cur > 0) launch_sum_slots(part, G, (int)cur, d_slots, s->stream);
+        launch_drift(prow, s->n, rscratch, d_drift, s->stream);
+        SV_HIP(hipMemcpyAsync(s->hout, s->dout, (std::max<uint64_t>(nslot_max, 1) + 3ull * B) * sizeof(double),
+                              hipMemcpyDeviceToHost, s->stream));
+        SV_HIP(hipStreamSynchronize(s->stream));
+        const double* h_slots = s->hout;
+        const double* h_loss = s->hout + std::max<uint64_t>(nslot_max, 1);
+        const double* h_drift = h_loss + 2ull * B;
+        if (n_params > 0) std::fill(grad_out, grad_out + (size_t)B * n_params, 0.0);
+        // slots were pushed in reverse gate order; accumulate in that fixed order
+        for (uint64_t q = 0; q < cur; ++q) grad_out[(size_t)slots[q].row * n_params + slots[q].param] += 2.0 * h_slots[q];
+        for (int r = 0; r < B; ++r) {
+            if (loss_out) loss_out[r] = h_loss[2 * r];
+            if (drift_out) drift_out[r] = std::sqrt(std::max(0.0, h_drift[r]));
+        }
+    });
+}
+
+sv_status sv_stream_copy(void* dst, const void* src, uint64_t bytes, void* stream)
+{
+    return guarded([&] {
+        need(dst && src, SV_ERR_INVALID_ARGUMENT, "null pointer");
+        need(bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0 &&
+                 (reinterpret_cast<uintptr_t>(src) & 15) == 0,
+             SV_ERR_INVALID_ARGUMENT, "copy needs 16-byte aligned pointers and size");
+        if (bytes) launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    });
+}
+
+const char* sv_status_string(sv_status st)
+{
+    switch (st) {
+    case SV_OK: return "ok";
+    case SV_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case SV_ERR_QUBIT_OUT_OF_RANGE: return "qubit out of range";
+    case SV_ERR_QUBIT_OVERLAP: return "qubit used twice";
+    case SV_ERR_UNSUPPORTED: return "unsupported";
+    case SV_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SV_ERR_HIP: return "HIP runtime error";
+    case SV_ERR_CAPTURE: return "stream is capturing";
+    case SV_ERR_NOT_UNITARY: return "matrix not unitary";
+    }
+    return "unknown status";
+}
+
+const char* sv_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

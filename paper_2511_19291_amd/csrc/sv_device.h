@@ -1,0 +1,64 @@
+// sv_device.h -- device helpers shared by the kernels of libsv.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sv {
+
+constexpr int kBlock = 256;   // threads per workgroup of the sweep kernels (4 wave64)
+
+// Insert a 0 bit at each position of pos[0..np) (ascending) into g: maps a
+// compact index over the free bits to an amplitude index whose bits at pos
+// are 0.
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const int* pos, int np)
+{
+    for (int i = 0; i < np; ++i) {
+        const uint64_t lo = g & ((1ull << pos[i]) - 1ull);
+        g = ((g >> pos[i]) << (pos[i] + 1)) | lo;
+    }
+    return g;
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// c + a * b
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c)
+{
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+
+__device__ __forceinline__ float2 lo2(float4 v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ float4 pack4(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+
+// Sum NV doubles over a 256-thread block; the result is valid in thread 0.
+// The order of additions is fixed, so the result is bitwise reproducible.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV])
+{
+    __shared__ double sh[kBlock / 64][NV];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[w][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = sh[0][i];
+#pragma unroll
+            for (int j = 1; j < kBlock / 64; ++j) s += sh[j][i];
+            v[i] = s;
+        }
+}
+
+}  // namespace sv

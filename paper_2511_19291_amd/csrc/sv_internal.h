@@ -1,0 +1,151 @@
+// sv_internal.h -- host-side structures and launcher declarations shared by
+// the translation units of libsv.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+
+namespace sv {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------ errors
+
+struct Error {
+    sv_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(sv_status st, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define SV_HIP(call) ::sv::hip_check((call), #call)
+
+// ------------------------------------------------------------ device info
+
+struct DeviceInfo {
+    int cu_count = 256;
+    int device = 0;
+};
+const DeviceInfo& device_info();
+
+// ------------------------------------------------------------ gate math (host, complex128)
+
+// Matrix of a named kind at the given parameters; returns k. Row-major,
+// first target = most significant bit of the index.
+int kind_matrix(int kind, const double* prm, cd* m);
+// d M / d prm[j]; returns k or -1 if the kind has no parameter j.
+int kind_dmatrix(int kind, const double* prm, int j, cd* m);
+int kind_targets(int kind);
+int kind_nparams(int kind);
+
+// ------------------------------------------------------------ kernel launch arguments
+
+// Row addressing: rows [0, nrow0) start at p0 + r * N, rows [nrow0, nrows)
+// at p1 + (r - nrow0) * N. Lets one launch sweep psi and lambda together.
+struct Rows {
+    float2* p0;
+    float2* p1;
+    int nrow0;
+    int nrows;
+    uint64_t N;
+};
+
+struct GateLaunch {
+    Rows rows;
+    int k;                    // 1 or 2 targets
+    int targets[2];
+    int nc;
+    int controls[SV_MAX_CONTROLS];
+    float2 m[16];             // complex64 matrix (k=1 uses 4)
+};
+
+struct DiagLaunch {
+    Rows rows;
+    int nfixed;               // qubits fixed to 1 (controls, and targets in "ones" mode)
+    int fixed[SV_MAX_CONTROLS + 2];
+    int nfree;                // targets whose bit selects the phase
+    int freeq[2];
+    float2 ph[4];             // phase per free-target bit pattern (free[0] = MSB)
+};
+
+// Plain gate kernels (k_gates.hip). All asynchronous on `st`.
+void launch_gate(const GateLaunch& g, hipStream_t st);
+void launch_diag(const DiagLaunch& d, hipStream_t st);
+void launch_basis(const Rows& r, uint64_t idx, hipStream_t st);
+void launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
+
+// Reductions (k_reduce.hip). Partial buffers are device memory owned by the
+// caller; sizes from the *_parts functions.
+uint64_t zall_parts(int n, int rows);                 // doubles of scratch
+void launch_zall(const Rows& r, int n, double* scratch, double* out /*[rows][n+1]*/, hipStream_t st);
+
+struct PauliGroup {             // terms sharing one x mask
+    uint64_t x_mask;
+    int nt;
+    uint64_t z_mask[8];
+    int y_count[8];             // popcount(x & z) per term
+};
+uint64_t pauli_parts(int n, int rows, int nt);
+void launch_pauli_group(const Rows& r, int n, const PauliGroup& g, double* scratch,
+                        double* out /*[rows][nt]*/, hipStream_t st);
+
+// inner: out[2r] = Re sum conj(a) b, out[2r + 1] = Im (FP64).
+uint64_t inner_parts(int n, int rows);
+void launch_inner(const Rows& a, const Rows& b, int n, double* scratch, double* out, hipStream_t st);
+// out[r] = || psi_r - e_0 ||^2
+uint64_t drift_parts(int n, int rows);
+void launch_drift(const Rows& a, int n, double* scratch, double* out, hipStream_t st);
+
+// Adjoint (k_adjoint.hip).
+struct PauliTermDev {
+    uint64_t x_mask, z_mask;
+    double coeff;
+    int y_count;
+    int pad;
+};
+// lam <- O psi, O = sum of terms (device array of nt terms).
+void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
+                            hipStream_t st);
+
+struct AdjLaunch {
+    Rows psi;                 // rows of psi
+    Rows lam;                 // rows of lambda (same count)
+    int k;
+    int targets[2];
+    int nc;
+    int controls[SV_MAX_CONTROLS];
+    float2 uinv[16];          // U^* in complex64
+    int nd;                   // derivative count (<= 3)
+    double2 g[3][16];         // G_j = dU/dtheta_j U^* in complex128
+};
+int adj_grid(int n, int k, int nc);                   // blocks per row of an adjoint step
+// partial sums land in part[(row * nd + j) * grid + block]
+void launch_adj_step(const AdjLaunch& a, double* part, hipStream_t st);
+// out[s] = sum_b part[s * grid + b], s < nslots
+void launch_sum_slots(const double* part, int grid, int nslots, double* out, hipStream_t st);
+
+}  // namespace sv
+
+// sv_state handle
+struct sv_state_s {
+    int n = 0;
+    int batch = 0;
+    uint64_t N = 0;
+    float2* psi = nullptr;
+    bool owns = false;
+    hipStream_t stream = nullptr;
+    float2* lam = nullptr;          // adjoint buffer (owned)
+    double* scratch = nullptr;      // device reduction scratch
+    size_t scratch_cap = 0;         // doubles
+    double* dout = nullptr;         // device small outputs
+    size_t dout_cap = 0;            // doubles
+    double* hout = nullptr;         // pinned host mirror of dout
+    void* dterms = nullptr;         // device copy of observable terms
+    size_t dterms_cap = 0;
+};

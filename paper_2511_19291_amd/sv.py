@@ -1,0 +1,295 @@
+"""ctypes binding of libsv.so (the C ABI declared in include/sv.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI. PyTorch supplies device memory (a complex64 tensor
+of shape [batch, 2^n]) and the stream (the current torch stream), so torch
+events and synchronisation see the library's kernels.
+
+Raises ``SvError`` when the library reports a failure and ``RuntimeError``
+at import time if libsv.so is missing -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import circuits as _circ
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+KINDS = {"h": 1, "x": 2, "y": 3, "z": 4, "s": 5, "sdg": 6, "t": 7, "tdg": 8, "sx": 9,
+         "rx": 10, "ry": 11, "rz": 12, "p": 13, "u3": 14, "swap": 15, "rxx": 16, "ryy": 17,
+         "rzz": 18, "matrix": 19}
+
+FLAG_ADJOINT = 1
+FLAG_CHECK_UNITARY = 2
+FUSED_FP32_MFMA = 0
+FUSED_BF16X3 = 1
+FUSED_VALU = 2
+BATCH_OUT_STRIDE = 32
+MAX_CONTROLS = 3
+
+
+class SvOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_targets", C.c_int32), ("targets", C.c_int32 * 2),
+                ("n_controls", C.c_int32), ("controls", C.c_int32 * MAX_CONTROLS),
+                ("param", C.c_int32 * 3), ("matrix", C.POINTER(C.c_double))]
+
+
+class SvBlock(C.Structure):
+    _fields_ = [("k", C.c_int32), ("targets", C.c_int32 * 5), ("matrix", C.POINTER(C.c_double))]
+
+
+class SvPauliTerm(C.Structure):
+    _fields_ = [("x_mask", C.c_uint64), ("z_mask", C.c_uint64), ("coeff", C.c_double)]
+
+
+class SvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libsv.so not built ({LIB_PATH}); run paper_2511_19291_amd/csrc/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, dp, i64, u64 = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_int64, C.c_uint64
+    sig = {
+        "sv_alloc": [C.c_int, C.c_int, vp, vp, C.POINTER(vp)],
+        "sv_free": [vp],
+        "sv_device_ptr": [vp, C.POINTER(vp)],
+        "sv_reset": [vp, u64],
+        "sv_copy_state": [vp, vp, C.c_int],
+        "sv_apply_gate": [vp, ip, C.c_int, ip, C.c_int, dp, i64, C.c_uint],
+        "sv_run": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int],
+        "sv_apply_fused": [vp, C.POINTER(SvBlock), C.c_int, C.c_int],
+        "sv_fuse_plan": [C.c_int, C.POINTER(SvOp), C.c_int, dp, C.c_int, C.c_int, C.POINTER(SvBlock),
+                         C.c_int, dp, ip],
+        "sv_expval_pauli": [vp, C.POINTER(SvPauliTerm), C.c_int, dp],
+        "sv_expval_z_all": [vp, dp],
+        "sv_adjoint_grad": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm), C.c_int,
+                            vp, dp, dp, dp],
+        "sv_batch_plan_create": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, vp, C.POINTER(vp)],
+        "sv_batch_param_layout": [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+        "sv_batch_launch": [vp, vp, vp],
+        "sv_batch_launch_pergate": [vp, vp, vp],
+        "sv_batch_plan_free": [vp],
+        "sv_stream_copy": [vp, vp, u64, vp],
+        "sv_check_gate": [C.c_int, ip, C.c_int, ip, C.c_int],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.sv_status_string.argtypes = [C.c_int]
+    L.sv_status_string.restype = C.c_char_p
+    L.sv_last_error.argtypes = []
+    L.sv_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != 0:
+        L = lib()
+        raise SvError(status, f"{L.sv_status_string(status).decode()}: {L.sv_last_error().decode()}")
+
+
+def _iarr(vals: Sequence[int]):
+    return (C.c_int * max(1, len(vals)))(*[int(v) for v in vals])
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _cmatrix(m) -> np.ndarray:
+    """complex matrix -> interleaved float64 array (kept alive by the caller)."""
+    return np.ascontiguousarray(np.asarray(m, dtype=np.complex128)).view(np.float64)
+
+
+class OpTable:
+    """A circuit's gate list as an sv_op array (plus the buffers it points to)."""
+
+    def __init__(self, ops: Iterable, matrices: Optional[dict] = None):
+        ops = list(ops)
+        self.arr = (SvOp * max(1, len(ops)))()
+        self.n = len(ops)
+        self._keep: List[np.ndarray] = []
+        for i, op in enumerate(ops):
+            o = self.arr[i]
+            o.kind = KINDS[op.kind]
+            o.n_targets = len(op.targets)
+            for j, t in enumerate(op.targets):
+                o.targets[j] = t
+            o.n_controls = len(op.controls)
+            for j, c in enumerate(op.controls):
+                o.controls[j] = c
+            for j in range(3):
+                o.param[j] = op.params[j] if j < len(op.params) else -1
+            if op.kind == "matrix":
+                m = _cmatrix(matrices[i])
+                self._keep.append(m)
+                o.matrix = _dptr(m)
+
+    @property
+    def ptr(self):
+        return self.arr
+
+
+def pauli_terms(terms: Sequence[Tuple[float, int, int]]):
+    arr = (SvPauliTerm * max(1, len(terms)))()
+    for i, (c, x, z) in enumerate(terms):
+        arr[i].x_mask = int(x)
+        arr[i].z_mask = int(z)
+        arr[i].coeff = float(c)
+    return arr
+
+
+def _params_rows(params, batch: int) -> Tuple[np.ndarray, int, int]:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    if p.ndim == 1:
+        return p, 0, int(p.shape[0])
+    assert p.ndim == 2 and p.shape[0] == batch, "per-row params must be [batch, n_params]"
+    return p, int(p.shape[1]), int(p.shape[1])
+
+
+class State:
+    """A batch of n-qubit complex64 state vectors in GPU memory."""
+
+    def __init__(self, n: int, batch: int = 1, device=None, tensor=None):
+        import torch
+
+        self.n = n
+        self.batch = batch
+        if tensor is None:
+            tensor = torch.empty((batch, 1 << n), dtype=torch.complex64, device=device or "cuda")
+        assert tensor.dtype == torch.complex64 and tensor.is_contiguous() and tensor.numel() == batch << n
+        self.tensor = tensor
+        self.stream = torch.cuda.current_stream(tensor.device)
+        h = C.c_void_p()
+        check(lib().sv_alloc(n, batch, C.c_void_p(tensor.data_ptr()), C.c_void_p(self.stream.cuda_stream),
+                             C.byref(h)))
+        self.h = h
+
+    def free(self) -> None:
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.sv_free(h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- state
+    def reset(self, idx: int = 0) -> "State":
+        check(lib().sv_reset(self.h, idx))
+        return self
+
+    def to_numpy(self) -> np.ndarray:
+        out = np.empty((self.batch, 1 << self.n), dtype=np.complex64)
+        check(lib().sv_copy_state(self.h, out.ctypes.data_as(C.c_void_p), 1))
+        return out
+
+    def from_numpy(self, a: np.ndarray) -> "State":
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.complex64).reshape(self.batch, 1 << self.n))
+        check(lib().sv_copy_state(self.h, a.ctypes.data_as(C.c_void_p), 0))
+        return self
+
+    # -- gates
+    def apply_gate(self, matrix, targets: Sequence[int], controls: Sequence[int] = (),
+                   adjoint: bool = False, check_unitary: bool = False) -> "State":
+        m = np.asarray(matrix, dtype=np.complex128)
+        stride = 0
+        if m.ndim == 3:
+            stride = m.shape[1] * m.shape[2]
+        buf = _cmatrix(m)
+        flags = (FLAG_ADJOINT if adjoint else 0) | (FLAG_CHECK_UNITARY if check_unitary else 0)
+        check(lib().sv_apply_gate(self.h, _iarr(targets), len(targets), _iarr(controls), len(controls),
+                                  _dptr(buf), stride, flags))
+        return self
+
+    def run(self, circuit, params=None) -> "State":
+        table = OpTable(circuit.ops)
+        p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
+        check(lib().sv_run(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar))
+        return self
+
+    def apply_fused(self, blocks: Sequence[Tuple[Sequence[int], np.ndarray]], mode: int = FUSED_FP32_MFMA) -> "State":
+        arr = (SvBlock * max(1, len(blocks)))()
+        keep = []
+        for i, (targets, m) in enumerate(blocks):
+            arr[i].k = len(targets)
+            for j, t in enumerate(targets):
+                arr[i].targets[j] = t
+            buf = _cmatrix(m)
+            keep.append(buf)
+            arr[i].matrix = _dptr(buf)
+        check(lib().sv_apply_fused(self.h, arr, len(blocks), mode))
+        return self
+
+    # -- measurement
+    def expval_z_all(self) -> np.ndarray:
+        """[batch, n + 1]: <Z_i> for i < n, then ||psi||^2."""
+        out = np.zeros((self.batch, self.n + 1), dtype=np.float64)
+        check(lib().sv_expval_z_all(self.h, _dptr(out)))
+        return out
+
+    def expval(self, terms: Sequence[Tuple[float, int, int]]) -> np.ndarray:
+        """[batch, n_terms]: coeff_t <P_t>."""
+        out = np.zeros((self.batch, len(terms)), dtype=np.float64)
+        check(lib().sv_expval_pauli(self.h, pauli_terms(terms), len(terms), _dptr(out)))
+        return out
+
+    # -- gradients
+    def adjoint_grad(self, circuit, terms: Sequence[Tuple[float, int, int]], params=None,
+                     lambda_tensor=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """The state must hold the forward output of ``circuit``. Returns
+        (loss [batch], grad [batch, n_params], drift [batch]) and leaves the
+        recomputed start state in the state."""
+        table = OpTable(circuit.ops)
+        p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
+        grad = np.zeros((self.batch, max(npar, 1)), dtype=np.float64)
+        loss = np.zeros(self.batch, dtype=np.float64)
+        drift = np.zeros(self.batch, dtype=np.float64)
+        lam = C.c_void_p(lambda_tensor.data_ptr()) if lambda_tensor is not None else None
+        check(lib().sv_adjoint_grad(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar,
+                                    pauli_terms(terms), len(terms), lam, _dptr(grad), _dptr(loss), _dptr(drift)))
+        return loss, grad[:, :npar], drift
+
+
+def fuse_plan(circuit, max_k: int = 5, params=None) -> List[Tuple[Tuple[int, ...], np.ndarray]]:
+    """Host-only fusion planner: blocks (targets, complex128 matrix)."""
+    table = OpTable(circuit.ops)
+    p = np.ascontiguousarray(np.asarray(circuit.params if params is None else params, dtype=np.float64))
+    max_blocks = max(1, len(circuit.ops))
+    blocks = (SvBlock * max_blocks)()
+    mats = np.zeros(max_blocks * (4 ** max_k) * 2, dtype=np.float64)
+    nb = C.c_int()
+    check(lib().sv_fuse_plan(circuit.n, table.ptr, table.n, _dptr(p) if len(p) else None, len(p), max_k,
+                             blocks, max_blocks, _dptr(mats), C.byref(nb)))
+    base = mats.ctypes.data
+    out = []
+    for i in range(nb.value):
+        b = blocks[i]
+        d = 1 << b.k
+        off = (C.cast(b.matrix, C.c_void_p).value - base) // 8
+        m = mats[off: off + 2 * d * d].view(np.complex128).reshape(d, d).copy()
+        out.append((tuple(b.targets[j] for j in range(b.k)), m))
+    return out

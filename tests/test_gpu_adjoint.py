@@ -1,0 +1,91 @@
+"""GPU adjoint gradients (un-applying gates, FP64 inner products) against the
+oracle's exact gradients.
+
+Tolerance: relative error ||g - g_ref||_2 / ||g_ref||_2 <= 1e-4 and per
+component |dg_p| <= 1e-4 ||g_ref||_inf (the stated gradient tolerance)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_19291_amd import circuits as C
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+
+
+def _close(g, ref):
+    scale = max(np.linalg.norm(ref), 1e-12)
+    assert np.linalg.norm(g - ref) / scale <= REL, np.linalg.norm(g - ref) / scale
+    assert np.max(np.abs(g - ref)) <= REL * max(np.max(np.abs(ref)), 1e-12)
+
+
+def test_ring14_vs_parameter_shift(sv):
+    """14-qubit copy of the differentiation workload: 10 x [RX, RY, CNOT
+    ring], loss <sum Z_i>; adjoint vs the oracle's parameter shift."""
+    circ = C.WORKLOADS["ring14"]()
+    terms = C.z_sum_terms(14)
+    st = sv.State(14).reset().run(circ)
+    loss, g, drift = st.adjoint_grad(circ, terms)
+    ref = oracle.grad_param_shift(circ, terms)
+    _close(g[0], ref)
+    assert abs(loss[0] - oracle.loss(circ, terms)) < 1e-4
+    assert drift[0] < 1e-4
+    # the state now holds the recomputed |0..0>
+    out = st.to_numpy()[0]
+    assert abs(out[0] - 1) < 1e-4
+
+
+@pytest.mark.parametrize("small", [False, True])
+def test_ring_vs_finite_difference(sv, small):
+    circ = C.rxry_ring(8, 4, 5, small_angle=small)
+    terms = C.z_sum_terms(8)
+    st = sv.State(8).reset().run(circ)
+    _, g, _ = st.adjoint_grad(circ, terms)
+    ref = oracle.grad_finite_diff(circ, terms, h=1e-4)
+    # central differences carry O(h^2) truncation: 1e-7 absolute on top
+    scale = np.linalg.norm(ref)
+    assert np.linalg.norm(g[0] - ref) <= REL * scale + 1e-6
+
+
+def test_mixed_kinds_and_observables(sv):
+    """U3 (three parameters), two-qubit rotations, controlled rotations and
+    phases, and an observable with X/Y parts: adjoint vs the oracle adjoint
+    (which is pinned to parameter shift and finite differences)."""
+    rng = np.random.default_rng(31)
+    n = 9
+    b = C._Builder(n)
+    for q in range(n):
+        b.gate("h", [q])
+    for _ in range(60):
+        kind = str(rng.choice(["u3", "rx", "ry", "rz", "p", "rxx", "ryy", "rzz", "x", "swap", "h"]))
+        nt = C.N_TARGETS[kind]
+        w = [int(x) for x in rng.permutation(n)]
+        nc = int(rng.integers(0, 3))
+        b.gate(kind, w[:nt], w[nt:nt + nc], rng.uniform(0, 2 * np.pi, C.N_PARAMS[kind]))
+    circ = b.build("mixed")
+    terms = [C.pauli_term(1.0, "Z0"), C.pauli_term(-0.7, "X1 Y4"), C.pauli_term(0.3, "Y8 Z2 X3"),
+             C.pauli_term(0.25, "Z5 Z6")]
+    st = sv.State(n).reset().run(circ)
+    loss, g, drift = st.adjoint_grad(circ, terms)
+    L, ref, _ = oracle.grad_adjoint(circ, terms)
+    _close(g[0], ref)
+    assert abs(loss[0] - L) < 1e-4
+
+
+def test_batched_per_row_inputs(sv):
+    """Batch of rows with per-row encoded inputs (the paper's batch of inputs
+    x_i): gradient rows match the oracle row by row."""
+    circ = C.encoded_ansatz(7, 2, np.random.default_rng(5))
+    B = 4
+    rng = np.random.default_rng(6)
+    P = np.tile(circ.params, (B, 1))
+    P[:, list(circ.feature_idx)] = rng.uniform(-np.pi, np.pi, size=(B, 7))
+    terms = C.z_sum_terms(7)
+    st = sv.State(7, B).reset().run(circ, params=P)
+    loss, g, _ = st.adjoint_grad(circ, terms, params=P)
+    for r in range(B):
+        ref = oracle.grad_param_shift(circ, terms, params=P[r])
+        _close(g[r], ref)
+        assert abs(loss[r] - oracle.loss(circ, terms, P[r])) < 1e-4
