@@ -1,0 +1,389 @@
+// fused.cpp -- host side of the fused-block path: the fusion planner that
+// multiplies runs of gates into <= 5-qubit blocks (complex128), and
+// sv_apply_fused, which prepares each block's matrix for the MFMA or vector
+// kernel and queues one sweep per block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+void need(bool ok, sv_status st, const std::string& msg)
+{
+    if (!ok) fail(st, msg);
+}
+
+// ------------------------------------------------------------ blocks
+
+// A block: ordered qubit list (qs[0] = most significant bit of the matrix
+// index) and its 2^m x 2^m complex128 matrix, row-major.
+struct Blk {
+    std::vector<int> qs;
+    std::vector<cd> m;
+    uint64_t mask = 0;
+    int gates = 0;
+};
+
+int bitpos(const Blk& b, int q)
+{
+    const int m = (int)b.qs.size();
+    for (int i = 0; i < m; ++i)
+        if (b.qs[i] == q) return m - 1 - i;
+    return -1;
+}
+
+// B <- G B for the gate (M on targets, controls) embedded in the block's
+// qubits: applied column by column with the gather / multiply / scatter of
+// the gate definition.
+void absorb(Blk& b, const cd* M, int k, const int* targets, int nc, const int* controls)
+{
+    const int m = (int)b.qs.size(), d = 1 << m, D = 1 << k;
+    int tp[5], cp[3];
+    uint64_t tmask = 0, cmask = 0;
+    for (int j = 0; j < k; ++j) { tp[j] = bitpos(b, targets[j]); tmask |= 1ull << tp[j]; }
+    for (int j = 0; j < nc; ++j) { cp[j] = bitpos(b, controls[j]); cmask |= 1ull << cp[j]; }
+    std::vector<cd> v(D), w(D);
+    for (int col = 0; col < d; ++col) {
+        for (int base = 0; base < d; ++base) {
+            if ((base & tmask) || ((uint64_t)base & cmask) != cmask) continue;
+            for (int r = 0; r < D; ++r) {
+                int idx = base;
+                for (int j = 0; j < k; ++j)
+                    if ((r >> (k - 1 - j)) & 1) idx |= 1 << tp[j];
+                v[r] = b.m[(size_t)idx * d + col];
+            }
+            for (int r = 0; r < D; ++r) {
+                cd acc = 0.0;
+                for (int s = 0; s < D; ++s) acc += M[r * D + s] * v[s];
+                w[r] = acc;
+            }
+            for (int r = 0; r < D; ++r) {
+                int idx = base;
+                for (int j = 0; j < k; ++j)
+                    if ((r >> (k - 1 - j)) & 1) idx |= 1 << tp[j];
+                b.m[(size_t)idx * d + col] = w[r];
+            }
+        }
+    }
+    b.gates += 1;
+}
+
+// a (x) b: the qubits of a become the more significant bits
+Blk kron(const Blk& a, const Blk& b)
+{
+    Blk o;
+    o.qs = a.qs;
+    o.qs.insert(o.qs.end(), b.qs.begin(), b.qs.end());
+    o.mask = a.mask | b.mask;
+    o.gates = a.gates + b.gates;
+    const int da = 1 << a.qs.size(), db = 1 << b.qs.size(), d = da * db;
+    o.m.assign((size_t)d * d, 0.0);
+    for (int ra = 0; ra < da; ++ra)
+        for (int ca = 0; ca < da; ++ca) {
+            const cd x = a.m[(size_t)ra * da + ca];
+            if (x == cd(0.0)) continue;
+            for (int rb = 0; rb < db; ++rb)
+                for (int cb = 0; cb < db; ++cb)
+                    o.m[(size_t)(ra * db + rb) * d + (ca * db + cb)] = x * b.m[(size_t)rb * db + cb];
+        }
+    return o;
+}
+
+Blk identity_on(const std::vector<int>& qs)
+{
+    Blk b;
+    b.qs = qs;
+    for (int q : qs) b.mask |= 1ull << q;
+    const int d = 1 << qs.size();
+    b.m.assign((size_t)d * d, 0.0);
+    for (int i = 0; i < d; ++i) b.m[(size_t)i * d + i] = 1.0;
+    return b;
+}
+
+struct PlanGate {
+    int k;
+    int targets[2];
+    int nc;
+    int controls[SV_MAX_CONTROLS];
+    cd m[16];
+    uint64_t mask;
+};
+
+// Group gates into blocks of <= max_k qubits. Open blocks hold disjoint
+// qubit sets, so they commute and may be closed in any order; a gate joins
+// the open blocks it touches (merging them) when the union fits, otherwise
+// the fullest touched blocks are closed until it fits. No gate moves past
+// another gate on a shared qubit, so the block sequence equals the circuit.
+std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
+{
+    std::vector<Blk> out, open;
+    for (const PlanGate& g : gates) {
+        std::vector<int> hit;
+        for (int i = 0; i < (int)open.size(); ++i)
+            if (open[i].mask & g.mask) hit.push_back(i);
+        auto union_size = [&](const std::vector<int>& keep) {
+            uint64_t u = g.mask;
+            for (int i : keep) u |= open[i].mask;
+            return __builtin_popcountll(u);
+        };
+        std::vector<int> keep = hit;
+        // close the fullest touched blocks until the gate fits
+        while (union_size(keep) > max_k) {
+            int best = -1;
+            for (int j = 0; j < (int)keep.size(); ++j)
+                if (best < 0 || open[keep[j]].qs.size() > open[keep[best]].qs.size()) best = j;
+            keep.erase(keep.begin() + best);
+        }
+        std::vector<int> closing;
+        for (int i : hit)
+            if (std::find(keep.begin(), keep.end(), i) == keep.end()) closing.push_back(i);
+        // merge the kept blocks, extend by the gate's new qubits, absorb the gate
+        Blk b;
+        bool first = true;
+        for (int i : keep) {
+            b = first ? open[i] : kron(b, open[i]);
+            first = false;
+        }
+        std::vector<int> fresh;
+        uint64_t have = first ? 0 : b.mask;
+        for (int j = 0; j < g.k + g.nc; ++j) {
+            const int q = j < g.k ? g.targets[j] : g.controls[j - g.k];
+            if (!((have >> q) & 1)) {
+                fresh.push_back(q);
+                have |= 1ull << q;
+            }
+        }
+        if (first) b = identity_on(fresh);
+        else if (!fresh.empty()) b = kron(b, identity_on(fresh));
+        absorb(b, g.m, g.k, g.targets, g.nc, g.controls);
+        // rebuild the open list: closed blocks go out first, in creation order
+        std::vector<Blk> next;
+        for (int i = 0; i < (int)open.size(); ++i) {
+            const bool is_hit = std::find(hit.begin(), hit.end(), i) != hit.end();
+            const bool is_closing = std::find(closing.begin(), closing.end(), i) != closing.end();
+            if (is_closing) out.push_back(std::move(open[i]));
+            else if (!is_hit) next.push_back(std::move(open[i]));
+        }
+        next.push_back(std::move(b));
+        open = std::move(next);
+    }
+    for (Blk& b : open) out.push_back(std::move(b));
+    return out;
+}
+
+uint16_t bf16_rne_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    const uint32_t lsb = (u >> 16) & 1;
+    u += 0x7fff + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_round(float x)
+{
+    const uint32_t u = (uint32_t)bf16_rne_bits(x) << 16;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
+void ensure_fused(sv_state s, size_t bytes)
+{
+    if (bytes <= s->dfused_cap) return;
+    if (s->dfused) {
+        SV_HIP(hipStreamSynchronize(s->stream));
+        SV_HIP(hipFree(s->dfused));
+        s->dfused = nullptr;
+        s->dfused_cap = 0;
+    }
+    if (hipMalloc(&s->dfused, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SV_ERR_OUT_OF_MEMORY, "fused matrix buffer allocation failed");
+    }
+    s->dfused_cap = bytes;
+}
+
+}  // namespace
+
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" sv_status sv_fuse_plan(int n_qubits, const sv_op* ops, int n_ops, const double* params, int n_params,
+                                  int max_k, sv_block* out_blocks, int max_blocks, double* out_matrices,
+                                  int* n_blocks_out)
+{
+    try {
+        need(n_qubits >= 1 && n_qubits <= SV_MAX_QUBITS, SV_ERR_INVALID_ARGUMENT, "n_qubits must be in [1, 34]");
+        need(max_k >= 1 && max_k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "max_k must be 1..5");
+        need(n_ops >= 0 && (n_ops == 0 || ops), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
+        need(out_blocks && out_matrices && n_blocks_out, SV_ERR_INVALID_ARGUMENT, "output pointer is NULL");
+        std::vector<PlanGate> gates;
+        for (int i = 0; i < n_ops; ++i) {
+            const sv_op& op = ops[i];
+            PlanGate g{};
+            int k = 0;
+            need(op.n_controls >= 0 && op.n_controls <= SV_MAX_CONTROLS, SV_ERR_UNSUPPORTED, "at most 3 controls");
+            need(sv_check_gate(n_qubits, op.targets, op.n_targets, op.controls, op.n_controls) == SV_OK,
+                 SV_ERR_QUBIT_OUT_OF_RANGE, std::string("bad gate ") + std::to_string(i) + ": " + sv_last_error());
+            for (int j = 0; j < 3; ++j)
+                if (op.param[j] >= 0) need(op.param[j] < n_params && params, SV_ERR_INVALID_ARGUMENT, "param index out of range");
+            gate_matrix_of_op(op, params, g.m, &k);
+            need(k == op.n_targets, SV_ERR_INVALID_ARGUMENT, "n_targets does not match the gate kind");
+            g.k = k;
+            g.nc = op.n_controls;
+            g.mask = 0;
+            for (int j = 0; j < k; ++j) { g.targets[j] = op.targets[j]; g.mask |= 1ull << op.targets[j]; }
+            for (int j = 0; j < g.nc; ++j) { g.controls[j] = op.controls[j]; g.mask |= 1ull << op.controls[j]; }
+            need(__builtin_popcountll(g.mask) <= max_k, SV_ERR_UNSUPPORTED, "a gate has more qubits than max_k");
+            gates.push_back(g);
+        }
+        std::vector<Blk> blocks = plan(gates, max_k);
+        need((int)blocks.size() <= max_blocks, SV_ERR_INVALID_ARGUMENT, "max_blocks too small");
+        const size_t stride = (size_t)2 * (1u << max_k) * (1u << max_k);
+        for (size_t bi = 0; bi < blocks.size(); ++bi) {
+            const Blk& b = blocks[bi];
+            sv_block& o = out_blocks[bi];
+            o.k = (int)b.qs.size();
+            for (int j = 0; j < SV_MAX_FUSED_TARGETS; ++j) o.targets[j] = j < o.k ? b.qs[j] : -1;
+            double* dst = out_matrices + bi * stride;
+            for (size_t i = 0; i < b.m.size(); ++i) {
+                dst[2 * i] = b.m[i].real();
+                dst[2 * i + 1] = b.m[i].imag();
+            }
+            o.matrix = dst;
+        }
+        *n_blocks_out = (int)blocks.size();
+        return SV_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.st;
+    } catch (...) {
+        return SV_ERR_INVALID_ARGUMENT;
+    }
+}
+
+extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_blocks, int mode)
+{
+    try {
+        need(s != nullptr && s->psi != nullptr, SV_ERR_INVALID_ARGUMENT, "null state");
+        need(mode == SV_FUSED_FP32_MFMA || mode == SV_FUSED_BF16X3 || mode == SV_FUSED_VALU,
+             SV_ERR_INVALID_ARGUMENT, "unknown fused mode");
+        need(n_blocks >= 0 && (n_blocks == 0 || blocks), SV_ERR_INVALID_ARGUMENT, "blocks is NULL");
+        const bool mfma = mode != SV_FUSED_VALU;
+        for (int i = 0; i < n_blocks; ++i) {
+            const sv_block& b = blocks[i];
+            need(b.k >= 1 && b.k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "block k must be 1..5");
+            need(b.matrix != nullptr, SV_ERR_INVALID_ARGUMENT, "block matrix is NULL");
+            uint64_t seen = 0;
+            for (int j = 0; j < b.k; ++j) {
+                need(b.targets[j] >= 0 && b.targets[j] < s->n, SV_ERR_QUBIT_OUT_OF_RANGE, "block target out of range");
+                need(!((seen >> b.targets[j]) & 1), SV_ERR_QUBIT_OVERLAP, "block target used twice");
+                seen |= 1ull << b.targets[j];
+            }
+            if (mfma) need(s->n >= 10, SV_ERR_INVALID_ARGUMENT, "the MFMA fused modes need n >= 10");
+        }
+        if (n_blocks == 0) return SV_OK;
+        // per-block device payload
+        const size_t per = mfma ? (size_t)2 * 64 * 64 * sizeof(float)
+                                : (size_t)32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t) + 8 * sizeof(int);
+        std::vector<unsigned char> host((size_t)n_blocks * per, 0);
+        std::vector<std::array<int, 5>> tgt(n_blocks);
+        for (int i = 0; i < n_blocks; ++i) {
+            const sv_block& b = blocks[i];
+            const int k = b.k, D = 1 << k;
+            unsigned char* dst = host.data() + (size_t)i * per;
+            if (mfma) {
+                // pad to five targets with identity qubits (lowest free qubits,
+                // appended as the least significant bits of the matrix index)
+                int t5[5], kk = k;
+                uint64_t used = 0;
+                for (int j = 0; j < k; ++j) { t5[j] = b.targets[j]; used |= 1ull << b.targets[j]; }
+                for (int q = 0; q < s->n && kk < 5; ++q)
+                    if (!((used >> q) & 1)) { t5[kk++] = q; used |= 1ull << q; }
+                const int pad = 5 - k;
+                for (int j = 0; j < 5; ++j) tgt[i][j] = t5[j];
+                float* A = reinterpret_cast<float*>(dst);
+                for (int r = 0; r < 32; ++r)
+                    for (int c = 0; c < 32; ++c) {
+                        // M5 = M (x) I_{2^pad}
+                        cd v = 0.0;
+                        if ((r & ((1 << pad) - 1)) == (c & ((1 << pad) - 1))) {
+                            const double* e = b.matrix + 2 * ((size_t)(r >> pad) * D + (c >> pad));
+                            v = cd(e[0], e[1]);
+                        }
+                        const float re = (float)v.real(), im = (float)v.imag();
+                        A[r * 64 + c] = re;
+                        A[r * 64 + 32 + c] = -im;
+                        A[(32 + r) * 64 + c] = im;
+                        A[(32 + r) * 64 + 32 + c] = re;
+                    }
+                if (mode == SV_FUSED_BF16X3) {
+                    float* L = A + 64 * 64;
+                    for (int q = 0; q < 64 * 64; ++q) {
+                        const float hi = bf16_round(A[q]);
+                        L[q] = A[q] - hi;
+                        A[q] = hi;
+                    }
+                }
+            } else {
+                float2* m = reinterpret_cast<float2*>(dst);
+                for (int q = 0; q < D * D; ++q)
+                    m[q] = make_float2((float)b.matrix[2 * q], (float)b.matrix[2 * q + 1]);
+                uint64_t* moff = reinterpret_cast<uint64_t*>(dst + 32 * 32 * sizeof(float2));
+                for (int r = 0; r < D; ++r) {
+                    uint64_t off = 0;
+                    for (int j = 0; j < k; ++j)
+                        if ((r >> (k - 1 - j)) & 1) off |= 1ull << b.targets[j];
+                    moff[r] = off;
+                }
+                int* pos = reinterpret_cast<int*>(dst + 32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t));
+                for (int j = 0; j < k; ++j) pos[j] = b.targets[j];
+                std::sort(pos, pos + k);
+            }
+        }
+        ensure_fused(s, host.size());
+        // pageable source: the copy has consumed `host` when the call returns
+        SV_HIP(hipMemcpyAsync(s->dfused, host.data(), host.size(), hipMemcpyHostToDevice, s->stream));
+        unsigned char* dev = static_cast<unsigned char*>(s->dfused);
+        for (int i = 0; i < n_blocks; ++i) {
+            unsigned char* p = dev + (size_t)i * per;
+            if (mfma) {
+                FusedLaunch f{};
+                f.psi = s->psi;
+                f.N = s->N;
+                f.nrows = s->batch;
+                for (int j = 0; j < 5; ++j) f.targets[j] = tgt[i][j];
+                f.mode = mode;
+                f.amat = reinterpret_cast<const float*>(p);
+                launch_fused_mfma(f, s->stream);
+            } else {
+                FusedValuLaunch f{};
+                f.psi = s->psi;
+                f.N = s->N;
+                f.nrows = s->batch;
+                f.k = blocks[i].k;
+                f.m = reinterpret_cast<const float2*>(p);
+                f.moff = reinterpret_cast<const uint64_t*>(p + 32 * 32 * sizeof(float2));
+                f.pos = reinterpret_cast<const int*>(p + 32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t));
+                launch_fused_valu(f, s->stream);
+            }
+        }
+        return SV_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.st;
+    } catch (...) {
+        return SV_ERR_INVALID_ARGUMENT;
+    }
+}

@@ -1,0 +1,294 @@
+// k_fused.hip -- one fused k-qubit gate block per sweep on the matrix cores.
+//
+// A block is (M, T): a 32 x 32 complex matrix on five ordered target qubits
+// (Alg. 1 of Sec. 4.1.1 with |Q| = 5; smaller blocks are padded with identity
+// qubits on the host). Viewing the state as X[r][j] with r the five target
+// bits (T[0] most significant) and j every other bit, the block computes
+// Y = M X over all 2^(n-5) columns -- a dense contraction.
+//
+// Tiling: a tile is 32 rows x 32 columns = 1024 amplitudes, the columns being
+// the five lowest non-target qubits. The tile's ten bit positions therefore
+// include every bit below the fifth-lowest non-target, so its memory image is
+// made of contiguous runs of at least 32 amplitudes (256 bytes). Each wave
+// owns one tile at a time:
+//   1. coalesced float4 loads in memory order -> LDS, split into real and
+//      imaginary planes;
+//   2. complex product on MFMA as a real 64 x 64 product
+//      [Yr; Yi] = [[Mr, -Mi], [Mi, Mr]] [Xr; Xi]:
+//      FP32: v_mfma_f32_32x32x2_f32, 2 x 32 k-steps;
+//      BF16X3: x = x_hi + x_lo with both parts rounded to BF16 (RNE), products
+//      hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16, FP32 accumulation;
+//      the left operand (the block matrix) stays in registers for the whole
+//      sweep;
+//   3. results -> LDS -> coalesced float4 stores in memory order.
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 4;
+constexpr int kXs = 33;              // FP32 layout Xs[64][33]: [k][col]
+constexpr int kXt = 68;              // BF16 layout Xt[32][68]: [col][k]
+constexpr int kWaveLds = 64 * kXs > 32 * kXt ? 64 * kXs : 32 * kXt;   // floats per wave
+
+struct KFused {
+    float2* psi;
+    uint64_t N;
+    uint64_t n_tiles;          // per row
+    int pos[10];               // tile bit positions, ascending
+    uint64_t bit_off64[10];    // amplitude offset of tile bit b (= 1 << pos[b])
+    int bit_row[10];           // row-index contribution of tile bit b (0 if a column bit)
+    int bit_col[10];           // column-index contribution of tile bit b (0 if a row bit)
+    const float* amat;         // FP32: A~[64][64]; BF16X3: hi A~[64][64] then lo A~[64][64] (as float)
+};
+
+__device__ __forceinline__ bf16x8 to_bf16(const float (&x)[8])
+{
+    bf16x8 r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = (__bf16)x[q];
+    return r;
+}
+
+// MODE 0: FP32 MFMA; MODE 1: BF16 x3.
+template <int MODE>
+__global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
+{
+    __shared__ float lds[kWaves * kWaveLds];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    float* xs = lds + wave * kWaveLds;
+    float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+    const int h = lane >> 5, c32 = lane & 31;
+
+    // per-lane part of the tile index L = 2*lane + 128*i (+ e): bits 1..6
+    uint64_t lane_off = 0;
+    int lane_r = 0, lane_c = 0;
+#pragma unroll
+    for (int b = 1; b <= 6; ++b)
+        if ((lane >> (b - 1)) & 1) {
+            lane_off += a.bit_off64[b];
+            lane_r += a.bit_row[b];
+            lane_c += a.bit_col[b];
+        }
+    uint64_t i_off[8];
+    int i_r[8], i_c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        i_off[i] = 0;
+        i_r[i] = 0;
+        i_c[i] = 0;
+#pragma unroll
+        for (int b = 7; b <= 9; ++b)
+            if ((i >> (b - 7)) & 1) {
+                i_off[i] += a.bit_off64[b];
+                i_r[i] += a.bit_row[b];
+                i_c[i] += a.bit_col[b];
+            }
+    }
+    const int r0 = a.bit_row[0], c0 = a.bit_col[0];   // bit 0 of L (the second amplitude of a float4)
+
+    // left operand fragments, loaded once
+    float afr[2][32];
+    bf16x8 ahi[2][4], alo[2][4];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 32; ++s) afr[b][s] = a.amat[(32 * b + c32) * 64 + 2 * s + h];
+    } else {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float th[8], tl[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    th[q] = a.amat[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    tl[q] = a.amat[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                }
+                ahi[b][s] = to_bf16(th);
+                alo[b][s] = to_bf16(tl);
+            }
+    }
+
+    const uint64_t waves_total = (uint64_t)gridDim.x * kWaves;
+    const uint64_t iters = (a.n_tiles + waves_total - 1) / waves_total;
+    for (uint64_t it = 0; it < iters; ++it) {
+        const uint64_t tile = it * waves_total + (uint64_t)blockIdx.x * kWaves + wave;
+        const bool live = tile < a.n_tiles;
+        const uint64_t base = insert_zeros(live ? tile : 0, a.pos, 10);
+        // 1. load the tile in memory order, scatter into LDS planes
+        float4 v[8];
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = ld4(psi + base + lane_off + i_off[i]);
+        }
+        __syncthreads();   // previous tile's results have been read from LDS
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = lane_r + i_r[i], c = lane_c + i_c[i];
+                if constexpr (MODE == 0) {
+                    xs[r * kXs + c] = v[i].x;
+                    xs[(32 + r) * kXs + c] = v[i].y;
+                    xs[(r + r0) * kXs + c + c0] = v[i].z;
+                    xs[(32 + r + r0) * kXs + c + c0] = v[i].w;
+                } else {
+                    xs[c * kXt + r] = v[i].x;
+                    xs[c * kXt + 32 + r] = v[i].y;
+                    xs[(c + c0) * kXt + r + r0] = v[i].z;
+                    xs[(c + c0) * kXt + 32 + r + r0] = v[i].w;
+                }
+            }
+        }
+        __syncthreads();
+        // 2. products on the matrix cores
+        f32x16 acc0 = {0}, acc1 = {0};
+        if (live) {
+            if constexpr (MODE == 0) {
+#pragma unroll
+                for (int s = 0; s < 32; ++s) {
+                    const float bv = xs[(2 * s + h) * kXs + c32];
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][s], bv, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][s], bv, acc1, 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float4 p0 = *reinterpret_cast<const float4*>(xs + c32 * kXt + 16 * s + 8 * h);
+                    const float4 p1 = *reinterpret_cast<const float4*>(xs + c32 * kXt + 16 * s + 8 * h + 4);
+                    float xh[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w}, xl[8];
+                    const bf16x8 bh = to_bf16(xh);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) xl[q] = xh[q] - (float)bh[q];
+                    const bf16x8 bl = to_bf16(xl);
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        f32x16& acc = b == 0 ? acc0 : acc1;
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[b][s], bh, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[b][s], bl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[b][s], bh, acc, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // every lane has read its B operands
+        // 3. results to LDS as Ys[64][33] (rows 0..31 real, 32..63 imaginary)
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int row = 8 * (q >> 2) + 4 * h + (q & 3);
+                xs[row * kXs + c32] = acc0[q];
+                xs[(32 + row) * kXs + c32] = acc1[q];
+            }
+        }
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = lane_r + i_r[i], c = lane_c + i_c[i];
+                float4 o;
+                o.x = xs[r * kXs + c];
+                o.y = xs[(32 + r) * kXs + c];
+                o.z = xs[(r + r0) * kXs + c + c0];
+                o.w = xs[(32 + r + r0) * kXs + c + c0];
+                st4(psi + base + lane_off + i_off[i], o);
+            }
+        }
+    }
+}
+
+// Plain FP32 vector form: one thread per column, the block matrix in LDS.
+template <int K>
+__global__ __launch_bounds__(256) void k_fused_valu(float2* psi, uint64_t N, uint64_t n_cols, int npos,
+                                                    const int* __restrict__ pos_dev, const uint64_t* __restrict__ moff_dev,
+                                                    const float2* __restrict__ m)
+{
+    constexpr int D = 1 << K;
+    __shared__ float2 ms[D * D];
+    __shared__ int pos[8];
+    __shared__ uint64_t moff[D];
+    for (int i = threadIdx.x; i < D * D; i += 256) ms[i] = m[i];
+    if (threadIdx.x < npos) pos[threadIdx.x] = pos_dev[threadIdx.x];
+    if (threadIdx.x < D) moff[threadIdx.x] = moff_dev[threadIdx.x];
+    __syncthreads();
+    float2* row = psi + (uint64_t)blockIdx.y * N;
+    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < n_cols; c += (uint64_t)gridDim.x * 256) {
+        const uint64_t base = insert_zeros(c, pos, npos);
+        float2 x[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = ld2(row + (base | moff[j]));
+#pragma unroll 4
+        for (int i = 0; i < D; ++i) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < D; ++j) acc = cfma(ms[i * D + j], x[j], acc);
+            st2(row + (base | moff[i]), acc);
+        }
+    }
+}
+
+}  // namespace
+
+void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
+{
+    KFused a{};
+    a.psi = f.psi;
+    a.N = f.N;
+    const int n = __builtin_ctzll(f.N);
+    a.n_tiles = 1ull << (n - 10);
+    // tile bits: the 5 targets and the 5 lowest non-target qubits
+    int cols[5], nc = 0;
+    uint64_t tmask = 0;
+    for (int j = 0; j < 5; ++j) tmask |= 1ull << f.targets[j];
+    for (int q = 0; q < n && nc < 5; ++q)
+        if (!((tmask >> q) & 1)) cols[nc++] = q;
+    int np = 0;
+    for (int q = 0; q < n; ++q)
+        if (((tmask >> q) & 1) || (nc > 0 && q <= cols[4] && !((tmask >> q) & 1))) a.pos[np++] = q;
+    // a.pos now lists every tile bit ascending (targets anywhere, columns = lowest non-targets)
+    for (int b = 0; b < 10; ++b) {
+        const int q = a.pos[b];
+        a.bit_off64[b] = 1ull << q;
+        a.bit_row[b] = 0;
+        a.bit_col[b] = 0;
+        for (int j = 0; j < 5; ++j)
+            if (f.targets[j] == q) a.bit_row[b] = 1 << (4 - j);
+        for (int c = 0; c < 5; ++c)
+            if (cols[c] == q) a.bit_col[b] = 1 << c;
+    }
+    a.amat = f.amat;
+    // persistent grid: two workgroups per CU are resident (registers, LDS)
+    const uint64_t want = (a.n_tiles + kWaves - 1) / kWaves;
+    const uint64_t cap = (uint64_t)device_info().cu_count * 2;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+    if (f.mode == SV_FUSED_FP32_MFMA)
+        hipLaunchKernelGGL(k_fused<0>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fused<1>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);
+    SV_HIP(hipGetLastError());
+}
+
+void launch_fused_valu(const FusedValuLaunch& f, hipStream_t st)
+{
+    const int n = __builtin_ctzll(f.N);
+    const uint64_t n_cols = 1ull << (n - f.k);
+    const uint64_t blocks = std::min<uint64_t>((n_cols + 255) / 256, (uint64_t)device_info().cu_count * 8);
+    const dim3 gd((unsigned)std::max<uint64_t>(blocks, 1), f.nrows);
+    switch (f.k) {
+    case 1: hipLaunchKernelGGL(k_fused_valu<1>, gd, dim3(256), 0, st, f.psi, f.N, n_cols, f.k, f.pos, f.moff, f.m); break;
+    case 2: hipLaunchKernelGGL(k_fused_valu<2>, gd, dim3(256), 0, st, f.psi, f.N, n_cols, f.k, f.pos, f.moff, f.m); break;
+    case 3: hipLaunchKernelGGL(k_fused_valu<3>, gd, dim3(256), 0, st, f.psi, f.N, n_cols, f.k, f.pos, f.moff, f.m); break;
+    case 4: hipLaunchKernelGGL(k_fused_valu<4>, gd, dim3(256), 0, st, f.psi, f.N, n_cols, f.k, f.pos, f.moff, f.m); break;
+    default: hipLaunchKernelGGL(k_fused_valu<5>, gd, dim3(256), 0, st, f.psi, f.N, n_cols, f.k, f.pos, f.moff, f.m); break;
+    }
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace sv

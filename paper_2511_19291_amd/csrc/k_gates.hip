@@ -5,18 +5,30 @@
 // (psi[b|off(r)])_r <- M (psi[b|off(r)])_r  (Alg. 1 of Sec. 4.1.1 with the
 // MoveDim done by index arithmetic instead of a tensor permute).
 //
-// Memory access: consecutive threads take consecutive group bases, so every
-// member stream is read and written with coalesced 16-byte (float4) accesses
-// whenever no target or control is qubit 0 (two neighbouring amplitudes then
-// belong to the same member). A gate on qubit 0 alone keeps the pair inside
-// one float4. Other qubit-0 cases use 8-byte accesses. Amplitudes outside the
-// control subspace are never touched.
+// Memory access forms, chosen per gate by the host:
+//   SHFL  one target t in 1..6, no control below 7: each wave owns 128
+//         consecutive amplitudes (one float4 per lane, a fully contiguous
+//         1 KiB access); the pair partner lives in lane ^ 2^(t-1) of the same
+//         wave and is exchanged by a cross-lane shuffle.
+//   VEC2  no target or control is qubit 0: each member of a group is read as a
+//         float4 holding two neighbouring amplitudes; consecutive lanes take
+//         consecutive float4s of every member stream.
+//   PAIR  one target at qubit 0: the pair (b, b|1) is one float4.
+//   ODD   a control at qubit 0 (e.g. CNOT from qubit 0): float4 members as in
+//         VEC2 with only the odd amplitude of each float4 updated.
+//   VEC1  anything else: float2 per member.
+// Accesses are non-temporal (each amplitude is touched once per sweep) when
+// every written 128-byte line is written whole; otherwise cached.
+// Amplitudes outside the control subspace are never read or written, except
+// the even neighbours in the ODD form, which are written back unchanged.
 #include "sv_device.h"
 #include "sv_internal.h"
 
 namespace sv {
 
 namespace {
+
+enum Form { VEC1 = 1, VEC2 = 2, PAIR = 0, ODD = 3, SHFL = 4 };
 
 struct KGate {
     float2* p0;
@@ -28,6 +40,7 @@ struct KGate {
     uint64_t moff[4];     // member offsets: bits of the targets selected by the member index
     int npos;             // positions where zero bits are inserted (sorted ascending)
     int pos[6];
+    int t;                // SHFL: the target qubit
     float2 m[16];         // row-major 2^k x 2^k complex64
 };
 
@@ -48,11 +61,7 @@ __device__ __forceinline__ void matvec(const float2 (&m)[16], const float2 (&x)[
     }
 }
 
-// VEC = 2: each member access is a float4 holding two neighbouring
-//          amplitudes (requires every target/control >= 1).
-// VEC = 1: float2 per member.
-// VEC = 0: k = 1 with target 0: one float4 holds the whole pair.
-template <int K, int VEC, int U>
+template <int K, int F, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
 {
     constexpr int D = 1 << K;
@@ -62,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
     for (int i = 0; i < D * D; ++i) m[i] = a.m[i];
     const uint64_t u0 = (uint64_t)blockIdx.x * (kBlock * U) + threadIdx.x;
 
-    if constexpr (VEC == 2) {
+    if constexpr (F == VEC2 || F == ODD) {
         float4 v[U][D];
         uint64_t base[U];
 #pragma unroll
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
             base[r] = insert_zeros(u << 1, a.pos, a.npos) | a.cmask;
             if (u < a.n_units)
 #pragma unroll
-                for (int j = 0; j < D; ++j) v[r][j] = *reinterpret_cast<const float4*>(psi + (base[r] | a.moff[j]));
+                for (int j = 0; j < D; ++j) v[r][j] = ld4<NT>(psi + (base[r] | a.moff[j]));
         }
 #pragma unroll
         for (int r = 0; r < U; ++r) {
@@ -80,13 +89,43 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
             float2 xl[D], xh[D], yl[D], yh[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) { xl[j] = lo2(v[r][j]); xh[j] = hi2(v[r][j]); }
-            matvec<D>(m, xl, yl);
+            if constexpr (F == VEC2) matvec<D>(m, xl, yl);
             matvec<D>(m, xh, yh);
 #pragma unroll
             for (int j = 0; j < D; ++j)
-                *reinterpret_cast<float4*>(psi + (base[r] | a.moff[j])) = pack4(yl[j], yh[j]);
+                st4<NT>(psi + (base[r] | a.moff[j]), pack4(F == VEC2 ? yl[j] : xl[j], yh[j]));
         }
-    } else if constexpr (VEC == 0) {
+    } else if constexpr (F == SHFL) {
+        static_assert(K == 1, "shuffle form is for one target");
+        const int t = a.t;
+        const int lane_xor = 1 << (t - 1);
+        float4 v[U];
+        uint64_t base[U];
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const uint64_t u = u0 + (uint64_t)r * kBlock;
+            base[r] = insert_zeros(u << 1, a.pos, a.npos) | a.cmask;
+            // whole waves are in or out of range (n_units is a multiple of 64)
+            if (u < a.n_units) v[r] = ld4<NT>(psi + base[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const uint64_t u = u0 + (uint64_t)r * kBlock;
+            if (u >= a.n_units) continue;
+            float4 w;
+            w.x = __shfl_xor(v[r].x, lane_xor, 64);
+            w.y = __shfl_xor(v[r].y, lane_xor, 64);
+            w.z = __shfl_xor(v[r].z, lane_xor, 64);
+            w.w = __shfl_xor(v[r].w, lane_xor, 64);
+            const bool hi = (base[r] >> t) & 1;
+            // low member: y0 = m00 x0 + m01 x1; high member: y1 = m10 x0 + m11 x1
+            const float2 cs = hi ? m[3] : m[0];   // coefficient of my own amplitude
+            const float2 cp = hi ? m[2] : m[1];   // coefficient of the partner's
+            const float2 y0 = cfma(cp, lo2(w), cmul(cs, lo2(v[r])));
+            const float2 y1 = cfma(cp, hi2(w), cmul(cs, hi2(v[r])));
+            st4<NT>(psi + base[r], pack4(y0, y1));
+        }
+    } else if constexpr (F == PAIR) {
         static_assert(K == 1, "pair-in-lane form is for one target");
         float4 v[U];
         uint64_t base[U];
@@ -94,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
         for (int r = 0; r < U; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             base[r] = insert_zeros(u, a.pos, a.npos) | a.cmask;
-            if (u < a.n_units) v[r] = *reinterpret_cast<const float4*>(psi + base[r]);
+            if (u < a.n_units) v[r] = ld4<NT>(psi + base[r]);
         }
 #pragma unroll
         for (int r = 0; r < U; ++r) {
@@ -102,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
             if (u >= a.n_units) continue;
             float2 x[2] = {lo2(v[r]), hi2(v[r])}, y[2];
             matvec<2>(m, x, y);
-            *reinterpret_cast<float4*>(psi + base[r]) = pack4(y[0], y[1]);
+            st4<NT>(psi + base[r], pack4(y[0], y[1]));
         }
     } else {
         float2 v[U][D];
@@ -113,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
             base[r] = insert_zeros(u, a.pos, a.npos) | a.cmask;
             if (u < a.n_units)
 #pragma unroll
-                for (int j = 0; j < D; ++j) v[r][j] = psi[base[r] | a.moff[j]];
+                for (int j = 0; j < D; ++j) v[r][j] = ld2<NT>(psi + (base[r] | a.moff[j]));
         }
 #pragma unroll
         for (int r = 0; r < U; ++r) {
@@ -122,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
             float2 y[D];
             matvec<D>(m, v[r], y);
 #pragma unroll
-            for (int j = 0; j < D; ++j) psi[base[r] | a.moff[j]] = y[j];
+            for (int j = 0; j < D; ++j) st2<NT>(psi + (base[r] | a.moff[j]), y[j]);
         }
     }
 }
@@ -130,14 +169,15 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
 // Diagonal gates: every amplitude of the swept subspace is multiplied by a
 // phase chosen by its free-target bits. Fixed positions (controls, and the
 // targets of gates that only change the all-ones pattern) are set to 1, so
-// e.g. CZ touches one quarter of the state.
+// e.g. CZ touches one quarter of the state. A fixed qubit 0 is handled with
+// float4 accesses that update only the odd amplitude.
 struct KDiag {
     float2* p0;
     float2* p1;
     int nrow0;
     uint64_t N;
     uint64_t n_units;
-    uint64_t fmask;       // fixed-to-1 bits
+    uint64_t fmask;       // fixed-to-1 bits above qubit 0
     int npos;
     int pos[5];
     int nfree;
@@ -152,27 +192,27 @@ __device__ __forceinline__ float2 diag_phase(const KDiag& a, uint64_t b)
     return a.ph[idx];
 }
 
-template <int VEC, int U>
+template <int F, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_diag(KDiag a)
 {
     float2* psi = row_ptr(a.p0, a.p1, a.nrow0, a.N, blockIdx.y);
     const uint64_t u0 = (uint64_t)blockIdx.x * (kBlock * U) + threadIdx.x;
-    if constexpr (VEC == 2) {
+    if constexpr (F == VEC2 || F == ODD) {
         float4 v[U];
         uint64_t base[U];
 #pragma unroll
         for (int r = 0; r < U; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             base[r] = insert_zeros(u << 1, a.pos, a.npos) | a.fmask;
-            if (u < a.n_units) v[r] = *reinterpret_cast<const float4*>(psi + base[r]);
+            if (u < a.n_units) v[r] = ld4<NT>(psi + base[r]);
         }
 #pragma unroll
         for (int r = 0; r < U; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             if (u >= a.n_units) continue;
-            const float2 y0 = cmul(diag_phase(a, base[r]), lo2(v[r]));
+            const float2 y0 = F == ODD ? lo2(v[r]) : cmul(diag_phase(a, base[r]), lo2(v[r]));
             const float2 y1 = cmul(diag_phase(a, base[r] | 1), hi2(v[r]));
-            *reinterpret_cast<float4*>(psi + base[r]) = pack4(y0, y1);
+            st4<NT>(psi + base[r], pack4(y0, y1));
         }
     } else {
         float2 v[U];
@@ -181,13 +221,13 @@ __global__ __launch_bounds__(kBlock) void k_diag(KDiag a)
         for (int r = 0; r < U; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             base[r] = insert_zeros(u, a.pos, a.npos) | a.fmask;
-            if (u < a.n_units) v[r] = psi[base[r]];
+            if (u < a.n_units) v[r] = ld2<NT>(psi + base[r]);
         }
 #pragma unroll
         for (int r = 0; r < U; ++r) {
             const uint64_t u = u0 + (uint64_t)r * kBlock;
             if (u >= a.n_units) continue;
-            psi[base[r]] = cmul(diag_phase(a, base[r]), v[r]);
+            st2<NT>(psi + base[r], cmul(diag_phase(a, base[r]), v[r]));
         }
     }
 }
@@ -195,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(KDiag a)
 // Every row := e_idx.
 __global__ __launch_bounds__(kBlock) void k_basis(float2* p0, uint64_t N, uint64_t idx)
 {
-    float4* row = reinterpret_cast<float4*>(p0 + (uint64_t)blockIdx.y * N);
+    float2* row = p0 + (uint64_t)blockIdx.y * N;
     const uint64_t n4 = N >> 1;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (uint64_t)gridDim.x * kBlock) {
         float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -203,24 +243,15 @@ __global__ __launch_bounds__(kBlock) void k_basis(float2* p0, uint64_t N, uint64
             if (idx & 1) z.z = 1.f;
             else z.x = 1.f;
         }
-        row[i] = z;
+        st4(row + 2 * i, z);
     }
 }
 
-// Plain streaming copy (the bandwidth ceiling reference).
-__global__ __launch_bounds__(kBlock) void k_copy(float4* __restrict__ dst, const float4* __restrict__ src, uint64_t n4)
+// Plain streaming copy (the bandwidth reference used to scale byte counters).
+__global__ __launch_bounds__(kBlock) void k_copy(float2* __restrict__ dst, const float2* __restrict__ src, uint64_t n4)
 {
-    constexpr int U = 4;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock * U;
-    for (uint64_t b = (uint64_t)blockIdx.x * kBlock * U + threadIdx.x; b < n4; b += stride) {
-        float4 v[U];
-#pragma unroll
-        for (int r = 0; r < U; ++r)
-            if (b + (uint64_t)r * kBlock < n4) v[r] = src[b + (uint64_t)r * kBlock];
-#pragma unroll
-        for (int r = 0; r < U; ++r)
-            if (b + (uint64_t)r * kBlock < n4) dst[b + (uint64_t)r * kBlock] = v[r];
-    }
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n4) st4(dst + 2 * i, ld4(src + 2 * i));
 }
 
 void sort_small(int* v, int n)
@@ -231,12 +262,15 @@ void sort_small(int* v, int n)
 
 constexpr int kUnroll = 2;
 
-template <int K, int VEC>
-void dispatch_gate(const KGate& a, int rows, hipStream_t st)
+template <int K, int F>
+void dispatch_gate(const KGate& a, int rows, bool nt, hipStream_t st)
 {
     const uint64_t per_block = (uint64_t)kBlock * kUnroll;
     const uint64_t blocks = (a.n_units + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_gate<K, VEC, kUnroll>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
+    if (nt)
+        hipLaunchKernelGGL((k_gate<K, F, kUnroll, true>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_gate<K, F, kUnroll, false>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
     SV_HIP(hipGetLastError());
 }
 
@@ -258,29 +292,54 @@ void launch_gate(const GateLaunch& g, hipStream_t st)
             if ((r >> (g.k - 1 - j)) & 1) off |= 1ull << g.targets[j];
         a.moff[r] = off;
     }
-    int lowest = 64;
-    a.npos = 0;
-    for (int j = 0; j < g.k; ++j) { a.pos[a.npos++] = g.targets[j]; lowest = std::min(lowest, g.targets[j]); }
+    int lowest_t = 64, lowest_c = 64;
+    for (int j = 0; j < g.k; ++j) lowest_t = std::min(lowest_t, g.targets[j]);
+    for (int j = 0; j < g.nc; ++j) lowest_c = std::min(lowest_c, g.controls[j]);
+    const int rows = g.rows.nrows;
+    const uint64_t groups = 1ull << (n - g.k - g.nc);
+
+    // SHFL: one target in 1..6, every control >= 7, whole waves of 128 amplitudes
+    if (g.k == 1 && lowest_t >= 1 && lowest_t <= 6 && lowest_c >= 7 && n - g.nc >= 7) {
+        for (int j = 0; j < g.nc; ++j) {
+            a.pos[a.npos++] = g.controls[j];
+            a.cmask |= 1ull << g.controls[j];
+        }
+        sort_small(a.pos, a.npos);
+        a.t = g.targets[0];
+        a.n_units = 1ull << (n - g.nc - 1);      // float4s in the control subspace
+        dispatch_gate<1, SHFL>(a, rows, true, st);
+        return;
+    }
+    // insert positions: targets and controls, except a control at qubit 0 in
+    // the ODD form (there the float4 spans bit 0 and only the odd half changes)
+    const bool odd = lowest_c == 0 && lowest_t >= 1;
+    for (int j = 0; j < g.k; ++j) a.pos[a.npos++] = g.targets[j];
     for (int j = 0; j < g.nc; ++j) {
-        a.pos[a.npos++] = g.controls[j];
         a.cmask |= 1ull << g.controls[j];
-        lowest = std::min(lowest, g.controls[j]);
+        if (!(odd && g.controls[j] == 0)) a.pos[a.npos++] = g.controls[j];
     }
     sort_small(a.pos, a.npos);
-    const uint64_t groups = 1ull << (n - g.k - g.nc);
-    const int rows = g.rows.nrows;
-    if (lowest >= 1 && groups >= 2) {
+    // whole 128-byte lines are written when no target/control sits below
+    // qubit 4 (a control at qubit 0 in the ODD form still writes both halves)
+    const bool nt = a.npos == 0 || a.pos[0] >= kFullLineQubit;
+    if (odd) {
+        a.cmask &= ~1ull;
+        a.n_units = groups;                      // one float4 (two amplitudes, bit 0 free) per group member
+        if (g.k == 1) dispatch_gate<1, ODD>(a, rows, nt, st);
+        else dispatch_gate<2, ODD>(a, rows, nt, st);
+    } else if (std::min(lowest_t, lowest_c) >= 1 && groups >= 2) {
         a.n_units = groups >> 1;
-        if (g.k == 1) dispatch_gate<1, 2>(a, rows, st);
-        else dispatch_gate<2, 2>(a, rows, st);
-    } else if (g.k == 1 && g.targets[0] == 0 && (g.nc == 0 || a.pos[1] >= 1)) {
+        if (g.k == 1) dispatch_gate<1, VEC2>(a, rows, nt, st);
+        else dispatch_gate<2, VEC2>(a, rows, nt, st);
+    } else if (g.k == 1 && g.targets[0] == 0) {
         // pair (b, b|1) in one float4: the zero inserted at bit 0 is the target
         a.n_units = groups;
-        dispatch_gate<1, 0>(a, rows, st);
+        // the inserted zero at bit 0 lies inside the float4: only controls split lines
+        dispatch_gate<1, PAIR>(a, rows, lowest_c >= kFullLineQubit, st);
     } else {
         a.n_units = groups;
-        if (g.k == 1) dispatch_gate<1, 1>(a, rows, st);
-        else dispatch_gate<2, 1>(a, rows, st);
+        if (g.k == 1) dispatch_gate<1, VEC1>(a, rows, nt, st);
+        else dispatch_gate<2, VEC1>(a, rows, nt, st);
     }
 }
 
@@ -292,29 +351,35 @@ void launch_diag(const DiagLaunch& d, hipStream_t st)
     a.p1 = d.rows.p1;
     a.nrow0 = d.rows.nrow0;
     a.N = d.rows.N;
-    a.npos = d.nfixed;
-    int lowest = 64;
+    bool fixed0 = false;
     for (int j = 0; j < d.nfixed; ++j) {
-        a.pos[j] = d.fixed[j];
+        if (d.fixed[j] == 0) {
+            fixed0 = true;
+            continue;
+        }
+        a.pos[a.npos++] = d.fixed[j];
         a.fmask |= 1ull << d.fixed[j];
-        lowest = std::min(lowest, d.fixed[j]);
     }
     sort_small(a.pos, a.npos);
     a.nfree = d.nfree;
     for (int j = 0; j < d.nfree; ++j) a.fbit[j] = 1ull << d.freeq[j];
     for (int i = 0; i < (1 << d.nfree); ++i) a.ph[i] = d.ph[i];
-    const uint64_t amps = 1ull << (n - d.nfixed);
     const uint64_t per_block = (uint64_t)kBlock * kUnroll;
     const int rows = d.rows.nrows;
-    if (lowest >= 1 && amps >= 2) {
-        a.n_units = amps >> 1;
-        const uint64_t blocks = (a.n_units + per_block - 1) / per_block;
-        hipLaunchKernelGGL((k_diag<2, kUnroll>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    } else {
-        a.n_units = amps;
-        const uint64_t blocks = (a.n_units + per_block - 1) / per_block;
-        hipLaunchKernelGGL((k_diag<1, kUnroll>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    }
+    // amplitudes in the swept subspace, counting bit 0 as free: fixed
+    // positions lie in 1..n-1, so there are at least two and the float4 forms
+    // always apply
+    a.n_units = 1ull << (n - a.npos - 1);
+    const uint64_t blocks = (a.n_units + per_block - 1) / per_block;
+    const bool nt = a.npos == 0 || a.pos[0] >= kFullLineQubit;
+    if (fixed0 && nt)
+        hipLaunchKernelGGL((k_diag<ODD, kUnroll, true>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
+    else if (fixed0)
+        hipLaunchKernelGGL((k_diag<ODD, kUnroll, false>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
+    else if (nt)
+        hipLaunchKernelGGL((k_diag<VEC2, kUnroll, true>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_diag<VEC2, kUnroll, false>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
     SV_HIP(hipGetLastError());
 }
 
@@ -330,9 +395,9 @@ void launch_basis(const Rows& r, uint64_t idx, hipStream_t st)
 void launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st)
 {
     const uint64_t n4 = bytes / 16;
-    const uint64_t blocks = std::min<uint64_t>((n4 + kBlock * 4 - 1) / (kBlock * 4), 65536);
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(kBlock), 0, st,
-                       static_cast<float4*>(dst), static_cast<const float4*>(src), n4);
+    const uint64_t blocks = (n4 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBlock), 0, st, static_cast<float2*>(dst),
+                       static_cast<const float2*>(src), n4);
     SV_HIP(hipGetLastError());
 }
 

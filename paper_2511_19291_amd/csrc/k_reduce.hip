@@ -36,12 +36,12 @@ __global__ __launch_bounds__(kBlock) void k_zall1(Rows rows, int tb, double* par
 {
     const int row = blockIdx.y;
     const uint64_t blk = blockIdx.x;
-    const float4* p = reinterpret_cast<const float4*>(crow(rows, row) + (blk << tb));
+    const float2* p = crow(rows, row) + (blk << tb);
     const int nr = 1 << (tb - 9);
     double tot = 0.0, s0 = 0.0, sr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
     for (int r = 0; r < nr; ++r) {
-        const float4 v = p[threadIdx.x + kBlock * r];
+        const float4 v = ld4(p + 2 * (threadIdx.x + kBlock * r));
         const double a = prob(lo2(v)), b = prob(hi2(v));
         const double ab = a + b;
         tot += ab;
@@ -84,34 +84,25 @@ __global__ __launch_bounds__(kBlock) void k_zall1_small(Rows rows, int n, double
     }
 }
 
-// Stage 2: one block per row. S_i for tile bits = sum of block S_i; for bits
-// above the tile, S_i = sum of block totals whose block index has bit i - tb.
-// out[row][i] = tot - 2 S_i, out[row][n] = tot.
+// Stage 2: block (i, row) produces output i of one row. S_i for a tile bit
+// is the sum of the blocks' S_i; for a bit above the tile it is the sum of the
+// totals of the blocks whose index has bit i - tb. Every block also sums the
+// totals (in the same fixed order), so out[row][i] = tot - 2 S_i and
+// out[row][n] = tot come out of one pass.
 __global__ __launch_bounds__(kBlock) void k_zall2(const double* part, int n, int tb, uint64_t nblk, double* out)
 {
-    const int row = blockIdx.x;
+    const int i = blockIdx.x;
+    const int row = blockIdx.y;
     const double* pr = part + (uint64_t)row * nblk * (tb + 1);
-    double v[SV_MAX_QUBITS + 1];
-#pragma unroll
-    for (int i = 0; i <= SV_MAX_QUBITS; ++i) v[i] = 0.0;
+    double v[2] = {0.0, 0.0};   // tot, S_i
     for (uint64_t b = threadIdx.x; b < nblk; b += kBlock) {
         const double* q = pr + b * (tb + 1);
-        const double t = q[0];
-        v[SV_MAX_QUBITS] += t;
-#pragma unroll
-        for (int i = 0; i < SV_MAX_QUBITS; ++i) {
-            if (i < tb) v[i] += q[1 + i];
-            else if (i < n && ((b >> (i - tb)) & 1)) v[i] += t;
-        }
+        v[0] += q[0];
+        if (i < tb) v[1] += q[1 + i];
+        else if (i < n && ((b >> (i - tb)) & 1)) v[1] += q[0];
     }
-    block_sum<SV_MAX_QUBITS + 1>(v);
-    if (threadIdx.x == 0) {
-        const double tot = v[SV_MAX_QUBITS];
-#pragma unroll
-        for (int i = 0; i < SV_MAX_QUBITS; ++i)
-            if (i < n) out[(uint64_t)row * (n + 1) + i] = tot - 2.0 * v[i];
-        out[(uint64_t)row * (n + 1) + n] = tot;
-    }
+    block_sum<2>(v);
+    if (threadIdx.x == 0) out[(uint64_t)row * (n + 1) + i] = i < n ? v[0] - 2.0 * v[1] : v[0];
 }
 
 // ---------------------------------------------------------- Pauli strings
@@ -242,7 +233,7 @@ void launch_zall(const Rows& r, int n, double* scratch, double* out, hipStream_t
         hipLaunchKernelGGL(k_zall1, dim3((unsigned)nblk, r.nrows), dim3(kBlock), 0, st, r, tb, scratch, nblk);
     }
     SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_zall2, dim3(r.nrows), dim3(kBlock), 0, st, scratch, n, tb, nblk, out);
+    hipLaunchKernelGGL(k_zall2, dim3(n + 1, r.nrows), dim3(kBlock), 0, st, scratch, n, tb, nblk, out);
     SV_HIP(hipGetLastError());
 }
 

@@ -7,8 +7,6 @@ static sv_status pending(const char* what)
     (void)what;
     return SV_ERR_UNSUPPORTED;
 }
-sv_status sv_apply_fused(sv_state, const sv_block*, int, int) { return pending("fused"); }
-sv_status sv_fuse_plan(int, const sv_op*, int, const double*, int, int, sv_block*, int, double*, int*) { return pending("plan"); }
 sv_status sv_batch_plan_create(int, const int*, const sv_op* const*, const int*, const int*, void*, sv_batch_plan*) { return pending("batch"); }
 sv_status sv_batch_param_layout(sv_batch_plan, int64_t*, int64_t*) { return pending("batch"); }
 sv_status sv_batch_launch(sv_batch_plan, const double*, double*) { return pending("batch"); }

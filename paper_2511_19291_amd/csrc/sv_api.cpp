@@ -20,6 +20,24 @@ thread_local std::string g_last_error;
 
 [[noreturn]] void fail(sv_status st, const std::string& msg) { throw Error{st, msg}; }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void gate_matrix_of_op(const sv_op& op, const double* params, cd* m, int* k)
+{
+    if (op.kind == SV_MATRIX) {
+        if (!op.matrix) fail(SV_ERR_INVALID_ARGUMENT, "SV_MATRIX op without a matrix");
+        *k = op.n_targets;
+        const int D = 1 << *k;
+        for (int i = 0; i < D * D; ++i) m[i] = cd(op.matrix[2 * i], op.matrix[2 * i + 1]);
+        return;
+    }
+    double prm[3] = {0.0, 0.0, 0.0};
+    const int np = kind_nparams(op.kind);
+    for (int j = 0; j < np; ++j) prm[j] = params[op.param[j]];
+    *k = kind_matrix(op.kind, prm, m);
+    if (*k < 0) fail(SV_ERR_INVALID_ARGUMENT, "unknown gate kind " + std::to_string(op.kind));
+}
+
 void hip_check(hipError_t e, const char* what)
 {
     if (e != hipSuccess) fail(SV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -363,6 +381,7 @@ sv_status sv_free(sv_state s)
         if (s->dout) (void)hipFree(s->dout);
         if (s->hout) (void)hipHostFree(s->hout);
         if (s->dterms) (void)hipFree(s->dterms);
+        if (s->dfused) (void)hipFree(s->dfused);
         delete s;
     });
 }

@@ -32,6 +32,62 @@ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c)
     return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
 }
 
+// Streaming (non-temporal) 16- and 8-byte accesses: every amplitude of a
+// sweep is touched once, so there is nothing to keep in the caches. Only
+// worth it when every 128-byte line a kernel writes is written whole: a
+// partially written line that bypasses the cache is merged in memory, which
+// costs far more than the cached path. The NT template flag selects.
+typedef float sv_v4f __attribute__((ext_vector_type(4)));
+typedef float sv_v2f __attribute__((ext_vector_type(2)));
+
+template <bool NT = true>
+__device__ __forceinline__ float4 ld4(const float2* p)
+{
+    if constexpr (NT) {
+        const sv_v4f v = __builtin_nontemporal_load(reinterpret_cast<const sv_v4f*>(p));
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const float4*>(p);
+    }
+}
+
+template <bool NT = true>
+__device__ __forceinline__ void st4(float2* p, float4 x)
+{
+    if constexpr (NT) {
+        const sv_v4f v = {x.x, x.y, x.z, x.w};
+        __builtin_nontemporal_store(v, reinterpret_cast<sv_v4f*>(p));
+    } else {
+        *reinterpret_cast<float4*>(p) = x;
+    }
+}
+
+template <bool NT = true>
+__device__ __forceinline__ float2 ld2(const float2* p)
+{
+    if constexpr (NT) {
+        const sv_v2f v = __builtin_nontemporal_load(reinterpret_cast<const sv_v2f*>(p));
+        return make_float2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT = true>
+__device__ __forceinline__ void st2(float2* p, float2 x)
+{
+    if constexpr (NT) {
+        const sv_v2f v = {x.x, x.y};
+        __builtin_nontemporal_store(v, reinterpret_cast<sv_v2f*>(p));
+    } else {
+        *p = x;
+    }
+}
+
+// Lowest qubit whose runs of consecutive amplitudes are written whole by a
+// sweep that skips positions below it: runs of 2^4 amplitudes = 128 bytes.
+constexpr int kFullLineQubit = 4;
+
 __device__ __forceinline__ float2 lo2(float4 v) { return make_float2(v.x, v.y); }
 __device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); }
 __device__ __forceinline__ float4 pack4(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }

@@ -23,6 +23,7 @@ struct Error {
 };
 
 [[noreturn]] void fail(sv_status st, const std::string& msg);
+void set_last_error(const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 #define SV_HIP(call) ::sv::hip_check((call), #call)
 
@@ -43,6 +44,9 @@ int kind_matrix(int kind, const double* prm, cd* m);
 int kind_dmatrix(int kind, const double* prm, int j, cd* m);
 int kind_targets(int kind);
 int kind_nparams(int kind);
+// Matrix of a circuit op (named kind at its parameters, or its explicit
+// matrix); *k = number of targets.
+void gate_matrix_of_op(const sv_op& op, const double* params, cd* m, int* k);
 
 // ------------------------------------------------------------ kernel launch arguments
 
@@ -130,6 +134,28 @@ void launch_adj_step(const AdjLaunch& a, double* part, hipStream_t st);
 // out[s] = sum_b part[s * grid + b], s < nslots
 void launch_sum_slots(const double* part, int grid, int nslots, double* out, hipStream_t st);
 
+// Fused blocks (k_fused.hip).
+struct FusedLaunch {
+    float2* psi;
+    uint64_t N;
+    int nrows;
+    int targets[5];           // exactly five (padded with identity qubits)
+    int mode;                 // SV_FUSED_FP32_MFMA or SV_FUSED_BF16X3
+    const float* amat;        // device: real 64x64 embedding (FP32), or hi then lo parts (BF16X3)
+};
+void launch_fused_mfma(const FusedLaunch& f, hipStream_t st);
+
+struct FusedValuLaunch {
+    float2* psi;
+    uint64_t N;
+    int nrows;
+    int k;
+    const int* pos;           // device: sorted target positions (k entries)
+    const uint64_t* moff;     // device: member offsets (2^k entries)
+    const float2* m;          // device: 2^k x 2^k complex64
+};
+void launch_fused_valu(const FusedValuLaunch& f, hipStream_t st);
+
 }  // namespace sv
 
 // sv_state handle
@@ -148,4 +174,6 @@ struct sv_state_s {
     double* hout = nullptr;         // pinned host mirror of dout
     void* dterms = nullptr;         // device copy of observable terms
     size_t dterms_cap = 0;
+    void* dfused = nullptr;         // device copy of fused block matrices
+    size_t dfused_cap = 0;
 };

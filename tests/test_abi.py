@@ -48,6 +48,40 @@ def test_status_strings(svmod):
     assert L.sv_status_string(99) == b"unknown status"
 
 
+@pytest.mark.parametrize("n,seed", [(3, 1), (6, 2), (9, 3)])
+def test_fusion_plan_reproduces_circuit(svmod, n, seed):
+    """The host fusion planner's blocks, applied in order by the oracle, give
+    the oracle's gate-by-gate state (the planner only regroups gates)."""
+    import oracle
+    circ = Cc.random_circuit(n, 120, seed)
+    for max_k in (3, 4, 5):
+        if max_k < 5 and any(len(op.qubits()) > max_k for op in circ.ops):
+            continue
+        blocks = svmod.fuse_plan(circ, max_k)
+        assert all(len(t) <= max_k for t, _ in blocks)
+        psi = oracle.basis_state(n)
+        for t, m in blocks:
+            oracle.apply_matrix(psi, n, m, list(t))
+        np.testing.assert_allclose(psi, oracle.run(circ), atol=1e-12)
+
+
+def test_fusion_plan_brickwork_block_count(svmod):
+    """32-qubit brickwork (950 gates) fuses into far fewer 5-qubit sweeps."""
+    circ = Cc.brickwork_u3_cz(32, 20, 3)
+    blocks = svmod.fuse_plan(circ, 5)
+    assert len(blocks) <= 100
+    assert sum(len(t) == 5 for t, _ in blocks) >= 0.8 * len(blocks)
+
+
+def test_fusion_plan_rejects_bad_input(svmod):
+    circ = Cc.random_circuit(4, 10, 1)
+    with pytest.raises(svmod.SvError):
+        svmod.fuse_plan(circ, 6)
+    bad = Cc.Circuit(4, [Cc.Op("x", (4,))], np.zeros(0))
+    with pytest.raises(svmod.SvError):
+        svmod.fuse_plan(bad, 5)
+
+
 @pytest.mark.parametrize("n,targets,controls,code", [
     (4, [0], [], 0), (4, [3, 0], [1, 2], 0), (4, [4], [], 2), (4, [-1], [], 2), (4, [1], [1], 3),
     (4, [0, 0], [], 3), (4, [0, 1, 2], [], 4), (5, [0], [1, 2, 3, 4], 4), (2, [0, 1], [], 0),

@@ -1,0 +1,121 @@
+"""GPU parity of the fused-block sweeps (FP32 MFMA, split BF16x3 MFMA, FP32
+vector) against the oracle's unfused gate-by-gate result.
+
+Tolerance: max |psi - psi_ref| <= 1e-5 per amplitude for every mode. FP32
+products round at 2^-24 relative; BF16x3 drops only the lo*lo product and
+the residual of the two-term split, about 2^-16 relative per product, which
+at the amplitudes of these states (<= 2^-n/2 typical) stays far below 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_19291_amd import circuits as C
+from paper_2511_19291_amd import sv as svmod
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+AMP_TOL = 1e-5
+MODES = [svmod.FUSED_FP32_MFMA, svmod.FUSED_BF16X3, svmod.FUSED_VALU]
+
+
+def _upload(sv, n, psi, batch=1):
+    st = sv.State(n, batch)
+    st.from_numpy(np.tile(psi.astype(np.complex64), (batch, 1)))
+    return st
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,targets", [
+    (10, (9, 8, 7, 6, 5)),        # targets high: columns = bits 0..4
+    (10, (0, 1, 2, 3, 4)),        # targets low: columns = bits 5..9
+    (12, (3, 0, 11, 6, 1)),       # scattered, unsorted
+    (15, (14, 2, 7, 9, 5)),
+    (16, (4, 12, 0, 15, 8)),
+])
+def test_single_block_random_unitary(sv, mode, n, targets):
+    """A Haar-random 32x32 unitary on five ordered targets: pins the MFMA
+    operand and result layouts and the tile bit mapping."""
+    rng = np.random.default_rng(n * 7 + sum(targets))
+    psi0 = pins.random_state(n, rng)
+    m = pins.haar_unitary(32, rng)
+    st = _upload(sv, n, psi0, batch=2)
+    st.apply_fused([(targets, m)], mode)
+    ref = psi0.astype(np.complex64).astype(np.complex128)
+    oracle.apply_matrix(ref, n, m, list(targets))
+    out = st.to_numpy()
+    for r in range(2):
+        assert np.max(np.abs(out[r] - ref)) <= AMP_TOL
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_small_blocks_padded(sv, mode, k):
+    n = 11
+    rng = np.random.default_rng(50 + k)
+    psi0 = pins.random_state(n, rng)
+    targets = tuple(int(x) for x in rng.permutation(n)[:k])
+    m = pins.haar_unitary(1 << k, rng)
+    st = _upload(sv, n, psi0)
+    st.apply_fused([(targets, m)], mode)
+    ref = psi0.astype(np.complex64).astype(np.complex128)
+    oracle.apply_matrix(ref, n, m, list(targets))
+    assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n", [10, 14, 18])
+def test_planned_brickwork_vs_unfused_oracle(sv, mode, n):
+    """The brickwork circuit fused into <= 5-qubit blocks by the planner and
+    run block by block equals the oracle's gate-by-gate state."""
+    circ = C.brickwork_u3_cz(n, 20, 3)
+    blocks = svmod.fuse_plan(circ, 5)
+    assert len(blocks) < len(circ.ops) / 4
+    st = sv.State(n).reset()
+    st.apply_fused(blocks, mode)
+    ref = oracle.run(circ)
+    assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
+
+
+def test_mfma_needs_ten_qubits_valu_does_not(sv):
+    n = 8
+    rng = np.random.default_rng(3)
+    m = pins.haar_unitary(32, rng)
+    st = sv.State(n).reset()
+    with pytest.raises(svmod.SvError) as e:
+        st.apply_fused([((0, 1, 2, 3, 4), m)], svmod.FUSED_FP32_MFMA)
+    assert e.value.status == 1
+    st.apply_fused([((0, 1, 2, 3, 4), m)], svmod.FUSED_VALU)
+    ref = oracle.basis_state(n, 0)
+    oracle.apply_matrix(ref, n, m, [0, 1, 2, 3, 4])
+    assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
+
+
+@pytest.fixture(scope="module")
+def fused24_reference():
+    circ = C.WORKLOADS["fused24"]()
+    return circ, oracle.run(circ)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_fused24_error_vs_fp64_oracle(sv, fused24_reference, mode):
+    """24-qubit instance of the fusion workload: FP32 MFMA and BF16x3 against
+    the complex128 oracle (max amplitude error, ||dpsi||_2, infidelity,
+    <sum Z> error), next to the plain per-gate path."""
+    circ, ref = fused24_reference
+    n = circ.n
+    blocks = svmod.fuse_plan(circ, 5)
+    st = sv.State(n).reset()
+    st.apply_fused(blocks, mode)
+    out = st.to_numpy()[0]
+    err = np.max(np.abs(out - ref))
+    dn = np.linalg.norm(out - ref)
+    infid = 1 - abs(np.vdot(ref, out)) ** 2
+    z = st.expval_z_all()[0]
+    zr, _ = oracle.expval_z_all(ref, n)
+    print(f"mode {mode}: max|dpsi| {err:.2e} ||dpsi|| {dn:.2e} 1-F {infid:.2e} "
+          f"d<sumZ> {abs(z[:n].sum() - zr.sum()):.2e}")
+    assert err <= AMP_TOL
+    assert abs(z[:n].sum() - zr.sum()) <= 2 * n * dn + 1e-12

@@ -83,6 +83,40 @@ def test_random_circuits(sv, n, seed):
     assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
 
 
+@pytest.mark.parametrize("n", [7, 12])
+def test_low_qubit_access_forms(sv, n):
+    """Controls and targets on the lowest qubits select the shuffle, odd-lane,
+    pair-in-lane and masked-diagonal forms: CNOT/CZ/controlled U3 from qubit
+    0 to every target, targets 1..6 with controls above and below 7, and
+    two-qubit gates with a target at qubit 0."""
+    rng = np.random.default_rng(40 + n)
+    psi0 = pins.random_state(n, rng)
+    st = _upload(sv, n, psi0)
+    ref = _ref_start(psi0)
+    b = C._Builder(n)
+    for t in range(1, n):
+        b.gate("x", [t], [0])
+        b.gate("z", [t], [0])
+        b.gate("u3", [t], [0], rng.uniform(0, 2 * np.pi, 3))
+        b.gate("p", [t], [0], [rng.uniform(0, 2 * np.pi)])
+        b.gate("rz", [t], [0], [rng.uniform(0, 2 * np.pi)])
+    for t in range(1, min(7, n)):
+        b.gate("u3", [t], [], rng.uniform(0, 2 * np.pi, 3))
+        if t != n - 1:
+            b.gate("ry", [t], [n - 1], [rng.uniform(0, 2 * np.pi)])
+        b.gate("rx", [t], [(t + 1) % n if (t + 1) % n != t else 0], [rng.uniform(0, 2 * np.pi)])
+    for t in range(1, n):
+        b.gate("rxx", [0, t], [], [rng.uniform(0, 2 * np.pi)])
+        b.gate("swap", [t, 0])
+        b.gate("rzz", [t, 0], [], [rng.uniform(0, 2 * np.pi)])
+    b.gate("x", [0], [n - 1])
+    b.gate("z", [0], [1, 2])
+    circ = b.build("low_forms")
+    st.run(circ)
+    oracle.run(circ, psi=ref)
+    assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
+
+
 def test_three_controls(sv):
     n = 8
     rng = np.random.default_rng(8)
