@@ -202,9 +202,117 @@ def main() -> int:
     return 0
 
 
+def _timed_ms(fn, stream) -> float:
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
-    """Fused-MFMA, adjoint and batched forms against the plain form."""
-    return {}
+    """Fused-MFMA, adjoint and batched forms against the plain form, each on
+    its own workload, all on this GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2511_19291_amd import circuits as C
+    from paper_2511_19291_amd import sv
+
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    # -- fused blocks: the same 30-qubit brickwork, and the 32-qubit instance
+    fused = {}
+    for nq, seed, with_plain in ((n, 2, False), (32, 3, True)):
+        circ = C.brickwork_u3_cz(nq, 20, seed)
+        t0 = time.perf_counter()
+        blocks = sv.fuse_plan(circ, 5)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        st = sv.State(nq)
+        entry = {"gates": len(circ.ops), "blocks": len(blocks), "plan_ms": round(plan_ms, 2)}
+        for mode, name in ((sv.FUSED_FP32_MFMA, "fp32_mfma"), (sv.FUSED_BF16X3, "bf16x3")):
+            st.reset()
+            st.apply_fused(blocks[:2], mode)
+            ms = _timed_ms(lambda: (st.reset(), st.apply_fused(blocks, mode)), stream)
+            per_block = ms / len(blocks)
+            entry[name] = {"ms": round(ms, 2), "gates_per_s": round(len(circ.ops) / (ms / 1e3), 1),
+                           "ms_per_block": round(per_block, 4),
+                           "GBps_per_block": round(16 * (1 << nq) / (per_block / 1e3) / 1e9, 1),
+                           "TFLOPs_per_block": round(8 * 32 * (1 << nq) / (per_block / 1e3) / 1e12, 2)}
+        if with_plain:
+            table = sv.OpTable(circ.ops)
+            p = np.ascontiguousarray(circ.params)
+            ms = _timed_ms(lambda: (st.reset(), st.run_ops(table, 0, len(circ.ops), p)), stream)
+            entry["plain_ms"] = round(ms, 2)
+        else:
+            entry["plain_ms"] = round(len(circ.ops) / plain_gates_per_s * 1e3, 2)
+        for name in ("fp32_mfma", "bf16x3"):
+            entry[name]["speedup_vs_plain"] = round(entry["plain_ms"] / entry[name]["ms"], 2)
+        fused[f"brickwork{nq}"] = entry
+        st.free()
+        del st
+        torch.cuda.empty_cache()
+        print(f"# fused {nq}q done", file=sys.stderr, flush=True)
+    res["fused"] = fused
+
+    # -- adjoint backward on the 28-qubit RX/RY + CNOT-ring ansatz
+    circ = C.rxry_ring(28, 10, 5)
+    terms = C.z_sum_terms(28)
+    st = sv.State(28)
+    table = sv.OpTable(circ.ops)
+    p = np.ascontiguousarray(circ.params)
+    fwd_ms = _timed_ms(lambda: (st.reset(), st.run_ops(table, 0, len(circ.ops), p)), stream)
+    t0 = time.perf_counter()
+    loss, grad, drift = st.adjoint_grad(circ, terms)
+    bwd_ms = (time.perf_counter() - t0) * 1e3
+    st.reset()
+    st.run_ops(table, 0, len(circ.ops), p)
+    t0 = time.perf_counter()
+    loss, grad, drift = st.adjoint_grad(circ, terms)
+    bwd_ms = min(bwd_ms, (time.perf_counter() - t0) * 1e3)
+    n_par = circ.n_params
+    shift_ms = 2 * n_par * fwd_ms
+    res["adjoint"] = {
+        "workload": "rxry_ring28: 28 qubits, 10 x [RX all, RY all, CNOT ring], loss <sum Z_i>",
+        "params": n_par, "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
+        "backward_over_forward": round(bwd_ms / fwd_ms, 3),
+        "param_shift_ms_est": round(shift_ms, 1),
+        "speedup_vs_param_shift": round(shift_ms / bwd_ms, 1),
+        "loss": float(loss[0]), "grad_norm": float(np.linalg.norm(grad[0])), "drift": float(drift[0]),
+    }
+    st.free()
+    del st
+    torch.cuda.empty_cache()
+    print("# adjoint done", file=sys.stderr, flush=True)
+
+    # -- batched: 256 uneven circuits in one graph launch vs per-gate launches
+    circs = C.batch_workload(256, 10, 20, 6, 4)
+    plan = sv.BatchPlan(circs)
+    dp = plan.pack()
+    out = plan.out_buffer()
+    plan.launch(dp, out)
+    torch.cuda.synchronize()
+    graph_ms = min(_timed_ms(lambda: plan.launch(dp, out), stream) for _ in range(3))
+    t0 = time.perf_counter()
+    plan.launch(dp, out, pergate=True)
+    torch.cuda.synchronize()
+    pergate_ms = (time.perf_counter() - t0) * 1e3
+    gates = sum(len(c.ops) for c in circs)
+    res["batched"] = {
+        "workload": "256 circuits, n uniform in 10..20, encoded RY inputs + 6 x [RY, RZ, CNOT ladder], all <Z_i>",
+        "gates": gates, "graph_launch_ms": round(graph_ms, 3), "per_gate_launches_ms": round(pergate_ms, 2),
+        "gates_per_s": round(gates / (graph_ms / 1e3), 1),
+        "speedup_vs_per_gate": round(pergate_ms / graph_ms, 2),
+    }
+    plan.free()
+    print("# batched done", file=sys.stderr, flush=True)
+    return res
 
 
 def cpu_baseline(circ, seconds: float) -> dict:

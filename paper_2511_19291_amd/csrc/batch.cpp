@@ -1,0 +1,375 @@
+// batch.cpp -- host side of batched execution: validation, the pass planner
+// that cuts each large circuit into LDS-tile passes, device tables, and the
+// hipGraph that holds the one persistent launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "batch.h"
+#include "sv_internal.h"
+
+struct sv_batch_plan_s {
+    int n_circ = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int> n;
+    std::vector<int64_t> param_off;
+    int64_t n_params_total = 0;
+    std::vector<std::vector<sv_op>> ops;       // host copy for the per-gate form
+    sv::BCirc* d_circ = nullptr;
+    sv::BPass* d_pass = nullptr;
+    sv::BOp* d_ops = nullptr;
+    float2* d_arena = nullptr;
+    int* d_counter = nullptr;
+    int grid = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const double* cap_params = nullptr;
+    double* cap_out = nullptr;
+    float2* pg_arena = nullptr;                 // per-gate form: one full state per circuit
+    std::vector<int64_t> pg_off;
+};
+
+namespace sv {
+
+namespace {
+
+void need(bool ok, sv_status st, const std::string& msg)
+{
+    if (!ok) fail(st, msg);
+}
+
+template <class F>
+sv_status guarded(F&& f)
+{
+    try {
+        f();
+        set_last_error("");
+        return SV_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return SV_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        set_last_error("unexpected error");
+        return SV_ERR_INVALID_ARGUMENT;
+    }
+}
+
+uint64_t op_mask(const sv_op& op)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < op.n_targets; ++j) m |= 1ull << op.targets[j];
+    for (int j = 0; j < op.n_controls; ++j) m |= 1ull << op.controls[j];
+    return m;
+}
+
+struct Pass {
+    std::vector<int> gates;
+    uint64_t tile;
+};
+
+// Cut a gate list into passes whose gates all act inside one tile of
+// kTileBits qubits that always contains qubits 0..kLowBits-1. Scanning in
+// order, a gate joins the pass when its qubits fit and it touches no qubit of
+// a gate already left for a later pass; so gates only move past gates on
+// disjoint qubits and the pass sequence equals the circuit.
+std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops)
+{
+    const uint64_t low = (1ull << kLowBits) - 1;
+    const int room = kTileBits - kLowBits;
+    std::vector<int> remaining(ops.size());
+    std::iota(remaining.begin(), remaining.end(), 0);
+    std::vector<Pass> passes;
+    while (!remaining.empty()) {
+        uint64_t chosen = 0, blocked = 0;
+        Pass p;
+        std::vector<int> rest;
+        for (int g : remaining) {
+            const uint64_t gm = op_mask(ops[g]);
+            if (gm & blocked) {
+                blocked |= gm;
+                rest.push_back(g);
+                continue;
+            }
+            const uint64_t hi = gm & ~low;
+            if (__builtin_popcountll(chosen | hi) <= room) {
+                chosen |= hi;
+                p.gates.push_back(g);
+            } else {
+                blocked |= gm;
+                rest.push_back(g);
+            }
+        }
+        uint64_t tile = low | chosen;
+        for (int q = 0; q < n && __builtin_popcountll(tile) < kTileBits; ++q) tile |= 1ull << q;
+        p.tile = tile;
+        passes.push_back(std::move(p));
+        remaining.swap(rest);
+    }
+    return passes;
+}
+
+template <class T>
+T* upload(const std::vector<T>& v)
+{
+    T* d = nullptr;
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SV_ERR_OUT_OF_MEMORY, "batch table allocation failed");
+    }
+    if (!v.empty()) SV_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+void destroy(sv_batch_plan p)
+{
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->d_circ);
+    (void)hipFree(p->d_pass);
+    (void)hipFree(p->d_ops);
+    (void)hipFree(p->d_arena);
+    (void)hipFree(p->d_counter);
+    (void)hipFree(p->pg_arena);
+    delete p;
+}
+
+BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
+{
+    BatchArgs a{};
+    a.circ = p->d_circ;
+    a.pass = p->d_pass;
+    a.ops = p->d_ops;
+    a.arena = p->d_arena;
+    a.params = params;
+    a.out = out;
+    a.counter = p->d_counter;
+    a.n_circ = p->n_circ;
+    return a;
+}
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op* const* ops, const int* n_ops,
+                               const int* n_params, void* stream, sv_batch_plan* out)
+{
+    sv_batch_plan p = nullptr;
+    const sv_status st = guarded([&] {
+        need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
+        *out = nullptr;
+        need(n_circuits >= 1, SV_ERR_INVALID_ARGUMENT, "need at least one circuit");
+        need(n_qubits && ops && n_ops && n_params, SV_ERR_INVALID_ARGUMENT, "null array");
+        p = new sv_batch_plan_s;
+        p->n_circ = n_circuits;
+        p->stream = static_cast<hipStream_t>(stream);
+        for (int c = 0; c < n_circuits; ++c) {
+            const int n = n_qubits[c];
+            need(n >= 1 && n <= kBatchMaxQubits, SV_ERR_INVALID_ARGUMENT,
+                 "circuit " + std::to_string(c) + ": n_qubits must be 1..24");
+            need(n_ops[c] >= 0 && (n_ops[c] == 0 || ops[c]), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
+            need(n_params[c] >= 0, SV_ERR_INVALID_ARGUMENT, "negative n_params");
+            std::vector<sv_op> v(ops[c], ops[c] + n_ops[c]);
+            for (int i = 0; i < n_ops[c]; ++i) {
+                const sv_op& op = v[i];
+                need(op.kind >= SV_H && op.kind <= SV_RZZ, SV_ERR_UNSUPPORTED,
+                     "circuit " + std::to_string(c) + " op " + std::to_string(i) + ": kind not allowed in a batch");
+                need(op.n_targets == kind_targets(op.kind), SV_ERR_INVALID_ARGUMENT, "n_targets does not match the kind");
+                const sv_status gs = sv_check_gate(n, op.targets, op.n_targets, op.controls, op.n_controls);
+                if (gs != SV_OK) fail(gs, "circuit " + std::to_string(c) + " op " + std::to_string(i) + ": " + sv_last_error());
+                for (int j = 0; j < kind_nparams(op.kind); ++j)
+                    need(op.param[j] >= 0 && op.param[j] < n_params[c], SV_ERR_INVALID_ARGUMENT,
+                         "circuit " + std::to_string(c) + " op " + std::to_string(i) + ": parameter index out of range");
+            }
+            p->n.push_back(n);
+            p->param_off.push_back(p->n_params_total);
+            p->n_params_total += n_params[c];
+            p->ops.push_back(std::move(v));
+        }
+        // largest circuits first (the atomic queue hands them out in this order)
+        std::vector<int> order(n_circuits);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->n[a] > p->n[b]; });
+        std::vector<BCirc> circ;
+        std::vector<BPass> pass;
+        std::vector<BOp> bops;
+        int64_t arena = 0;
+        for (int c : order) {
+            const int n = p->n[c];
+            const std::vector<sv_op>& v = p->ops[c];
+            BCirc bc{};
+            bc.n = n;
+            bc.m = std::min(n, kTileBits);
+            bc.param_off = p->param_off[c];
+            bc.out_idx = c;
+            bc.arena_off = 0;
+            if (n > kTileBits) {
+                bc.arena_off = arena;
+                arena += 1ll << n;
+            }
+            std::vector<Pass> pl;
+            if (n <= kTileBits) {
+                Pass one;
+                one.gates.resize(v.size());
+                std::iota(one.gates.begin(), one.gates.end(), 0);
+                one.tile = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+                pl.push_back(std::move(one));
+            } else {
+                pl = plan_passes(n, v);
+            }
+            bc.pass_begin = (int)pass.size();
+            for (const Pass& ps : pl) {
+                BPass bp{};
+                int local[64];
+                int j = 0;
+                for (int q = 0; q < n; ++q)
+                    if ((ps.tile >> q) & 1) {
+                        local[q] = j;
+                        bp.pos[j++] = q;
+                    }
+                bp.op_begin = (int)bops.size();
+                for (int g : ps.gates) {
+                    const sv_op& op = v[g];
+                    BOp b{};
+                    b.kind = op.kind;
+                    b.nt = op.n_targets;
+                    b.nc = op.n_controls;
+                    for (int t = 0; t < op.n_targets; ++t) b.t[t] = local[op.targets[t]];
+                    for (int t = 0; t < op.n_controls; ++t) b.c[t] = local[op.controls[t]];
+                    for (int t = 0; t < 3; ++t) b.p[t] = t < kind_nparams(op.kind) ? op.param[t] : -1;
+                    bops.push_back(b);
+                }
+                bp.op_end = (int)bops.size();
+                pass.push_back(bp);
+            }
+            bc.pass_end = (int)pass.size();
+            circ.push_back(bc);
+        }
+        p->d_circ = upload(circ);
+        p->d_pass = upload(pass);
+        p->d_ops = upload(bops);
+        if (arena > 0 && hipMalloc(&p->d_arena, (size_t)arena * sizeof(float2)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(SV_ERR_OUT_OF_MEMORY, "batch state arena allocation failed");
+        }
+        SV_HIP(hipMalloc(&p->d_counter, sizeof(int)));
+        p->grid = std::max(1, std::min(n_circuits, device_info().cu_count));
+        *out = p;
+    });
+    if (st != SV_OK) destroy(p);
+    return st;
+}
+
+sv_status sv_batch_param_layout(sv_batch_plan p, int64_t* param_offsets, int64_t* total)
+{
+    return guarded([&] {
+        need(p != nullptr, SV_ERR_INVALID_ARGUMENT, "null plan");
+        if (param_offsets)
+            for (int c = 0; c < p->n_circ; ++c) param_offsets[c] = p->param_off[c];
+        if (total) *total = p->n_params_total;
+    });
+}
+
+sv_status sv_batch_launch(sv_batch_plan p, const double* dev_params, double* dev_out)
+{
+    return guarded([&] {
+        need(p != nullptr, SV_ERR_INVALID_ARGUMENT, "null plan");
+        need(dev_out != nullptr, SV_ERR_INVALID_ARGUMENT, "dev_out is NULL");
+        need(dev_params != nullptr || p->n_params_total == 0, SV_ERR_INVALID_ARGUMENT, "dev_params is NULL");
+        const BatchArgs a = args_of(p, dev_params, dev_out);
+        if (!p->stream) {
+            // the legacy default stream cannot be captured: launch directly
+            launch_batch(a, p->grid, p->stream);
+            return;
+        }
+        if (!p->exec || p->cap_params != dev_params || p->cap_out != dev_out) {
+            if (p->exec) {
+                SV_HIP(hipGraphExecDestroy(p->exec));
+                p->exec = nullptr;
+            }
+            if (p->graph) {
+                SV_HIP(hipGraphDestroy(p->graph));
+                p->graph = nullptr;
+            }
+            SV_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+            try {
+                launch_batch(a, p->grid, p->stream);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(p->stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SV_HIP(hipStreamEndCapture(p->stream, &p->graph));
+            SV_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+            p->cap_params = dev_params;
+            p->cap_out = dev_out;
+        }
+        SV_HIP(hipGraphLaunch(p->exec, p->stream));
+    });
+}
+
+sv_status sv_batch_launch_pergate(sv_batch_plan p, const double* dev_params, double* dev_out)
+{
+    return guarded([&] {
+        need(p != nullptr, SV_ERR_INVALID_ARGUMENT, "null plan");
+        need(dev_out != nullptr, SV_ERR_INVALID_ARGUMENT, "dev_out is NULL");
+        if (!p->pg_arena) {
+            int64_t total = 0;
+            for (int c = 0; c < p->n_circ; ++c) {
+                p->pg_off.push_back(total);
+                total += 1ll << p->n[c];
+            }
+            if (hipMalloc(&p->pg_arena, (size_t)total * sizeof(float2)) != hipSuccess) {
+                (void)hipGetLastError();
+                p->pg_arena = nullptr;
+                fail(SV_ERR_OUT_OF_MEMORY, "per-gate state arena allocation failed");
+            }
+        }
+        std::vector<double> hp((size_t)std::max<int64_t>(p->n_params_total, 1));
+        if (p->n_params_total > 0) {
+            SV_HIP(hipMemcpyAsync(hp.data(), dev_params, (size_t)p->n_params_total * sizeof(double),
+                                  hipMemcpyDeviceToHost, p->stream));
+            SV_HIP(hipStreamSynchronize(p->stream));
+        }
+        std::vector<double> out((size_t)p->n_circ * SV_BATCH_OUT_STRIDE, 0.0);
+        for (int c = 0; c < p->n_circ; ++c) {
+            const int n = p->n[c];
+            sv_state s = nullptr;
+            sv_status st = sv_alloc(n, 1, p->pg_arena + p->pg_off[c], p->stream, &s);
+            if (st != SV_OK) fail(st, sv_last_error());
+            std::vector<double> z(n + 1);
+            st = sv_reset(s, 0);
+            if (st == SV_OK)
+                st = sv_run(s, p->ops[c].data(), (int)p->ops[c].size(), hp.data() + p->param_off[c], 0,
+                            (int)(p->n_params_total - p->param_off[c]));
+            if (st == SV_OK) st = sv_expval_z_all(s, z.data());
+            const std::string err = sv_last_error();
+            sv_free(s);
+            if (st != SV_OK) fail(st, err);
+            for (int i = 0; i < n; ++i) out[(size_t)c * SV_BATCH_OUT_STRIDE + i] = z[i];
+        }
+        SV_HIP(hipMemcpyAsync(dev_out, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+        SV_HIP(hipStreamSynchronize(p->stream));
+    });
+}
+
+sv_status sv_batch_plan_free(sv_batch_plan p)
+{
+    return guarded([&] { destroy(p); });
+}
+
+}  // extern "C"

@@ -297,3 +297,68 @@ def fuse_plan(circuit, max_k: int = 5, params=None) -> List[Tuple[Tuple[int, ...
         m = mats[off: off + 2 * d * d].view(np.complex128).reshape(d, d).copy()
         out.append((tuple(b.targets[j] for j in range(b.k)), m))
     return out
+
+
+class BatchPlan:
+    """Many independent circuits (uneven qubit counts) run by one persistent
+    kernel launch captured in a hipGraph; every circuit starts from |0..0>
+    and yields all <Z_i>."""
+
+    def __init__(self, circuits: Sequence, device=None):
+        import torch
+
+        self.circuits = list(circuits)
+        self.stream = torch.cuda.current_stream(device)
+        self.tables = [OpTable(c.ops) for c in self.circuits]
+        nc = len(self.circuits)
+        nq = _iarr([c.n for c in self.circuits])
+        nops = _iarr([t.n for t in self.tables])
+        npar = _iarr([c.n_params for c in self.circuits])
+        ops_arr = (C.POINTER(SvOp) * nc)(*[C.cast(t.arr, C.POINTER(SvOp)) for t in self.tables])
+        h = C.c_void_p()
+        check(lib().sv_batch_plan_create(nc, nq, ops_arr, nops, npar, C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(h)))
+        self.h = h
+        offs = (C.c_int64 * nc)()
+        total = C.c_int64()
+        check(lib().sv_batch_param_layout(self.h, offs, C.byref(total)))
+        self.offsets = [int(x) for x in offs]
+        self.total = int(total.value)
+
+    def pack(self, params_list=None):
+        """Device FP64 parameter block in the plan's layout."""
+        import torch
+
+        flat = np.zeros(max(self.total, 1), dtype=np.float64)
+        for i, (c, off) in enumerate(zip(self.circuits, self.offsets)):
+            p = c.params if params_list is None else params_list[i]
+            flat[off: off + c.n_params] = p
+        return torch.from_numpy(flat).to(device=self.stream.device)
+
+    def out_buffer(self):
+        import torch
+
+        return torch.zeros((len(self.circuits), BATCH_OUT_STRIDE), dtype=torch.float64, device=self.stream.device)
+
+    def launch(self, dev_params, dev_out, pergate: bool = False) -> None:
+        f = lib().sv_batch_launch_pergate if pergate else lib().sv_batch_launch
+        check(f(self.h, C.c_void_p(dev_params.data_ptr()), C.c_void_p(dev_out.data_ptr())))
+
+    def run(self, params_list=None, pergate: bool = False) -> np.ndarray:
+        dp = self.pack(params_list)
+        out = self.out_buffer()
+        self.launch(dp, out, pergate)
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def free(self) -> None:
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.sv_batch_plan_free(h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
