@@ -89,3 +89,31 @@ def test_batched_per_row_inputs(sv):
         ref = oracle.grad_param_shift(circ, terms, params=P[r])
         _close(g[r], ref)
         assert abs(loss[r] - oracle.loss(circ, terms, P[r])) < 1e-4
+
+
+def test_autograd_function(sv):
+    """torch.autograd through the adjoint backward: loss and gradient
+    against the oracle, for a single row and a batch of rows."""
+    import torch
+
+    from paper_2511_19291_amd.autograd import QuantumExpval
+
+    circ = C.rxry_ring(9, 3, 12)
+    terms = C.z_sum_terms(9) + [C.pauli_term(0.4, "X2 X3")]
+    mod = QuantumExpval(circ, terms)
+    th = torch.tensor(circ.params, dtype=torch.float64, requires_grad=True)
+    loss = mod(th)
+    loss.backward()
+    ref = oracle.grad_param_shift(circ, terms)
+    assert abs(loss.item() - oracle.loss(circ, terms)) < 1e-4
+    _close(th.grad.numpy(), ref)
+
+    B = 3
+    rng = np.random.default_rng(1)
+    P = np.tile(circ.params, (B, 1)) + rng.uniform(-0.3, 0.3, size=(B, circ.n_params))
+    modb = QuantumExpval(circ, terms, batch=B)
+    tb = torch.tensor(P, requires_grad=True)
+    lb = modb(tb)
+    (lb * torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64)).sum().backward()
+    for r, w in enumerate([1.0, -2.0, 0.5]):
+        _close(tb.grad.numpy()[r] / w, oracle.grad_param_shift(circ, terms, params=P[r]))
