@@ -21,8 +21,15 @@ struct sv_batch_plan_s {
     sv::BCirc* d_circ = nullptr;
     sv::BPass* d_pass = nullptr;
     sv::BOp* d_ops = nullptr;
+    sv::BTask* d_tasks = nullptr;
     float2* d_arena = nullptr;
+    float2* d_mats = nullptr;
+    double* d_zpart = nullptr;
     int* d_counter = nullptr;
+    int* d_done = nullptr;
+    int n_tasks = 0;
+    int n_ops = 0;
+    int n_pass = 0;
     int grid = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -137,8 +144,12 @@ void destroy(sv_batch_plan p)
     (void)hipFree(p->d_circ);
     (void)hipFree(p->d_pass);
     (void)hipFree(p->d_ops);
+    (void)hipFree(p->d_tasks);
     (void)hipFree(p->d_arena);
+    (void)hipFree(p->d_mats);
+    (void)hipFree(p->d_zpart);
     (void)hipFree(p->d_counter);
+    (void)hipFree(p->d_done);
     (void)hipFree(p->pg_arena);
     delete p;
 }
@@ -149,11 +160,17 @@ BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
     a.circ = p->d_circ;
     a.pass = p->d_pass;
     a.ops = p->d_ops;
+    a.tasks = p->d_tasks;
+    a.n_tasks = p->n_tasks;
+    a.n_ops = p->n_ops;
+    a.n_pass = p->n_pass;
     a.arena = p->d_arena;
+    a.mats = p->d_mats;
+    a.zpart = p->d_zpart;
     a.params = params;
     a.out = out;
     a.counter = p->d_counter;
-    a.n_circ = p->n_circ;
+    a.done = p->d_done;
     return a;
 }
 
@@ -206,26 +223,29 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
         std::vector<BCirc> circ;
         std::vector<BPass> pass;
         std::vector<BOp> bops;
-        int64_t arena = 0;
+        int64_t arena = 0, zrows = 0;
         for (int c : order) {
             const int n = p->n[c];
             const std::vector<sv_op>& v = p->ops[c];
             BCirc bc{};
             bc.n = n;
             bc.m = std::min(n, kTileBits);
-            bc.param_off = p->param_off[c];
+            bc.ntiles = 1 << (n - bc.m);
             bc.out_idx = c;
             bc.arena_off = 0;
+            bc.zpart_off = 0;
             if (n > kTileBits) {
                 bc.arena_off = arena;
                 arena += 1ll << n;
+                bc.zpart_off = zrows;
+                zrows += bc.ntiles;
             }
             std::vector<Pass> pl;
             if (n <= kTileBits) {
                 Pass one;
                 one.gates.resize(v.size());
                 std::iota(one.gates.begin(), one.gates.end(), 0);
-                one.tile = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+                one.tile = (1ull << n) - 1;
                 pl.push_back(std::move(one));
             } else {
                 pl = plan_passes(n, v);
@@ -246,10 +266,22 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
                     BOp b{};
                     b.kind = op.kind;
                     b.nt = op.n_targets;
-                    b.nc = op.n_controls;
-                    for (int t = 0; t < op.n_targets; ++t) b.t[t] = local[op.targets[t]];
-                    for (int t = 0; t < op.n_controls; ++t) b.c[t] = local[op.controls[t]];
-                    for (int t = 0; t < 3; ++t) b.p[t] = t < kind_nparams(op.kind) ? op.param[t] : -1;
+                    b.np = 0;
+                    for (int t = 0; t < op.n_targets; ++t) b.pos[b.np++] = local[op.targets[t]];
+                    for (int t = 0; t < op.n_controls; ++t) {
+                        b.pos[b.np++] = local[op.controls[t]];
+                        b.cmask |= 1u << local[op.controls[t]];
+                    }
+                    std::sort(b.pos, b.pos + b.np);
+                    const int D = 1 << b.nt;
+                    for (int r = 0; r < D; ++r) {
+                        uint32_t off = 0;
+                        for (int t = 0; t < b.nt; ++t)
+                            if ((r >> (b.nt - 1 - t)) & 1) off |= 1u << local[op.targets[t]];
+                        b.off[r] = off;
+                    }
+                    for (int t = 0; t < 3; ++t)
+                        b.p[t] = t < kind_nparams(op.kind) ? (int)(p->param_off[c] + op.param[t]) : -1;
                     bops.push_back(b);
                 }
                 bp.op_end = (int)bops.size();
@@ -258,15 +290,42 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
             bc.pass_end = (int)pass.size();
             circ.push_back(bc);
         }
+        need(p->n_params_total < (1ll << 31) && bops.size() < (1u << 31), SV_ERR_UNSUPPORTED, "batch too large");
+        // tasks: round r = pass r of every circuit that has one (largest first),
+        // all its tiles; the single-task small circuits follow round 0's large ones
+        std::vector<BTask> tasks;
+        int max_pass = 0;
+        for (const BCirc& bc : circ) max_pass = std::max(max_pass, bc.pass_end - bc.pass_begin);
+        for (int r = 0; r < max_pass; ++r) {
+            for (int ci = 0; ci < (int)circ.size(); ++ci) {
+                const BCirc& bc = circ[ci];
+                if (bc.n <= kTileBits || r >= bc.pass_end - bc.pass_begin) continue;
+                for (int t = 0; t < bc.ntiles; ++t) tasks.push_back(BTask{ci, bc.pass_begin + r, t, 0});
+            }
+            if (r == 0)
+                for (int ci = 0; ci < (int)circ.size(); ++ci)
+                    if (circ[ci].n <= kTileBits) tasks.push_back(BTask{ci, circ[ci].pass_begin, 0, 0});
+        }
+        p->n_tasks = (int)tasks.size();
+        p->n_ops = (int)bops.size();
+        p->n_pass = (int)pass.size();
         p->d_circ = upload(circ);
         p->d_pass = upload(pass);
         p->d_ops = upload(bops);
-        if (arena > 0 && hipMalloc(&p->d_arena, (size_t)arena * sizeof(float2)) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(SV_ERR_OUT_OF_MEMORY, "batch state arena allocation failed");
-        }
-        SV_HIP(hipMalloc(&p->d_counter, sizeof(int)));
-        p->grid = std::max(1, std::min(n_circuits, device_info().cu_count));
+        p->d_tasks = upload(tasks);
+        auto dev_alloc = [&](void** ptr, size_t bytes, const char* what) {
+            if (hipMalloc(ptr, std::max<size_t>(bytes, 16)) != hipSuccess) {
+                (void)hipGetLastError();
+                *ptr = nullptr;
+                fail(SV_ERR_OUT_OF_MEMORY, std::string("batch ") + what + " allocation failed");
+            }
+        };
+        if (arena > 0) dev_alloc((void**)&p->d_arena, (size_t)arena * sizeof(float2), "state arena");
+        dev_alloc((void**)&p->d_mats, (size_t)p->n_ops * kMatStride * sizeof(float2), "matrix table");
+        dev_alloc((void**)&p->d_zpart, (size_t)zrows * (kBatchMaxQubits + 1) * sizeof(double), "partials");
+        dev_alloc((void**)&p->d_done, (size_t)p->n_pass * sizeof(int), "pass counters");
+        dev_alloc((void**)&p->d_counter, sizeof(int), "queue counter");
+        p->grid = std::max(1, std::min(p->n_tasks, device_info().cu_count));
         *out = p;
     });
     if (st != SV_OK) destroy(p);

@@ -11,16 +11,17 @@ namespace sv {
 constexpr int kTileBits = 14;         // LDS tile: 2^14 complex64 = 128 KiB
 constexpr int kLowBits = 6;           // qubits 0..5 are in every tile (runs of 64 amplitudes)
 constexpr int kBatchMaxQubits = 24;
+constexpr int kMatStride = 16;        // complex64 entries reserved per gate matrix
 
-// One gate with tile-local qubit positions.
+// One gate with tile-local qubit positions and its precomputed addressing.
 struct BOp {
     int kind;
-    int nt;
-    int nc;
-    int t[2];
-    int c[3];
-    int p[3];                         // parameter indices in the circuit's row, -1 = none
-    int pad;
+    int nt;                           // 1 or 2 targets
+    int np;                           // number of positions where zeros are inserted
+    int pos[5];                       // tile-local targets and controls, ascending
+    uint32_t cmask;                   // tile-local control bits
+    uint32_t off[4];                  // member offsets (target bits by member index)
+    int p[3];                         // absolute parameter indices in the launch's block, -1 = none
 };
 
 // A pass: gates [op_begin, op_end) all act inside the tile whose bit j is
@@ -36,9 +37,19 @@ struct BCirc {
     int m;                            // tile bits: min(n, kTileBits)
     int pass_begin;
     int pass_end;
-    int64_t param_off;                // first parameter in the launch's parameter block
     int64_t arena_off;                // amplitude offset of the state in the arena (n > kTileBits)
+    int64_t zpart_off;                // first row of this circuit's per-tile <Z> partials
+    int ntiles;                       // 2^(n - m)
     int out_idx;                      // row of the output
+};
+
+// A unit of work: one tile of one pass of one circuit. Tasks are ordered so
+// that every tile of a pass precedes every tile of the next pass of the same
+// circuit: a task only ever waits for tasks handed out before it.
+struct BTask {
+    int circ;
+    int pass;
+    int tile;
     int pad;
 };
 
@@ -46,11 +57,17 @@ struct BatchArgs {
     const BCirc* circ;
     const BPass* pass;
     const BOp* ops;
+    const BTask* tasks;
+    int n_tasks;
+    int n_ops;
+    int n_pass;
     float2* arena;
+    float2* mats;                     // n_ops * kMatStride complex64
+    double* zpart;                    // per-tile partials [row][kBatchMaxQubits + 1]
     const double* params;
     double* out;
-    int* counter;
-    int n_circ;
+    int* counter;                     // next task
+    int* done;                        // finished tiles per pass
 };
 
 void launch_batch(const BatchArgs& a, int grid, hipStream_t st);
