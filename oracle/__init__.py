@@ -6,3 +6,4 @@ seeded circuits (plain data) and computes everything else on its own.
 """
 
 from .oracle import *  # noqa: F401,F403
+from .oracle import using_library  # noqa: F401

@@ -34,7 +34,12 @@ def load() -> C.CDLL:
         return _LIB
     if not os.path.exists(_build.LIB):
         _build.build()
-    lib = C.CDLL(_build.LIB)
+    _LIB = bind(C.CDLL(_build.LIB))
+    return _LIB
+
+
+def bind(lib: C.CDLL) -> C.CDLL:
+    """Declare the C signatures on a loaded oracle library."""
     dp = C.POINTER(C.c_double)
     ip = C.POINTER(C.c_int)
     lib.orc_gate_matrix.argtypes = [C.c_char_p, dp, dp]
@@ -56,8 +61,26 @@ def load() -> C.CDLL:
     u64p = C.POINTER(C.c_uint64)
     lib.orc_apply_pauli_sum.argtypes = [dp, C.c_int, C.c_int, u64p, u64p, dp, dp]
     lib.orc_apply_pauli_sum.restype = None
-    _LIB = lib
     return lib
+
+
+class using_library:
+    """Context manager: run the oracle functions on another build of
+    sv_oracle.c (the mutation tests plant mistakes in a copy)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _LIB
+        self.saved = load()
+        _LIB = bind(C.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _LIB
+        _LIB = self.saved
+        return False
 
 
 def _dptr(a: np.ndarray):

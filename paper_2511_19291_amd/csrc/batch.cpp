@@ -22,6 +22,7 @@ struct sv_batch_plan_s {
     sv::BPass* d_pass = nullptr;
     sv::BOp* d_ops = nullptr;
     sv::BTask* d_tasks = nullptr;
+    sv::BPhase* d_phases = nullptr;
     float2* d_arena = nullptr;
     float2* d_mats = nullptr;
     double* d_zpart = nullptr;
@@ -121,6 +122,54 @@ std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops)
     return passes;
 }
 
+// Cut the gates of one pass (tile-local masks, in pass order) into register
+// phases of four qubits, with the same in-order rule as the passes: a gate
+// joins the phase when its qubits fit and it touches no qubit of a gate left
+// for a later phase. A gate on more than four qubits is a phase of its own
+// (run as one LDS sweep, marked by g[0] = -1). Returns the gate order and
+// fills the phases (op ranges relative to the pass).
+std::vector<int> plan_phases(const std::vector<uint32_t>& masks, int m, std::vector<BPhase>& phases)
+{
+    std::vector<int> order, remaining(masks.size());
+    std::iota(remaining.begin(), remaining.end(), 0);
+    while (!remaining.empty()) {
+        uint32_t chosen = 0, blocked = 0;
+        std::vector<int> take, rest;
+        if (__builtin_popcount(masks[remaining[0]]) > kRegBits) {
+            take.push_back(remaining[0]);
+            rest.assign(remaining.begin() + 1, remaining.end());
+            BPhase ph{};
+            ph.op_begin = (int)order.size();
+            ph.op_end = ph.op_begin + 1;
+            ph.g[0] = -1;
+            phases.push_back(ph);
+            order.push_back(take[0]);
+            remaining.swap(rest);
+            continue;
+        }
+        for (int g : remaining) {
+            const uint32_t q = masks[g];
+            if ((q & blocked) || __builtin_popcount(chosen | q) > kRegBits) {
+                blocked |= q;
+                rest.push_back(g);
+                continue;
+            }
+            chosen |= q;
+            take.push_back(g);
+        }
+        for (int b = 0; b < m && __builtin_popcount(chosen) < kRegBits; ++b) chosen |= 1u << b;
+        BPhase ph{};
+        ph.op_begin = (int)order.size();
+        ph.op_end = ph.op_begin + (int)take.size();
+        for (int b = 0, i = 0; b < m; ++b)
+            if ((chosen >> b) & 1) ph.g[i++] = b;
+        phases.push_back(ph);
+        order.insert(order.end(), take.begin(), take.end());
+        remaining.swap(rest);
+    }
+    return order;
+}
+
 template <class T>
 T* upload(const std::vector<T>& v)
 {
@@ -145,6 +194,7 @@ void destroy(sv_batch_plan p)
     (void)hipFree(p->d_pass);
     (void)hipFree(p->d_ops);
     (void)hipFree(p->d_tasks);
+    (void)hipFree(p->d_phases);
     (void)hipFree(p->d_arena);
     (void)hipFree(p->d_mats);
     (void)hipFree(p->d_zpart);
@@ -161,6 +211,7 @@ BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
     a.pass = p->d_pass;
     a.ops = p->d_ops;
     a.tasks = p->d_tasks;
+    a.phases = p->d_phases;
     a.n_tasks = p->n_tasks;
     a.n_ops = p->n_ops;
     a.n_pass = p->n_pass;
@@ -223,6 +274,7 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
         std::vector<BCirc> circ;
         std::vector<BPass> pass;
         std::vector<BOp> bops;
+        std::vector<BPhase> phase;
         int64_t arena = 0, zrows = 0;
         for (int c : order) {
             const int n = p->n[c];
@@ -261,16 +313,23 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
                         bp.pos[j++] = q;
                     }
                 bp.op_begin = (int)bops.size();
+                std::vector<BOp> pops;
+                std::vector<uint32_t> masks;
                 for (int g : ps.gates) {
                     const sv_op& op = v[g];
                     BOp b{};
                     b.kind = op.kind;
                     b.nt = op.n_targets;
                     b.np = 0;
-                    for (int t = 0; t < op.n_targets; ++t) b.pos[b.np++] = local[op.targets[t]];
+                    uint32_t mask = 0;
+                    for (int t = 0; t < op.n_targets; ++t) {
+                        b.pos[b.np++] = local[op.targets[t]];
+                        mask |= 1u << local[op.targets[t]];
+                    }
                     for (int t = 0; t < op.n_controls; ++t) {
                         b.pos[b.np++] = local[op.controls[t]];
                         b.cmask |= 1u << local[op.controls[t]];
+                        mask |= 1u << local[op.controls[t]];
                     }
                     std::sort(b.pos, b.pos + b.np);
                     const int D = 1 << b.nt;
@@ -282,7 +341,35 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
                     }
                     for (int t = 0; t < 3; ++t)
                         b.p[t] = t < kind_nparams(op.kind) ? (int)(p->param_off[c] + op.param[t]) : -1;
-                    bops.push_back(b);
+                    pops.push_back(b);
+                    masks.push_back(mask);
+                }
+                bp.phase_begin = bp.phase_end = (int)phase.size();
+                if (bc.m >= kRegMinTile) {
+                    std::vector<BPhase> ph;
+                    const std::vector<int> order = plan_phases(masks, bc.m, ph);
+                    for (BPhase& x : ph) {
+                        // register positions of each gate's qubits inside the phase
+                        for (int oi = x.op_begin; oi < x.op_end && x.g[0] >= 0; ++oi) {
+                            BOp& b = pops[order[oi]];
+                            auto rpos = [&](int tilebit) {
+                                for (int i = 0; i < kRegBits; ++i)
+                                    if (x.g[i] == tilebit) return i;
+                                return -1;
+                            };
+                            for (int t = 0; t < b.nt; ++t) b.rt[t] = rpos(__builtin_ctz(b.off[b.nt == 1 ? 1 : (t == 0 ? 2 : 1)]));
+                            b.rcmask = 0;
+                            for (int q = 0; q < 32; ++q)
+                                if ((b.cmask >> q) & 1) b.rcmask |= 1 << rpos(q);
+                        }
+                        x.op_begin += (int)bops.size();
+                        x.op_end += (int)bops.size();
+                        phase.push_back(x);
+                    }
+                    bp.phase_end = (int)phase.size();
+                    for (int oi : order) bops.push_back(pops[oi]);
+                } else {
+                    bops.insert(bops.end(), pops.begin(), pops.end());
                 }
                 bp.op_end = (int)bops.size();
                 pass.push_back(bp);
@@ -313,6 +400,7 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
         p->d_pass = upload(pass);
         p->d_ops = upload(bops);
         p->d_tasks = upload(tasks);
+        p->d_phases = upload(phase);
         auto dev_alloc = [&](void** ptr, size_t bytes, const char* what) {
             if (hipMalloc(ptr, std::max<size_t>(bytes, 16)) != hipSuccess) {
                 (void)hipGetLastError();

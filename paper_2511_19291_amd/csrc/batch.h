@@ -13,6 +13,9 @@ constexpr int kLowBits = 6;           // qubits 0..5 are in every tile (runs of 
 constexpr int kBatchMaxQubits = 24;
 constexpr int kMatStride = 16;        // complex64 entries reserved per gate matrix
 
+constexpr int kRegBits = 4;           // register blocking: 16 amplitudes per thread
+constexpr int kRegMinTile = 12;       // tiles of >= 2^12 amplitudes use register phases
+
 // One gate with tile-local qubit positions and its precomputed addressing.
 struct BOp {
     int kind;
@@ -22,13 +25,27 @@ struct BOp {
     uint32_t cmask;                   // tile-local control bits
     uint32_t off[4];                  // member offsets (target bits by member index)
     int p[3];                         // absolute parameter indices in the launch's block, -1 = none
+    int rt[2];                        // register phase: target bits within the phase's 4 qubits
+    int rcmask;                       // register phase: control bits within the phase's 4 qubits
+};
+
+// A register phase: gates [op_begin, op_end) all act inside the four
+// tile-local qubits g[0..3]; each thread holds the 16 amplitudes that differ
+// only in those qubits and applies the gates in registers.
+struct BPhase {
+    int op_begin;
+    int op_end;
+    int g[kRegBits];
 };
 
 // A pass: gates [op_begin, op_end) all act inside the tile whose bit j is
-// qubit pos[j] (ascending).
+// qubit pos[j] (ascending). Tiles of >= 2^12 amplitudes run the gates as the
+// register phases [phase_begin, phase_end) instead of one by one.
 struct BPass {
     int op_begin;
     int op_end;
+    int phase_begin;
+    int phase_end;
     int pos[kTileBits];
 };
 
@@ -58,6 +75,7 @@ struct BatchArgs {
     const BPass* pass;
     const BOp* ops;
     const BTask* tasks;
+    const BPhase* phases;
     int n_tasks;
     int n_ops;
     int n_pass;

@@ -70,53 +70,99 @@ __device__ __forceinline__ void adj_group(const KAdj& a, const float2 (&x)[D], c
     }
 }
 
-// VEC = 2: float4 accesses (two neighbouring amplitudes per member; every
-// target/control >= 1). VEC = 1: float2 accesses. Fixed grid with a
-// grid-stride loop so each block's share (and the summation order) is fixed.
-template <int K, int VEC>
+// Forms (as for the plain sweeps): VEC2 = float4 members (no target/control
+// on qubit 0), PAIR = one target at qubit 0 with the pair inside a float4,
+// VEC1 = float2 members. Fixed grid with a grid-stride loop so each block's
+// share (and the summation order) is fixed; two units per iteration for
+// memory-level parallelism. NT = streaming accesses (whole lines written).
+template <int K, int F, bool NT>
 __global__ __launch_bounds__(kBlock) void k_adj(KAdj a, double* part)
 {
     constexpr int D = 1 << K;
+    constexpr int U = 2;
     const int row = blockIdx.y;
     float2* psi = mrow(a.psi, row);
     float2* lam = mrow(a.lam, row);
     double acc[3] = {0.0, 0.0, 0.0};
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t u = (uint64_t)blockIdx.x * kBlock + threadIdx.x; u < a.n_units; u += stride) {
-        if constexpr (VEC == 2) {
-            const uint64_t base = insert_zeros(u << 1, a.pos, a.npos) | a.cmask;
-            float4 vx[D], vl[D];
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * U;
+    const uint64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    for (uint64_t u0 = blk * kBlock * U + threadIdx.x; u0 < a.n_units; u0 += stride) {
+        if constexpr (F == 2) {
+            float4 vx[U][D], vl[U][D];
+            uint64_t base[U];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                vx[j] = *reinterpret_cast<const float4*>(psi + (base | a.moff[j]));
-                vl[j] = *reinterpret_cast<const float4*>(lam + (base | a.moff[j]));
+            for (int r = 0; r < U; ++r) {
+                const uint64_t u = u0 + (uint64_t)r * kBlock;
+                base[r] = insert_zeros(u << 1, a.pos, a.npos) | a.cmask;
+                if (u < a.n_units)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        vx[r][j] = ld4<NT>(psi + (base[r] | a.moff[j]));
+                        vl[r][j] = ld4<NT>(lam + (base[r] | a.moff[j]));
+                    }
             }
-            float2 x0[D], l0[D], x1[D], l1[D], xo0[D], lo0[D], xo1[D], lo1[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                x0[j] = lo2(vx[j]); x1[j] = hi2(vx[j]);
-                l0[j] = lo2(vl[j]); l1[j] = hi2(vl[j]);
+            for (int r = 0; r < U; ++r) {
+                if (u0 + (uint64_t)r * kBlock >= a.n_units) continue;
+                float2 x0[D], l0[D], x1[D], l1[D], xo0[D], lo0[D], xo1[D], lo1[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    x0[j] = lo2(vx[r][j]); x1[j] = hi2(vx[r][j]);
+                    l0[j] = lo2(vl[r][j]); l1[j] = hi2(vl[r][j]);
+                }
+                adj_group<D>(a, x0, l0, xo0, lo0, acc);
+                adj_group<D>(a, x1, l1, xo1, lo1, acc);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    st4<NT>(psi + (base[r] | a.moff[j]), pack4(xo0[j], xo1[j]));
+                    st4<NT>(lam + (base[r] | a.moff[j]), pack4(lo0[j], lo1[j]));
+                }
             }
-            adj_group<D>(a, x0, l0, xo0, lo0, acc);
-            adj_group<D>(a, x1, l1, xo1, lo1, acc);
+        } else if constexpr (F == 0) {
+            static_assert(K == 1, "pair form is for one target");
+            float4 vx[U], vl[U];
+            uint64_t base[U];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                *reinterpret_cast<float4*>(psi + (base | a.moff[j])) = pack4(xo0[j], xo1[j]);
-                *reinterpret_cast<float4*>(lam + (base | a.moff[j])) = pack4(lo0[j], lo1[j]);
+            for (int r = 0; r < U; ++r) {
+                const uint64_t u = u0 + (uint64_t)r * kBlock;
+                base[r] = insert_zeros(u, a.pos, a.npos) | a.cmask;
+                if (u < a.n_units) {
+                    vx[r] = ld4<NT>(psi + base[r]);
+                    vl[r] = ld4<NT>(lam + base[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                if (u0 + (uint64_t)r * kBlock >= a.n_units) continue;
+                float2 x[2] = {lo2(vx[r]), hi2(vx[r])}, l[2] = {lo2(vl[r]), hi2(vl[r])}, xo[2], lo[2];
+                adj_group<2>(a, x, l, xo, lo, acc);
+                st4<NT>(psi + base[r], pack4(xo[0], xo[1]));
+                st4<NT>(lam + base[r], pack4(lo[0], lo[1]));
             }
         } else {
-            const uint64_t base = insert_zeros(u, a.pos, a.npos) | a.cmask;
-            float2 x[D], l[D], xo[D], lo[D];
+            float2 x[U][D], l[U][D];
+            uint64_t base[U];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                x[j] = psi[base | a.moff[j]];
-                l[j] = lam[base | a.moff[j]];
+            for (int r = 0; r < U; ++r) {
+                const uint64_t u = u0 + (uint64_t)r * kBlock;
+                base[r] = insert_zeros(u, a.pos, a.npos) | a.cmask;
+                if (u < a.n_units)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        x[r][j] = ld2<NT>(psi + (base[r] | a.moff[j]));
+                        l[r][j] = ld2<NT>(lam + (base[r] | a.moff[j]));
+                    }
             }
-            adj_group<D>(a, x, l, xo, lo, acc);
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                psi[base | a.moff[j]] = xo[j];
-                lam[base | a.moff[j]] = lo[j];
+            for (int r = 0; r < U; ++r) {
+                if (u0 + (uint64_t)r * kBlock >= a.n_units) continue;
+                float2 xo[D], lo[D];
+                adj_group<D>(a, x[r], l[r], xo, lo, acc);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    st2<NT>(psi + (base[r] | a.moff[j]), xo[j]);
+                    st2<NT>(lam + (base[r] | a.moff[j]), lo[j]);
+                }
             }
         }
     }
@@ -192,16 +238,24 @@ void launch_adj_step(const AdjLaunch& g, double* part, hipStream_t st)
     for (int i = 1; i < a.npos; ++i)
         for (int j = i; j > 0 && a.pos[j - 1] > a.pos[j]; --j) std::swap(a.pos[j - 1], a.pos[j]);
     const uint64_t groups = 1ull << (n - g.k - g.nc);
-    const int grid = adj_grid(n, g.k, g.nc);
-    const dim3 gd(grid, g.psi.nrows);
+    // every step of one backward uses the same grid: the partial-sum slots
+    // are laid out with that stride
+    const dim3 gd(g.grid, g.psi.nrows);
+    const bool nt = a.pos[0] >= kFullLineQubit;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, gd, dim3(kBlock), 0, st, a, part); };
     if (lowest >= 1 && groups >= 2) {
         a.n_units = groups >> 1;
-        if (g.k == 1) hipLaunchKernelGGL((k_adj<1, 2>), gd, dim3(kBlock), 0, st, a, part);
-        else hipLaunchKernelGGL((k_adj<2, 2>), gd, dim3(kBlock), 0, st, a, part);
+        if (g.k == 1) nt ? go(k_adj<1, 2, true>) : go(k_adj<1, 2, false>);
+        else nt ? go(k_adj<2, 2, true>) : go(k_adj<2, 2, false>);
+    } else if (g.k == 1 && g.targets[0] == 0) {
+        // pair (b, b|1) in one float4; lines are whole unless a control splits them
+        a.n_units = groups;
+        const bool nt_pair = a.npos < 2 || a.pos[1] >= kFullLineQubit;
+        nt_pair ? go(k_adj<1, 0, true>) : go(k_adj<1, 0, false>);
     } else {
         a.n_units = groups;
-        if (g.k == 1) hipLaunchKernelGGL((k_adj<1, 1>), gd, dim3(kBlock), 0, st, a, part);
-        else hipLaunchKernelGGL((k_adj<2, 1>), gd, dim3(kBlock), 0, st, a, part);
+        if (g.k == 1) go(k_adj<1, 1, false>);
+        else go(k_adj<2, 1, false>);
     }
     SV_HIP(hipGetLastError());
 }

@@ -161,6 +161,127 @@ __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, c
     }
 }
 
+// ---------------------------------------------------------- register phases
+//
+// Thread t (t < 2^(m-4)) holds the 16 amplitudes whose tile index has the
+// bits of t on the phase's complement positions and every combination j on
+// its four qubits g[0..3] (bit i of j <-> qubit g[i]). Gates of the phase act
+// on those four qubits only, so they run in registers; the tile goes through
+// LDS once per phase instead of once per gate.
+
+template <int P>
+__device__ __forceinline__ void rg1(float2 (&v)[16], const float2* __restrict__ mat, int cm)
+{
+    const float2 m0 = mat[0], m1 = mat[1], m2 = mat[2], m3 = mat[3];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & (1 << P)) continue;
+        if ((j & cm) != cm) continue;
+        const int j1 = j | (1 << P);
+        const float2 x0 = v[j], x1 = v[j1];
+        v[j] = cfma(m1, x1, cmul(m0, x0));
+        v[j1] = cfma(m3, x1, cmul(m2, x0));
+    }
+}
+
+// two targets: P0 is the most significant bit of the 4x4 matrix index
+template <int P0, int P1>
+__device__ __forceinline__ void rg2(float2 (&v)[16], const float2* __restrict__ mat, int cm)
+{
+    float2 mm[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) mm[q] = mat[q];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & ((1 << P0) | (1 << P1))) continue;
+        if ((j & cm) != cm) continue;
+        const int o[4] = {j, j | (1 << P1), j | (1 << P0), j | (1 << P0) | (1 << P1)};
+        float2 x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = v[o[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float2 acc = cmul(mm[r * 4], x[0]);
+#pragma unroll
+            for (int c = 1; c < 4; ++c) acc = cfma(mm[r * 4 + c], x[c], acc);
+            v[o[r]] = acc;
+        }
+    }
+}
+
+__device__ __forceinline__ void reg_gate(float2 (&v)[16], const BOp& op, const float2* __restrict__ mat)
+{
+    if (op.nt == 1) {
+        switch (op.rt[0]) {
+        case 0: rg1<0>(v, mat, op.rcmask); break;
+        case 1: rg1<1>(v, mat, op.rcmask); break;
+        case 2: rg1<2>(v, mat, op.rcmask); break;
+        default: rg1<3>(v, mat, op.rcmask); break;
+        }
+        return;
+    }
+    switch (op.rt[0] * 4 + op.rt[1]) {
+    case 1: rg2<0, 1>(v, mat, op.rcmask); break;
+    case 2: rg2<0, 2>(v, mat, op.rcmask); break;
+    case 3: rg2<0, 3>(v, mat, op.rcmask); break;
+    case 4: rg2<1, 0>(v, mat, op.rcmask); break;
+    case 6: rg2<1, 2>(v, mat, op.rcmask); break;
+    case 7: rg2<1, 3>(v, mat, op.rcmask); break;
+    case 8: rg2<2, 0>(v, mat, op.rcmask); break;
+    case 9: rg2<2, 1>(v, mat, op.rcmask); break;
+    case 11: rg2<2, 3>(v, mat, op.rcmask); break;
+    case 12: rg2<3, 0>(v, mat, op.rcmask); break;
+    case 13: rg2<3, 1>(v, mat, op.rcmask); break;
+    default: rg2<3, 2>(v, mat, op.rcmask); break;
+    }
+}
+
+// One pass on the tile in LDS as register phases (m >= 12).
+__device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs& a)
+{
+    const bool active = threadIdx.x < (1u << (m - kRegBits));
+    for (int hi = ps.phase_begin; hi < ps.phase_end; ++hi) {
+        const BPhase ph = a.phases[hi];
+        if (ph.g[0] < 0) {
+            // a gate on more than four qubits: one LDS sweep
+            for (int oi = ph.op_begin; oi < ph.op_end; ++oi) {
+                lds_gate(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
+                __syncthreads();
+            }
+            continue;
+        }
+        uint32_t gmask = 0;
+#pragma unroll
+        for (int i = 0; i < kRegBits; ++i) gmask |= 1u << ph.g[i];
+        // deposit the thread index on the complement positions
+        uint32_t base = 0;
+        for (int b = 0, k = 0; b < m; ++b) {
+            if ((gmask >> b) & 1) continue;
+            if ((threadIdx.x >> k) & 1) base |= 1u << b;
+            ++k;
+        }
+        float2 v[16];
+        uint32_t off[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            uint32_t o = base;
+#pragma unroll
+            for (int i = 0; i < kRegBits; ++i)
+                if ((j >> i) & 1) o |= 1u << ph.g[i];
+            off[j] = o;
+        }
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = tile[off[j]];
+            for (int oi = ph.op_begin; oi < ph.op_end; ++oi) reg_gate(v, a.ops[oi], a.mats + (size_t)oi * kMatStride);
+            // each thread writes back exactly the amplitudes it read
+#pragma unroll
+            for (int j = 0; j < 16; ++j) tile[off[j]] = v[j];
+        }
+        __syncthreads();
+    }
+}
+
 // offset of tile-local index l = threadIdx.x + 1024 j inside the state
 __device__ __forceinline__ uint64_t tile_off(const BPass& ps, int m, uint64_t off_t, uint32_t j)
 {
@@ -228,9 +349,13 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
             else tile[l] = ld2<false>(a.arena + c.arena_off + base + tile_off(ps, m, off_t, j));
         }
         __syncthreads();
-        for (int oi = ps.op_begin; oi < ps.op_end; ++oi) {
-            lds_gate(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
-            __syncthreads();
+        if (m >= kRegMinTile) {
+            run_phases(tile, m, ps, a);
+        } else {
+            for (int oi = ps.op_begin; oi < ps.op_end; ++oi) {
+                lds_gate(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
+                __syncthreads();
+            }
         }
         if (last) {
             double zs[kZ];

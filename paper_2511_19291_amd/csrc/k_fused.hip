@@ -204,6 +204,246 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
     }
 }
 
+// Direct form for blocks whose five targets are all >= 5 (then the columns are
+// qubits 0..4, so every row of a tile is 32 consecutive amplitudes, 256 B):
+// each lane loads the matrix-core operands straight from memory and stores
+// its accumulators straight back -- no LDS staging. Lane (h, c) of the
+// 32x32x2 FP32 operand layout needs X~[2s + h][c]: amplitude (row 2s + h,
+// column c) gives the real part for k-step s and the imaginary part for
+// k-step s + 16. For the 32x32x16 BF16 layout lane (h, c) needs rows
+// 8h + q and 16 + 8h + q (q < 8). Accumulator q of lane (h, c) is output row
+// 8 (q / 4) + 4 h + q % 4, column c. Offsets fit 32 bits (n <= 32).
+struct KFusedDirect {
+    float2* psi;
+    uint64_t N;
+    uint64_t n_tiles;
+    int pos[10];               // tile bits ascending: 0..4 and the targets
+    uint32_t toff[5];          // 1 << target j (T[0] = most significant row bit)
+    const float* amat;
+};
+
+__device__ __forceinline__ uint32_t row_off(const KFusedDirect& a, int r)
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+        if ((r >> (4 - j)) & 1) o += a.toff[j];
+    return o;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_fused_direct(KFusedDirect a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5, c32 = lane & 31;
+    float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+
+    uint32_t ro_in[16], ro_out[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int r = MODE == 0 ? 2 * s + h : (s < 8 ? 8 * h + s : 16 + 8 * h + (s - 8));
+        ro_in[s] = row_off(a, r) + c32;
+        ro_out[s] = row_off(a, 8 * (s >> 2) + 4 * h + (s & 3)) + c32;
+    }
+    float afr[2][32];
+    bf16x8 ahi[2][4], alo[2][4];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 32; ++s) afr[b][s] = a.amat[(32 * b + c32) * 64 + 2 * s + h];
+    } else {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float th[8], tl[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    th[q] = a.amat[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    tl[q] = a.amat[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                }
+                ahi[b][s] = to_bf16(th);
+                alo[b][s] = to_bf16(tl);
+            }
+    }
+    // tiles of this wave: w, w + W, w + 2W, ... (W waves in the grid); the
+    // next tile's operands are loaded before this tile's products start, so
+    // the load latency hides behind the matrix-core work
+    const uint64_t waves_total = (uint64_t)gridDim.x * 4;
+    uint64_t tile = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+    float2 x[16];
+    if (tile < a.n_tiles) {
+        const float2* tp = psi + insert_zeros(tile, a.pos, 10);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) x[s] = ld2(tp + ro_in[s]);
+    }
+    for (; tile < a.n_tiles; tile += waves_total) {
+        float2* tp = psi + insert_zeros(tile, a.pos, 10);
+        const uint64_t next = tile + waves_total;
+        float2 xn[16];
+        if (next < a.n_tiles) {
+            const float2* np_ = psi + insert_zeros(next, a.pos, 10);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) xn[s] = ld2(np_ + ro_in[s]);
+        }
+        f32x16 acc0 = {0}, acc1 = {0};
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][s], x[s].x, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][s], x[s].x, acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][16 + s], x[s].y, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][16 + s], x[s].y, acc1, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float xh[8], xl[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) xh[q] = (s & 1) ? (s < 2 ? x[8 + q].x : x[8 + q].y)
+                                                           : (s < 2 ? x[q].x : x[q].y);
+                const bf16x8 bh = to_bf16(xh);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) xl[q] = xh[q] - (float)bh[q];
+                const bf16x8 bl = to_bf16(xl);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[0][s], bh, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[1][s], bh, acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][s], bl, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][s], bl, acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][s], bh, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][s], bh, acc1, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) st2(tp + ro_out[q], make_float2(acc0[q], acc1[q]));
+#pragma unroll
+        for (int s = 0; s < 16; ++s) x[s] = xn[s];
+    }
+}
+
+// Wide direct form for blocks whose five targets are all >= 6: a wave's tile
+// is 32 rows x 64 columns (qubits 0..5), and every lane moves 16 bytes per
+// access -- columns 2c and 2c+1 of one row. The two columns feed two
+// independent products (column block A = even columns, B = odd columns), so
+// the operand layout is unchanged and each memory instruction carries twice
+// the bytes of the 8-byte form.
+struct KFusedWide {
+    float2* psi;
+    uint64_t N;
+    uint64_t n_tiles;
+    int pos[11];               // tile bits ascending: 0..5 and the targets
+    uint32_t toff[5];
+    const float* amat;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5, c32 = lane & 31;
+    float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+
+    auto roff = [&](int r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if ((r >> (4 - j)) & 1) o += a.toff[j];
+        return o + 2 * c32;
+    };
+    uint32_t ro_in[16], ro_out[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        ro_in[s] = roff(MODE == 0 ? 2 * s + h : (s < 8 ? 8 * h + s : 16 + 8 * h + (s - 8)));
+        ro_out[s] = roff(8 * (s >> 2) + 4 * h + (s & 3));
+    }
+    float afr[2][32];
+    bf16x8 ahi[2][4], alo[2][4];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 32; ++s) afr[b][s] = a.amat[(32 * b + c32) * 64 + 2 * s + h];
+    } else {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float th[8], tl[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    th[q] = a.amat[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    tl[q] = a.amat[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                }
+                ahi[b][s] = to_bf16(th);
+                alo[b][s] = to_bf16(tl);
+            }
+    }
+    const uint64_t waves_total = (uint64_t)gridDim.x * 4;
+    for (uint64_t tile = xcd_block(blockIdx.x, gridDim.x) * 4 + wave; tile < a.n_tiles; tile += waves_total) {
+        float2* tp = psi + insert_zeros(tile, a.pos, 11);
+        float4 x[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) x[s] = ld4(tp + ro_in[s]);
+        f32x16 a0 = {0}, a1 = {0}, b0 = {0}, b1 = {0};
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][s], x[s].x, a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][s], x[s].x, a1, 0, 0, 0);
+                b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][s], x[s].z, b0, 0, 0, 0);
+                b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][s], x[s].z, b1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][16 + s], x[s].y, a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][16 + s], x[s].y, a1, 0, 0, 0);
+                b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][16 + s], x[s].w, b0, 0, 0, 0);
+                b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][16 + s], x[s].w, b1, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                // rows of k-step s: real parts of rows 8h+q (s=0), 16+8h+q (s=1),
+                // imaginary parts of the same rows (s=2, 3)
+                float xa[8], xb[8], la[8], lb[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float4 v = (s & 1) ? x[8 + q] : x[q];
+                    xa[q] = s < 2 ? v.x : v.y;
+                    xb[q] = s < 2 ? v.z : v.w;
+                }
+                const bf16x8 ah = to_bf16(xa), bh = to_bf16(xb);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    la[q] = xa[q] - (float)ah[q];
+                    lb[q] = xb[q] - (float)bh[q];
+                }
+                const bf16x8 al = to_bf16(la), bl = to_bf16(lb);
+                a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[0][s], ah, a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[1][s], ah, a1, 0, 0, 0);
+                b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[0][s], bh, b0, 0, 0, 0);
+                b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[1][s], bh, b1, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][s], al, a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][s], al, a1, 0, 0, 0);
+                b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][s], bl, b0, 0, 0, 0);
+                b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][s], bl, b1, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][s], ah, a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][s], ah, a1, 0, 0, 0);
+                b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][s], bh, b0, 0, 0, 0);
+                b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][s], bh, b1, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) st4(tp + ro_out[q], make_float4(a0[q], a1[q], b0[q], b1[q]));
+    }
+}
+
 // Plain FP32 vector form: one thread per column, the block matrix in LDS.
 template <int K>
 __global__ __launch_bounds__(256) void k_fused_valu(float2* psi, uint64_t N, uint64_t n_cols, int npos,
@@ -238,6 +478,59 @@ __global__ __launch_bounds__(256) void k_fused_valu(float2* psi, uint64_t N, uin
 
 void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
 {
+    const int nq = __builtin_ctzll(f.N);
+    int lowest_target = 64;
+    for (int j = 0; j < 5; ++j) lowest_target = std::min(lowest_target, f.targets[j]);
+    if (lowest_target >= 6 && nq <= 32) {
+        KFusedWide d{};
+        d.psi = f.psi;
+        d.N = f.N;
+        d.n_tiles = 1ull << (nq - 11);
+        int t5[5];
+        for (int j = 0; j < 5; ++j) {
+            t5[j] = f.targets[j];
+            d.toff[j] = 1u << f.targets[j];
+        }
+        std::sort(t5, t5 + 5);
+        for (int b = 0; b < 6; ++b) d.pos[b] = b;
+        for (int b = 0; b < 5; ++b) d.pos[6 + b] = t5[b];
+        d.amat = f.amat;
+        // persistent grid: two workgroups per CU are resident (registers)
+        const uint64_t want = (d.n_tiles + 3) / 4;
+        const uint64_t cap = (uint64_t)device_info().cu_count * 2;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+        if (f.mode == SV_FUSED_FP32_MFMA)
+            hipLaunchKernelGGL(k_fused_wide<0>, dim3(grid, f.nrows), dim3(256), 0, st, d);
+        else
+            hipLaunchKernelGGL(k_fused_wide<1>, dim3(grid, f.nrows), dim3(256), 0, st, d);
+        SV_HIP(hipGetLastError());
+        return;
+    }
+    if (lowest_target >= 5 && nq <= 32) {
+        KFusedDirect d{};
+        d.psi = f.psi;
+        d.N = f.N;
+        d.n_tiles = 1ull << (nq - 10);
+        int t5[5];
+        for (int j = 0; j < 5; ++j) {
+            t5[j] = f.targets[j];
+            d.toff[j] = 1u << f.targets[j];
+        }
+        std::sort(t5, t5 + 5);
+        for (int b = 0; b < 5; ++b) d.pos[b] = b;
+        for (int b = 0; b < 5; ++b) d.pos[5 + b] = t5[b];
+        d.amat = f.amat;
+        // persistent grid: two workgroups per CU are resident (registers)
+        const uint64_t want = (d.n_tiles + 3) / 4;
+        const uint64_t cap = (uint64_t)device_info().cu_count * 2;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+        if (f.mode == SV_FUSED_FP32_MFMA)
+            hipLaunchKernelGGL(k_fused_direct<0>, dim3(grid, f.nrows), dim3(256), 0, st, d);
+        else
+            hipLaunchKernelGGL(k_fused_direct<1>, dim3(grid, f.nrows), dim3(256), 0, st, d);
+        SV_HIP(hipGetLastError());
+        return;
+    }
     KFused a{};
     a.psi = f.psi;
     a.N = f.N;

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
     float2 m[16];
 #pragma unroll
     for (int i = 0; i < D * D; ++i) m[i] = a.m[i];
-    const uint64_t u0 = (uint64_t)blockIdx.x * (kBlock * U) + threadIdx.x;
+    const uint64_t u0 = xcd_block(blockIdx.x, gridDim.x) * (kBlock * U) + threadIdx.x;
 
     if constexpr (F == VEC2 || F == ODD) {
         float4 v[U][D];
@@ -196,7 +196,7 @@ template <int F, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_diag(KDiag a)
 {
     float2* psi = row_ptr(a.p0, a.p1, a.nrow0, a.N, blockIdx.y);
-    const uint64_t u0 = (uint64_t)blockIdx.x * (kBlock * U) + threadIdx.x;
+    const uint64_t u0 = xcd_block(blockIdx.x, gridDim.x) * (kBlock * U) + threadIdx.x;
     if constexpr (F == VEC2 || F == ODD) {
         float4 v[U];
         uint64_t base[U];
@@ -260,7 +260,7 @@ void sort_small(int* v, int n)
         for (int j = i; j > 0 && v[j - 1] > v[j]; --j) std::swap(v[j - 1], v[j]);
 }
 
-constexpr int kUnroll = 2;
+constexpr int kUnroll = 1;   // one unit per thread: measured best with the XCD renumbering
 
 template <int K, int F>
 void dispatch_gate(const KGate& a, int rows, bool nt, hipStream_t st)

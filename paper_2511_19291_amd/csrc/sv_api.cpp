@@ -638,6 +638,7 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
                             a.g[d][r * D + c] = make_double2(acc.real(), acc.imag());
                         }
                 }
+                a.grid = G;
                 launch_adj_step(a, part + cur * G, s->stream);
                 const int rows_here = per_row ? 1 : B;
                 for (int r = 0; r < rows_here; ++r)

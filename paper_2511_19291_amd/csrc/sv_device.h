@@ -88,6 +88,16 @@ __device__ __forceinline__ void st2(float2* p, float2 x)
 // sweep that skips positions below it: runs of 2^4 amplitudes = 128 bytes.
 constexpr int kFullLineQubit = 4;
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8). Renumbering so that each XCD sweeps one contiguous eighth of the
+// block range keeps every XCD's concurrent accesses close together in
+// memory (measured ~10% faster sweeps at large strides). A bijection only
+// when the block count is a multiple of 8; otherwise the identity.
+__device__ __forceinline__ uint64_t xcd_block(uint64_t b, uint64_t nb)
+{
+    return (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ float2 lo2(float4 v) { return make_float2(v.x, v.y); }
 __device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); }
 __device__ __forceinline__ float4 pack4(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }

@@ -127,8 +127,9 @@ struct AdjLaunch {
     float2 uinv[16];          // U^* in complex64
     int nd;                   // derivative count (<= 3)
     double2 g[3][16];         // G_j = dU/dtheta_j U^* in complex128
+    int grid;                 // blocks per row (the slot stride of the partials)
 };
-int adj_grid(int n, int k, int nc);                   // blocks per row of an adjoint step
+int adj_grid(int n, int k, int nc);                   // blocks per row for a gate's unit count
 // partial sums land in part[(row * nd + j) * grid + block]
 void launch_adj_step(const AdjLaunch& a, double* part, hipStream_t st);
 // out[s] = sum_b part[s * grid + b], s < nslots

@@ -74,6 +74,29 @@ def test_mixed_kinds_and_observables(sv):
     assert abs(loss[0] - L) < 1e-4
 
 
+@pytest.mark.parametrize("n", [12, 15])
+def test_controlled_and_two_qubit_params_larger_state(sv, n):
+    """Controlled and two-qubit parameterised gates at sizes where those
+    gates sweep fewer amplitudes than an uncontrolled one (the partial-sum
+    layout must not depend on the gate)."""
+    rng = np.random.default_rng(200 + n)
+    b = C._Builder(n)
+    for q in range(n):
+        b.gate("ry", [q], values=[rng.uniform(0, 2 * np.pi)])
+    for _ in range(25):
+        kind = str(rng.choice(["rx", "u3", "rzz", "ryy", "p"]))
+        nt = C.N_TARGETS[kind]
+        w = [int(x) for x in rng.permutation(n)]
+        b.gate(kind, w[:nt], w[nt:nt + int(rng.integers(0, 3))], rng.uniform(0, 2 * np.pi, C.N_PARAMS[kind]))
+    circ = b.build("ctrl_params")
+    terms = C.z_sum_terms(n) + [C.pauli_term(0.5, "X0 X1")]
+    st = sv.State(n).reset().run(circ)
+    loss, g, _ = st.adjoint_grad(circ, terms)
+    L, ref, _ = oracle.grad_adjoint(circ, terms)
+    _close(g[0], ref)
+    assert abs(loss[0] - L) < 1e-4
+
+
 def test_batched_per_row_inputs(sv):
     """Batch of rows with per-row encoded inputs (the paper's batch of inputs
     x_i): gradient rows match the oracle row by row."""

@@ -34,6 +34,10 @@ def _upload(sv, n, psi, batch=1):
     (12, (3, 0, 11, 6, 1)),       # scattered, unsorted
     (15, (14, 2, 7, 9, 5)),
     (16, (4, 12, 0, 15, 8)),
+    (13, (12, 5, 9, 6, 11)),      # all targets >= 5: direct operand form
+    (20, (19, 7, 13, 5, 16)),
+    (12, (11, 10, 9, 8, 7)),      # all targets >= 6: wide direct form
+    (17, (13, 6, 16, 7, 10)),
 ])
 def test_single_block_random_unitary(sv, mode, n, targets):
     """A Haar-random 32x32 unitary on five ordered targets: pins the MFMA
