@@ -256,6 +256,20 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
             entry["plain_ms"] = round(len(circ.ops) / plain_gates_per_s * 1e3, 2)
         for name in ("fp32_mfma", "bf16x3"):
             entry[name]["speedup_vs_plain"] = round(entry["plain_ms"] / entry[name]["ms"], 2)
+        if nq == n:
+            # fusion width and arithmetic picked by the library's autotuner
+            # (plain sweeps, vector blocks of k = 2..5, matrix-core blocks)
+            t0 = time.perf_counter()
+            best, trials = sv.fused_autotune(st, circ, modes=(sv.FUSED_FP32_MFMA, sv.FUSED_BF16X3, sv.FUSED_VALU),
+                                             reps=1)
+            names = {-1: "plain", sv.FUSED_FP32_MFMA: "fp32_mfma", sv.FUSED_BF16X3: "bf16x3", sv.FUSED_VALU: "valu"}
+            entry["autotune"] = {
+                "chosen": {"max_k": best["max_k"], "mode": names[best["mode"]], "ms": round(best["ms"], 2),
+                           "sweeps": best["n_sweeps"]},
+                "trials": [{"max_k": t["max_k"], "mode": names[t["mode"]], "sweeps": t["n_sweeps"],
+                            "ms": round(t["ms"], 2)} for t in trials],
+                "tune_s": round(time.perf_counter() - t0, 2),
+            }
         fused[f"brickwork{nq}"] = entry
         st.free()
         del st
@@ -293,26 +307,38 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     torch.cuda.empty_cache()
     print("# adjoint done", file=sys.stderr, flush=True)
 
-    # -- batched: 256 uneven circuits in one graph launch vs per-gate launches
+    # -- batched: 256 uneven circuits in one graph launch vs per-gate launches;
+    #    the launch shape is picked by the library's autotuner
     circs = C.batch_workload(256, 10, 20, 6, 4)
-    plan = sv.BatchPlan(circs)
-    dp = plan.pack()
-    out = plan.out_buffer()
-    plan.launch(dp, out)
-    torch.cuda.synchronize()
-    graph_ms = min(_timed_ms(lambda: plan.launch(dp, out), stream) for _ in range(3))
     t0 = time.perf_counter()
-    plan.launch(dp, out, pergate=True)
-    torch.cuda.synchronize()
-    pergate_ms = (time.perf_counter() - t0) * 1e3
+    best, trials = sv.batch_autotune(circs, reps=2)
+    tune_s = time.perf_counter() - t0
+    timings = {}
+    for name, cfg in (("default", None), ("tuned", best)):
+        plan = sv.BatchPlan(circs, config=cfg)
+        dp = plan.pack()
+        out = plan.out_buffer()
+        plan.launch(dp, out)
+        torch.cuda.synchronize()
+        timings[name] = min(_timed_ms(lambda: plan.launch(dp, out), stream) for _ in range(3))
+        if name == "tuned":
+            info = plan.info()
+            t0 = time.perf_counter()
+            plan.launch(dp, out, pergate=True)
+            torch.cuda.synchronize()
+            pergate_ms = (time.perf_counter() - t0) * 1e3
+        plan.free()
+    graph_ms = timings["tuned"]
     gates = sum(len(c.ops) for c in circs)
     res["batched"] = {
         "workload": "256 circuits, n uniform in 10..20, encoded RY inputs + 6 x [RY, RZ, CNOT ladder], all <Z_i>",
         "gates": gates, "graph_launch_ms": round(graph_ms, 3), "per_gate_launches_ms": round(pergate_ms, 2),
         "gates_per_s": round(gates / (graph_ms / 1e3), 1),
         "speedup_vs_per_gate": round(pergate_ms / graph_ms, 2),
+        "default_config_ms": round(timings["default"], 3),
+        "autotune": {"chosen": info["config"], "grid": info["grid"], "tasks": info["n_tasks"],
+                     "passes": info["n_passes"], "configs_tried": len(trials), "tune_s": round(tune_s, 2)},
     }
-    plan.free()
     print("# batched done", file=sys.stderr, flush=True)
     return res
 
@@ -351,9 +377,10 @@ def cpu_baseline(circ, seconds: float) -> dict:
 
 def run_pmc_probe(n: int) -> int:
     """Short fixed sequence for hardware counters: 4 dense U3 sweeps on
-    targets >= 7 of an n-qubit state (k_gate<1, 2, 1, true>), two fused
-    5-qubit blocks in each matrix-core mode, then one plain copy of the state
-    (8 * 2^n bytes read, the same written) to scale the counters."""
+    targets >= 7 of an n-qubit state (k_gate<1, 2, 1, true>), four fused
+    5-qubit blocks in each matrix-core mode (one direct, two wide, one
+    LDS-staged launch), then one plain copy of the state (8 * 2^n bytes read,
+    the same written) to scale the counters."""
     import numpy as np
     import torch
 
@@ -367,12 +394,13 @@ def run_pmc_probe(n: int) -> int:
     circ = b.build("pmc_probe")
     st.run(circ)
     torch.cuda.synchronize()
-    # two fused 5-qubit blocks per matrix-core mode (targets >= 5: direct form)
+    # fused 5-qubit blocks per matrix-core mode, one per kernel form: lowest
+    # target 5 (direct form), >= 6 (wide form, twice), < 5 (LDS-staged form)
     rng = np.random.Generator(np.random.PCG64(7))
     z = rng.normal(size=(32, 32)) + 1j * rng.normal(size=(32, 32))
     q, r = np.linalg.qr(z)
     m = q * (np.diag(r) / np.abs(np.diag(r)))
-    blocks = [((9, 8, 7, 6, 5), m), ((n - 1, 20, 14, 10, 5), m)]
+    blocks = [((9, 8, 7, 6, 5), m), ((n - 1, 20, 14, 10, 6), m), ((11, 10, 9, 8, 7), m), ((n - 1, 12, 3, 2, 0), m)]
     st.apply_fused(blocks, sv.FUSED_FP32_MFMA)
     st.apply_fused(blocks, sv.FUSED_BF16X3)
     torch.cuda.synchronize()
@@ -380,7 +408,7 @@ def run_pmc_probe(n: int) -> int:
     sv.check(sv.lib().sv_stream_copy(dst.data_ptr(), st.tensor.data_ptr(), 8 * (1 << n),
                                      torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": True, "n": n, "dense_launches": 4, "fused_launches_per_mode": 2,
+    print(json.dumps({"pmc_probe": True, "n": n, "dense_launches": 4, "fused_launches_per_mode": len(blocks),
                       "copy_bytes": 8 * (1 << n),
                       "kernel_source_digest": kernel_source_digest()}), flush=True)
     return 0

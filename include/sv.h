@@ -244,6 +244,42 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
                                const int* n_ops, const int* n_params, void* stream,
                                sv_batch_plan* out);
 
+/* Launch shape of a batch plan (the tile shape of the persistent kernel).
+ *   tile_bits: 10..14. A tile holds 2^tile_bits complex64 amplitudes in LDS
+ *     (8 KiB .. 128 KiB per workgroup); a circuit of n <= tile_bits qubits is
+ *     one task run entirely in LDS, a wider one is cut into passes of tiles
+ *     that go through a device arena between passes.
+ *   threads: 256, 512 or 1024 threads per workgroup.
+ *   reg_min_bits: 4..15. Tiles of >= 2^reg_min_bits amplitudes apply their
+ *     gates as register phases (each thread holds the 16 amplitudes of four
+ *     qubits and applies every gate of a phase in registers); smaller tiles
+ *     make one LDS sweep per gate. 15: never.
+ *   wg_per_cu: persistent workgroups per compute unit, 1..16, at most the
+ *     number that are resident at once; 0: as many as are resident.
+ * Every configuration computes the same <Z_i> up to FP32 rounding order. */
+typedef struct sv_batch_config {
+    int32_t tile_bits;
+    int32_t threads;
+    int32_t reg_min_bits;
+    int32_t wg_per_cu;
+} sv_batch_config;
+
+/* The configuration sv_batch_plan_create uses: {14, 1024, 12, 0}. */
+sv_status sv_batch_default_config(sv_batch_config* out);
+
+/* sv_batch_plan_create with an explicit launch shape (config NULL: the
+ * default). Errors as sv_batch_plan_create; SV_ERR_INVALID_ARGUMENT for a
+ * field outside its range. */
+sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_op* const* ops,
+                                  const int* n_ops, const int* n_params,
+                                  const sv_batch_config* config, void* stream, sv_batch_plan* out);
+
+/* The plan's effective configuration (wg_per_cu resolved to the number
+ * launched per CU), its persistent grid size, number of tile tasks and of
+ * passes. Any output pointer may be NULL. */
+sv_status sv_batch_plan_info(sv_batch_plan p, sv_batch_config* config, int* grid, int* n_tasks,
+                             int* n_passes);
+
 /* Number of doubles in the parameter block the launch reads: circuit c's
  * parameter j is at offset param_offset[c] + j. */
 sv_status sv_batch_param_layout(sv_batch_plan p, int64_t* param_offsets, int64_t* total);
@@ -262,6 +298,56 @@ sv_status sv_batch_launch(sv_batch_plan p, const double* dev_params, double* dev
 sv_status sv_batch_launch_pergate(sv_batch_plan p, const double* dev_params, double* dev_out);
 
 sv_status sv_batch_plan_free(sv_batch_plan p);
+
+/* ------------------------------------------------------------ autotuning */
+
+/* One configuration the batch autotuner ran. */
+typedef struct sv_batch_trial {
+    sv_batch_config config;   /* effective configuration */
+    double ms;                /* mean time of one launch (graph replay) */
+    double max_dev;           /* max |out - out of the default configuration|; NaN if an output was NaN */
+} sv_batch_trial;
+
+/* Autotuner of the batched launch: times the batch (the same arguments as
+ * sv_batch_plan_create) under a staged search over launch shapes -- tile
+ * width x threads per workgroup, then where register phases start, then
+ * workgroups per CU -- and returns the fastest configuration whose outputs
+ * agree with the default configuration's within 1e-4 (FP32 rounding order).
+ *   dev_params: the device parameter block of sv_batch_param_layout (the
+ *     layout does not depend on the configuration).
+ *   reps: timed launches per configuration (after one warm-up launch).
+ *   stream: as for the plan; timing uses HIP events on it.
+ *   trials[max_trials]: may be NULL with max_trials 0; *n_trials (may be
+ *     NULL) receives the number of configurations run.
+ * Synchronous. Allocates and frees one output buffer and every trial's plan.
+ * Errors as sv_batch_plan_create; SV_ERR_HIP when no configuration
+ * reproduces the default's output. */
+sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* const* ops,
+                            const int* n_ops, const int* n_params, const double* dev_params,
+                            int reps, void* stream, sv_batch_config* best,
+                            sv_batch_trial* trials, int max_trials, int* n_trials);
+
+/* One way of applying a circuit: plain per-gate sweeps (max_k = 1, mode =
+ * -1) or the fusion planner's blocks of at most max_k qubits applied with
+ * sv_apply_fused in `mode`. */
+typedef struct sv_fusion_choice {
+    int32_t max_k;
+    int32_t mode;
+    int32_t n_sweeps;         /* gates (plain) or blocks: passes over the state */
+    double ms;                /* time of one application of the whole circuit */
+} sv_fusion_choice;
+
+/* Autotuner of the fusion width: times the circuit (host params, the same
+ * for every row) on the state s as plain sweeps, as SV_FUSED_VALU blocks of
+ * max_k = 2..5, and (n >= 10) as five-qubit matrix-core blocks in the modes
+ * that mode_mask allows (bit 1 << SV_FUSED_*; plain sweeps are always tried),
+ * and returns the fastest. The state's contents are overwritten (reset it
+ * afterwards). A width that some gate of the circuit exceeds is skipped.
+ *   reps: timed applications per candidate (after one warm-up).
+ * Synchronous. Errors as sv_run / sv_fuse_plan / sv_apply_fused. */
+sv_status sv_fused_autotune(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                            int n_params, uint32_t mode_mask, int reps, sv_fusion_choice* best,
+                            sv_fusion_choice* trials, int max_trials, int* n_trials);
 
 /* ------------------------------------------------------------- utility */
 

@@ -32,6 +32,7 @@ struct sv_batch_plan_s {
     int n_ops = 0;
     int n_pass = 0;
     int grid = 1;
+    sv_batch_config cfg{};                     // effective configuration
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const double* cap_params = nullptr;
@@ -81,15 +82,20 @@ struct Pass {
     uint64_t tile;
 };
 
+// Qubits 0..low_bits-1 are in every tile, so a tile is made of contiguous
+// runs of 2^low_bits amplitudes; the rest of the tile (at least five qubits,
+// the most one gate touches) is free for the pass's gates.
+int low_bits_of(int tile_bits) { return std::min(6, tile_bits - 5); }
+
 // Cut a gate list into passes whose gates all act inside one tile of
-// kTileBits qubits that always contains qubits 0..kLowBits-1. Scanning in
-// order, a gate joins the pass when its qubits fit and it touches no qubit of
-// a gate already left for a later pass; so gates only move past gates on
-// disjoint qubits and the pass sequence equals the circuit.
-std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops)
+// tile_bits qubits that always contains the low qubits. Scanning in order, a
+// gate joins the pass when its qubits fit and it touches no qubit of a gate
+// already left for a later pass; so gates only move past gates on disjoint
+// qubits and the pass sequence equals the circuit.
+std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops, int tile_bits)
 {
-    const uint64_t low = (1ull << kLowBits) - 1;
-    const int room = kTileBits - kLowBits;
+    const uint64_t low = (1ull << low_bits_of(tile_bits)) - 1;
+    const int room = tile_bits - low_bits_of(tile_bits);
     std::vector<int> remaining(ops.size());
     std::iota(remaining.begin(), remaining.end(), 0);
     std::vector<Pass> passes;
@@ -114,7 +120,7 @@ std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops)
             }
         }
         uint64_t tile = low | chosen;
-        for (int q = 0; q < n && __builtin_popcountll(tile) < kTileBits; ++q) tile |= 1ull << q;
+        for (int q = 0; q < n && __builtin_popcountll(tile) < tile_bits; ++q) tile |= 1ull << q;
         p.tile = tile;
         passes.push_back(std::move(p));
         remaining.swap(rest);
@@ -204,6 +210,27 @@ void destroy(sv_batch_plan p)
     delete p;
 }
 
+sv_batch_config default_config()
+{
+    sv_batch_config c{};
+    c.tile_bits = kMaxTileBits;
+    c.threads = 1024;
+    c.reg_min_bits = 12;
+    c.wg_per_cu = 0;
+    return c;
+}
+
+void check_config(const sv_batch_config& c)
+{
+    need(c.tile_bits >= kMinTileBits && c.tile_bits <= kMaxTileBits, SV_ERR_INVALID_ARGUMENT,
+         "tile_bits must be 10..14");
+    need(c.threads == 256 || c.threads == 512 || c.threads == 1024, SV_ERR_INVALID_ARGUMENT,
+         "threads must be 256, 512 or 1024");
+    need(c.reg_min_bits >= kRegBits && c.reg_min_bits <= kMaxTileBits + 1, SV_ERR_INVALID_ARGUMENT,
+         "reg_min_bits must be 4..15");
+    need(c.wg_per_cu >= 0 && c.wg_per_cu <= 16, SV_ERR_INVALID_ARGUMENT, "wg_per_cu must be 0..16");
+}
+
 BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
 {
     BatchArgs a{};
@@ -232,13 +259,24 @@ using namespace sv;
 
 extern "C" {
 
-sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op* const* ops, const int* n_ops,
-                               const int* n_params, void* stream, sv_batch_plan* out)
+sv_status sv_batch_default_config(sv_batch_config* out)
+{
+    return guarded([&] {
+        need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
+        *out = default_config();
+    });
+}
+
+sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_op* const* ops, const int* n_ops,
+                                  const int* n_params, const sv_batch_config* config, void* stream,
+                                  sv_batch_plan* out)
 {
     sv_batch_plan p = nullptr;
     const sv_status st = guarded([&] {
         need(out != nullptr, SV_ERR_INVALID_ARGUMENT, "out is NULL");
         *out = nullptr;
+        const sv_batch_config cfg = config ? *config : default_config();
+        check_config(cfg);
         need(n_circuits >= 1, SV_ERR_INVALID_ARGUMENT, "need at least one circuit");
         need(n_qubits && ops && n_ops && n_params, SV_ERR_INVALID_ARGUMENT, "null array");
         p = new sv_batch_plan_s;
@@ -281,26 +319,26 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
             const std::vector<sv_op>& v = p->ops[c];
             BCirc bc{};
             bc.n = n;
-            bc.m = std::min(n, kTileBits);
+            bc.m = std::min(n, cfg.tile_bits);
             bc.ntiles = 1 << (n - bc.m);
             bc.out_idx = c;
             bc.arena_off = 0;
             bc.zpart_off = 0;
-            if (n > kTileBits) {
+            if (n > cfg.tile_bits) {
                 bc.arena_off = arena;
                 arena += 1ll << n;
                 bc.zpart_off = zrows;
                 zrows += bc.ntiles;
             }
             std::vector<Pass> pl;
-            if (n <= kTileBits) {
+            if (n <= cfg.tile_bits) {
                 Pass one;
                 one.gates.resize(v.size());
                 std::iota(one.gates.begin(), one.gates.end(), 0);
                 one.tile = (1ull << n) - 1;
                 pl.push_back(std::move(one));
             } else {
-                pl = plan_passes(n, v);
+                pl = plan_passes(n, v, cfg.tile_bits);
             }
             bc.pass_begin = (int)pass.size();
             for (const Pass& ps : pl) {
@@ -345,7 +383,7 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
                     masks.push_back(mask);
                 }
                 bp.phase_begin = bp.phase_end = (int)phase.size();
-                if (bc.m >= kRegMinTile) {
+                if (bc.m >= cfg.reg_min_bits) {
                     std::vector<BPhase> ph;
                     const std::vector<int> order = plan_phases(masks, bc.m, ph);
                     for (BPhase& x : ph) {
@@ -386,12 +424,12 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
         for (int r = 0; r < max_pass; ++r) {
             for (int ci = 0; ci < (int)circ.size(); ++ci) {
                 const BCirc& bc = circ[ci];
-                if (bc.n <= kTileBits || r >= bc.pass_end - bc.pass_begin) continue;
+                if (bc.ntiles == 1 || r >= bc.pass_end - bc.pass_begin) continue;
                 for (int t = 0; t < bc.ntiles; ++t) tasks.push_back(BTask{ci, bc.pass_begin + r, t, 0});
             }
             if (r == 0)
                 for (int ci = 0; ci < (int)circ.size(); ++ci)
-                    if (circ[ci].n <= kTileBits) tasks.push_back(BTask{ci, circ[ci].pass_begin, 0, 0});
+                    if (circ[ci].ntiles == 1) tasks.push_back(BTask{ci, circ[ci].pass_begin, 0, 0});
         }
         p->n_tasks = (int)tasks.size();
         p->n_ops = (int)bops.size();
@@ -413,11 +451,34 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
         dev_alloc((void**)&p->d_zpart, (size_t)zrows * (kBatchMaxQubits + 1) * sizeof(double), "partials");
         dev_alloc((void**)&p->d_done, (size_t)p->n_pass * sizeof(int), "pass counters");
         dev_alloc((void**)&p->d_counter, sizeof(int), "queue counter");
-        p->grid = std::max(1, std::min(p->n_tasks, device_info().cu_count));
+        // persistent grid: the requested workgroups per CU, at most as many
+        // as are resident at once (LDS, registers), at most one per task
+        const int resident = batch_max_wg_per_cu(cfg.threads, cfg.tile_bits);
+        const int per_cu = cfg.wg_per_cu == 0 ? resident : std::min(cfg.wg_per_cu, resident);
+        p->cfg = cfg;
+        p->cfg.wg_per_cu = per_cu;
+        p->grid = std::max(1, std::min(p->n_tasks, device_info().cu_count * per_cu));
         *out = p;
     });
     if (st != SV_OK) destroy(p);
     return st;
+}
+
+sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op* const* ops, const int* n_ops,
+                               const int* n_params, void* stream, sv_batch_plan* out)
+{
+    return sv_batch_plan_create_ex(n_circuits, n_qubits, ops, n_ops, n_params, nullptr, stream, out);
+}
+
+sv_status sv_batch_plan_info(sv_batch_plan p, sv_batch_config* config, int* grid, int* n_tasks, int* n_passes)
+{
+    return guarded([&] {
+        need(p != nullptr, SV_ERR_INVALID_ARGUMENT, "null plan");
+        if (config) *config = p->cfg;
+        if (grid) *grid = p->grid;
+        if (n_tasks) *n_tasks = p->n_tasks;
+        if (n_passes) *n_passes = p->n_pass;
+    });
 }
 
 sv_status sv_batch_param_layout(sv_batch_plan p, int64_t* param_offsets, int64_t* total)
@@ -439,7 +500,7 @@ sv_status sv_batch_launch(sv_batch_plan p, const double* dev_params, double* dev
         const BatchArgs a = args_of(p, dev_params, dev_out);
         if (!p->stream) {
             // the legacy default stream cannot be captured: launch directly
-            launch_batch(a, p->grid, p->stream);
+            launch_batch(a, p->grid, p->cfg.threads, p->cfg.tile_bits, p->stream);
             return;
         }
         if (!p->exec || p->cap_params != dev_params || p->cap_out != dev_out) {
@@ -453,7 +514,7 @@ sv_status sv_batch_launch(sv_batch_plan p, const double* dev_params, double* dev
             }
             SV_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
             try {
-                launch_batch(a, p->grid, p->stream);
+                launch_batch(a, p->grid, p->cfg.threads, p->cfg.tile_bits, p->stream);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(p->stream, &g);

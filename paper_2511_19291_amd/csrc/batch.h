@@ -8,13 +8,12 @@
 
 namespace sv {
 
-constexpr int kTileBits = 14;         // LDS tile: 2^14 complex64 = 128 KiB
-constexpr int kLowBits = 6;           // qubits 0..5 are in every tile (runs of 64 amplitudes)
+constexpr int kMaxTileBits = 14;      // widest LDS tile: 2^14 complex64 = 128 KiB
+constexpr int kMinTileBits = 10;
 constexpr int kBatchMaxQubits = 24;
 constexpr int kMatStride = 16;        // complex64 entries reserved per gate matrix
 
-constexpr int kRegBits = 4;           // register blocking: 16 amplitudes per thread
-constexpr int kRegMinTile = 12;       // tiles of >= 2^12 amplitudes use register phases
+constexpr int kRegBits = 4;           // register blocking: 16 amplitudes per unit
 
 // One gate with tile-local qubit positions and its precomputed addressing.
 struct BOp {
@@ -39,22 +38,22 @@ struct BPhase {
 };
 
 // A pass: gates [op_begin, op_end) all act inside the tile whose bit j is
-// qubit pos[j] (ascending). Tiles of >= 2^12 amplitudes run the gates as the
-// register phases [phase_begin, phase_end) instead of one by one.
+// qubit pos[j] (ascending). When phase_begin < phase_end the gates run as
+// those register phases instead of one LDS sweep each.
 struct BPass {
     int op_begin;
     int op_end;
     int phase_begin;
     int phase_end;
-    int pos[kTileBits];
+    int pos[kMaxTileBits];
 };
 
 struct BCirc {
     int n;
-    int m;                            // tile bits: min(n, kTileBits)
+    int m;                            // tile bits: min(n, the plan's tile width)
     int pass_begin;
     int pass_end;
-    int64_t arena_off;                // amplitude offset of the state in the arena (n > kTileBits)
+    int64_t arena_off;                // amplitude offset of the state in the arena (n > m)
     int64_t zpart_off;                // first row of this circuit's per-tile <Z> partials
     int ntiles;                       // 2^(n - m)
     int out_idx;                      // row of the output
@@ -88,6 +87,11 @@ struct BatchArgs {
     int* done;                        // finished tiles per pass
 };
 
-void launch_batch(const BatchArgs& a, int grid, hipStream_t st);
+// dynamic LDS of one workgroup for tiles of 2^tile_bits amplitudes
+size_t batch_lds_bytes(int tile_bits);
+// resident workgroups per CU of the persistent kernel (also raises the
+// kernel's dynamic-LDS limit to that size)
+int batch_max_wg_per_cu(int threads, int tile_bits);
+void launch_batch(const BatchArgs& a, int grid, int threads, int tile_bits, hipStream_t st);
 
 }  // namespace sv

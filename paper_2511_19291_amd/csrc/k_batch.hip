@@ -7,16 +7,17 @@
 // computed once from the parameter block (so a replay of the graph reads new
 // parameters), and the queue and pass counters are cleared.
 //
-// Persistent kernel: each workgroup (1024 threads) takes tasks from an atomic
-// counter. A task is one tile of one pass of one circuit; a tile holds up to
-// 2^14 amplitudes in LDS (128 KiB).
-//   n <= 14: the whole circuit is one task: the state is created in LDS as
+// Persistent kernel: each workgroup (NT = 256, 512 or 1024 threads) takes
+// tasks from an atomic counter. A task is one tile of one pass of one
+// circuit; a tile holds up to 2^T amplitudes in LDS (T = 10..14, the plan's
+// tile width; 2^14 complex64 = 128 KiB), sized at launch as dynamic LDS.
+//   n <= T:  the whole circuit is one task: the state is created in LDS as
 //            |0..0>, every gate runs in LDS, <Z_i> is reduced from LDS -- the
 //            state never touches HBM.
-//   n > 14:  the gate list is cut into passes whose gates all act inside one
-//            14-qubit tile (always including qubits 0..5, so a tile is made of
-//            contiguous runs of >= 64 amplitudes); the 2^(n-14) tiles of a
-//            pass are independent tasks, spread over many workgroups. A tile
+//   n > T:   the gate list is cut into passes whose gates all act inside one
+//            T-qubit tile (always including the lowest qubits, so a tile is
+//            made of contiguous runs of >= 32 amplitudes); the 2^(n-T) tiles
+//            of a pass are independent tasks, spread over many workgroups. A tile
 //            of pass p waits (bounded) until every tile of pass p-1 of its
 //            circuit is done; tasks are ordered so such a wait only ever
 //            depends on tasks handed out earlier. The first pass creates
@@ -31,7 +32,6 @@ namespace sv {
 
 namespace {
 
-constexpr int kBT = 1024;
 constexpr int kZ = kBatchMaxQubits + 1;
 
 __device__ __forceinline__ float2 f2(double re, double im) { return make_float2((float)re, (float)im); }
@@ -127,13 +127,14 @@ __device__ __forceinline__ uint32_t ins0(uint32_t g, const int* pos, int np)
 }
 
 // One gate on the tile in LDS.
+template <int NT>
 __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, const float2* __restrict__ mat)
 {
     const uint32_t groups = 1u << (m_bits - op.np);
     if (op.nt == 1) {
         const float2 m0 = mat[0], m1 = mat[1], m2 = mat[2], m3 = mat[3];
         const uint32_t tb = op.off[1];
-        for (uint32_t g = threadIdx.x; g < groups; g += kBT) {
+        for (uint32_t g = threadIdx.x; g < groups; g += NT) {
             const uint32_t i0 = ins0(g, op.pos, op.np) | op.cmask, i1 = i0 | tb;
             const float2 x0 = s[i0], x1 = s[i1];
             s[i0] = cfma(m1, x1, cmul(m0, x0));
@@ -143,7 +144,7 @@ __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, c
         float2 mm[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) mm[q] = mat[q];
-        for (uint32_t g = threadIdx.x; g < groups; g += kBT) {
+        for (uint32_t g = threadIdx.x; g < groups; g += NT) {
             const uint32_t base = ins0(g, op.pos, op.np) | op.cmask;
             float2 x[4], y[4];
 #pragma unroll
@@ -236,45 +237,52 @@ __device__ __forceinline__ void reg_gate(float2 (&v)[16], const BOp& op, const f
     }
 }
 
-// One pass on the tile in LDS as register phases (m >= 12).
+// One pass on the tile in LDS as register phases. A unit u < 2^(m-4) is the
+// set of 16 amplitudes that share the complement bits u; the units of a phase
+// are disjoint, so the threads take them in any order.
+template <int NT>
 __device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs& a)
 {
-    const bool active = threadIdx.x < (1u << (m - kRegBits));
+    const uint32_t units = 1u << (m - kRegBits);
     for (int hi = ps.phase_begin; hi < ps.phase_end; ++hi) {
         const BPhase ph = a.phases[hi];
         if (ph.g[0] < 0) {
             // a gate on more than four qubits: one LDS sweep
             for (int oi = ph.op_begin; oi < ph.op_end; ++oi) {
-                lds_gate(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
+                lds_gate<NT>(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
                 __syncthreads();
             }
             continue;
         }
+        uint32_t goff[kRegBits];
         uint32_t gmask = 0;
 #pragma unroll
-        for (int i = 0; i < kRegBits; ++i) gmask |= 1u << ph.g[i];
-        // deposit the thread index on the complement positions
-        uint32_t base = 0;
-        for (int b = 0, k = 0; b < m; ++b) {
-            if ((gmask >> b) & 1) continue;
-            if ((threadIdx.x >> k) & 1) base |= 1u << b;
-            ++k;
+        for (int i = 0; i < kRegBits; ++i) {
+            goff[i] = 1u << ph.g[i];
+            gmask |= goff[i];
         }
-        float2 v[16];
-        uint32_t off[16];
+        for (uint32_t u = threadIdx.x; u < units; u += NT) {
+            // deposit the unit index on the complement positions
+            uint32_t base = 0;
+            for (int b = 0, k = 0; b < m; ++b) {
+                if ((gmask >> b) & 1) continue;
+                if ((u >> k) & 1) base |= 1u << b;
+                ++k;
+            }
+            float2 v[16];
+            uint32_t off[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            uint32_t o = base;
+            for (int j = 0; j < 16; ++j) {
+                uint32_t o = base;
 #pragma unroll
-            for (int i = 0; i < kRegBits; ++i)
-                if ((j >> i) & 1) o |= 1u << ph.g[i];
-            off[j] = o;
-        }
-        if (active) {
+                for (int i = 0; i < kRegBits; ++i)
+                    if ((j >> i) & 1) o |= goff[i];
+                off[j] = o;
+            }
 #pragma unroll
             for (int j = 0; j < 16; ++j) v[j] = tile[off[j]];
             for (int oi = ph.op_begin; oi < ph.op_end; ++oi) reg_gate(v, a.ops[oi], a.mats + (size_t)oi * kMatStride);
-            // each thread writes back exactly the amplitudes it read
+            // each unit writes back exactly the amplitudes it read
 #pragma unroll
             for (int j = 0; j < 16; ++j) tile[off[j]] = v[j];
         }
@@ -282,15 +290,19 @@ __device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs
     }
 }
 
-// offset of tile-local index l = threadIdx.x + 1024 j inside the state
-__device__ __forceinline__ uint64_t tile_off(const BPass& ps, int m, uint64_t off_t, uint32_t j)
+// Offset inside the state of tile-local index l = threadIdx.x + NT j: the
+// thread's own bits (off_t) plus the bits of j on tile positions LB.. (LB =
+// log2 NT).
+template <int LB>
+__device__ __forceinline__ uint64_t tile_off(const int* pos, int m, uint64_t off_t, uint32_t j)
 {
     uint64_t off = off_t;
-    for (int b = 10; b < m; ++b)
-        if ((j >> (b - 10)) & 1) off |= 1ull << ps.pos[b];
+    for (int b = LB; b < m; ++b)
+        if ((j >> (b - LB)) & 1) off |= 1ull << pos[b];
     return off;
 }
 
+template <int NT>
 __device__ __forceinline__ void wg_sum(double (&zs)[kZ], double (*red)[kZ])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -304,10 +316,16 @@ __device__ __forceinline__ void wg_sum(double (&zs)[kZ], double (*red)[kZ])
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
+constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
 {
-    __shared__ float2 tile[1 << kTileBits];
-    __shared__ double red[kBT / 64][kZ];
+    constexpr int LB = log2i(NT);
+    constexpr int NW = NT / 64;
+    extern __shared__ float2 tile[];         // 2^m complex64, m <= the plan's tile width
+    __shared__ double red[NW][kZ];
+    __shared__ int s_pos[kMaxTileBits];      // the pass's tile qubits (LDS: indexed at run time)
     __shared__ int s_task, s_final, s_late;
     for (;;) {
         if (threadIdx.x == 0) s_task = atomicAdd(a.counter, 1);
@@ -317,8 +335,9 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
         if (ti >= a.n_tasks) break;
         const BTask tk = a.tasks[ti];
         const BCirc c = a.circ[tk.circ];
-        const BPass ps = a.pass[tk.pass];
+        const BPass& ps = a.pass[tk.pass];
         const int m = c.m;
+        if (threadIdx.x < kMaxTileBits) s_pos[threadIdx.x] = ps.pos[threadIdx.x];
         const uint32_t tsize = 1u << m;
         const bool first = tk.pass == c.pass_begin, last = tk.pass == c.pass_end - 1;
         if (threadIdx.x == 0) {
@@ -337,23 +356,23 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
             }
         }
         __syncthreads();
-        const uint64_t base = insert_zeros((uint64_t)tk.tile, ps.pos, m);
+        const uint64_t base = insert_zeros((uint64_t)tk.tile, s_pos, m);
         uint64_t off_t = 0;
-        for (int b = 0; b < m && b < 10; ++b)
-            if ((threadIdx.x >> b) & 1) off_t |= 1ull << ps.pos[b];
+        for (int b = 0; b < m && b < LB; ++b)
+            if ((threadIdx.x >> b) & 1) off_t |= 1ull << s_pos[b];
         // fill the tile
-        for (uint32_t j = 0; (j << 10) < tsize; ++j) {
-            const uint32_t l = threadIdx.x + (j << 10);
+        for (uint32_t j = 0; (j << LB) < tsize; ++j) {
+            const uint32_t l = threadIdx.x + (j << LB);
             if (l >= tsize) break;
             if (first) tile[l] = make_float2(base == 0 && l == 0 ? 1.f : 0.f, 0.f);
-            else tile[l] = ld2<false>(a.arena + c.arena_off + base + tile_off(ps, m, off_t, j));
+            else tile[l] = ld2<false>(a.arena + c.arena_off + base + tile_off<LB>(s_pos, m, off_t, j));
         }
         __syncthreads();
-        if (m >= kRegMinTile) {
-            run_phases(tile, m, ps, a);
+        if (ps.phase_end > ps.phase_begin) {
+            run_phases<NT>(tile, m, ps, a);
         } else {
             for (int oi = ps.op_begin; oi < ps.op_end; ++oi) {
-                lds_gate(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
+                lds_gate<NT>(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
                 __syncthreads();
             }
         }
@@ -361,10 +380,10 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
             double zs[kZ];
 #pragma unroll
             for (int i = 0; i < kZ; ++i) zs[i] = 0.0;
-            for (uint32_t j = 0; (j << 10) < tsize; ++j) {
-                const uint32_t l = threadIdx.x + (j << 10);
+            for (uint32_t j = 0; (j << LB) < tsize; ++j) {
+                const uint32_t l = threadIdx.x + (j << LB);
                 if (l >= tsize) break;
-                const uint64_t gb = base + tile_off(ps, m, off_t, j);
+                const uint64_t gb = base + tile_off<LB>(s_pos, m, off_t, j);
                 const float2 v = tile[l];
                 const double p = (double)v.x * v.x + (double)v.y * v.y;
                 zs[kBatchMaxQubits] += p;
@@ -372,13 +391,13 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
                 for (int i = 0; i < kBatchMaxQubits; ++i)
                     if ((gb >> i) & 1) zs[i] += p;
             }
-            wg_sum(zs, red);
+            wg_sum<NT>(zs, red);
             if (c.ntiles == 1) {
                 if (threadIdx.x < SV_BATCH_OUT_STRIDE) {
                     const int i = threadIdx.x;
                     double t = 0.0, s = 0.0;
                     if (i < c.n)
-                        for (int w = 0; w < kBT / 64; ++w) {
+                        for (int w = 0; w < NW; ++w) {
                             t += red[w][kBatchMaxQubits];
                             s += red[w][i];
                         }
@@ -387,14 +406,14 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
                 }
             } else if (threadIdx.x < kZ) {
                 double s = 0.0;
-                for (int w = 0; w < kBT / 64; ++w) s += red[w][threadIdx.x];
+                for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
                 a.zpart[(size_t)(c.zpart_off + tk.tile) * kZ + threadIdx.x] = s_late ? __builtin_nan("") : s;
             }
         } else {
-            for (uint32_t j = 0; (j << 10) < tsize; ++j) {
-                const uint32_t l = threadIdx.x + (j << 10);
+            for (uint32_t j = 0; (j << LB) < tsize; ++j) {
+                const uint32_t l = threadIdx.x + (j << LB);
                 if (l >= tsize) break;
-                st2<false>(a.arena + c.arena_off + base + tile_off(ps, m, off_t, j), tile[l]);
+                st2<false>(a.arena + c.arena_off + base + tile_off<LB>(s_pos, m, off_t, j), tile[l]);
             }
         }
         __syncthreads();   // all results written before the pass counter moves
@@ -426,14 +445,40 @@ __global__ __launch_bounds__(kBT) void k_batch(BatchArgs a)
     }
 }
 
+template <int NT>
+void* batch_kernel()
+{
+    return reinterpret_cast<void*>(&k_batch<NT>);
+}
+
 }  // namespace
 
-void launch_batch(const BatchArgs& a, int grid, hipStream_t st)
+size_t batch_lds_bytes(int tile_bits)
+{
+    return (sizeof(float2) << tile_bits);
+}
+
+int batch_max_wg_per_cu(int threads, int tile_bits)
+{
+    int nb = 0;
+    const size_t lds = batch_lds_bytes(tile_bits);
+    void* f = threads == 256 ? batch_kernel<256>() : threads == 512 ? batch_kernel<512>() : batch_kernel<1024>();
+    SV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, threads, lds));
+    return std::max(nb, 1);
+}
+
+void launch_batch(const BatchArgs& a, int grid, int threads, int tile_bits, hipStream_t st)
 {
     const int items = std::max(std::max(a.n_ops, a.n_pass), 1);
     hipLaunchKernelGGL(k_batch_prep, dim3((items + 255) / 256), dim3(256), 0, st, a);
     SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), 0, st, a);
+    const size_t lds = batch_lds_bytes(tile_bits);
+    switch (threads) {
+    case 256: hipLaunchKernelGGL(k_batch<256>, dim3(grid), dim3(256), lds, st, a); break;
+    case 512: hipLaunchKernelGGL(k_batch<512>, dim3(grid), dim3(512), lds, st, a); break;
+    default: hipLaunchKernelGGL(k_batch<1024>, dim3(grid), dim3(1024), lds, st, a); break;
+    }
     SV_HIP(hipGetLastError());
 }
 

@@ -36,6 +36,7 @@ struct KGate {
     int nrow0;
     uint64_t N;
     uint64_t n_units;     // per row
+    uint64_t unit0;       // first unit of this launch (launches are split at kMaxBlocks)
     uint64_t cmask;       // control bits, OR'ed into every base
     uint64_t moff[4];     // member offsets: bits of the targets selected by the member index
     int npos;             // positions where zero bits are inserted (sorted ascending)
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
     float2 m[16];
 #pragma unroll
     for (int i = 0; i < D * D; ++i) m[i] = a.m[i];
-    const uint64_t u0 = xcd_block(blockIdx.x, gridDim.x) * (kBlock * U) + threadIdx.x;
+    const uint64_t u0 = a.unit0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock * U) + threadIdx.x;
 
     if constexpr (F == VEC2 || F == ODD) {
         float4 v[U][D];
@@ -177,6 +178,7 @@ struct KDiag {
     int nrow0;
     uint64_t N;
     uint64_t n_units;
+    uint64_t unit0;       // first unit of this launch
     uint64_t fmask;       // fixed-to-1 bits above qubit 0
     int npos;
     int pos[5];
@@ -196,7 +198,7 @@ template <int F, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_diag(KDiag a)
 {
     float2* psi = row_ptr(a.p0, a.p1, a.nrow0, a.N, blockIdx.y);
-    const uint64_t u0 = xcd_block(blockIdx.x, gridDim.x) * (kBlock * U) + threadIdx.x;
+    const uint64_t u0 = a.unit0 + xcd_block(blockIdx.x, gridDim.x) * (kBlock * U) + threadIdx.x;
     if constexpr (F == VEC2 || F == ODD) {
         float4 v[U];
         uint64_t base[U];
@@ -262,16 +264,33 @@ void sort_small(int* v, int n)
 
 constexpr int kUnroll = 1;   // one unit per thread: measured best with the XCD renumbering
 
+// A launch holds fewer than 2^32 work-items in x: sweeps of more units (states
+// above 32 qubits) are split into launches of at most kMaxBlocks workgroups,
+// each starting at its own first unit.
+constexpr uint64_t kMaxBlocks = 1ull << 22;
+
+template <class Args, class Launch>
+void split_launch(Args a, uint64_t blocks, Launch&& launch)
+{
+    const uint64_t per_block = (uint64_t)kBlock * kUnroll;
+    for (uint64_t b0 = 0; b0 < blocks; b0 += kMaxBlocks) {
+        a.unit0 = b0 * per_block;
+        launch(a, (unsigned)std::min(kMaxBlocks, blocks - b0));
+        SV_HIP(hipGetLastError());
+    }
+}
+
 template <int K, int F>
 void dispatch_gate(const KGate& a, int rows, bool nt, hipStream_t st)
 {
     const uint64_t per_block = (uint64_t)kBlock * kUnroll;
     const uint64_t blocks = (a.n_units + per_block - 1) / per_block;
-    if (nt)
-        hipLaunchKernelGGL((k_gate<K, F, kUnroll, true>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_gate<K, F, kUnroll, false>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    SV_HIP(hipGetLastError());
+    split_launch(a, blocks, [&](const KGate& x, unsigned nb) {
+        if (nt)
+            hipLaunchKernelGGL((k_gate<K, F, kUnroll, true>), dim3(nb, rows), dim3(kBlock), 0, st, x);
+        else
+            hipLaunchKernelGGL((k_gate<K, F, kUnroll, false>), dim3(nb, rows), dim3(kBlock), 0, st, x);
+    });
 }
 
 }  // namespace
@@ -372,15 +391,16 @@ void launch_diag(const DiagLaunch& d, hipStream_t st)
     a.n_units = 1ull << (n - a.npos - 1);
     const uint64_t blocks = (a.n_units + per_block - 1) / per_block;
     const bool nt = a.npos == 0 || a.pos[0] >= kFullLineQubit;
-    if (fixed0 && nt)
-        hipLaunchKernelGGL((k_diag<ODD, kUnroll, true>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    else if (fixed0)
-        hipLaunchKernelGGL((k_diag<ODD, kUnroll, false>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    else if (nt)
-        hipLaunchKernelGGL((k_diag<VEC2, kUnroll, true>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_diag<VEC2, kUnroll, false>), dim3((unsigned)blocks, rows), dim3(kBlock), 0, st, a);
-    SV_HIP(hipGetLastError());
+    split_launch(a, blocks, [&](const KDiag& x, unsigned nb) {
+        if (fixed0 && nt)
+            hipLaunchKernelGGL((k_diag<ODD, kUnroll, true>), dim3(nb, rows), dim3(kBlock), 0, st, x);
+        else if (fixed0)
+            hipLaunchKernelGGL((k_diag<ODD, kUnroll, false>), dim3(nb, rows), dim3(kBlock), 0, st, x);
+        else if (nt)
+            hipLaunchKernelGGL((k_diag<VEC2, kUnroll, true>), dim3(nb, rows), dim3(kBlock), 0, st, x);
+        else
+            hipLaunchKernelGGL((k_diag<VEC2, kUnroll, false>), dim3(nb, rows), dim3(kBlock), 0, st, x);
+    });
 }
 
 void launch_basis(const Rows& r, uint64_t idx, hipStream_t st)
@@ -395,10 +415,14 @@ void launch_basis(const Rows& r, uint64_t idx, hipStream_t st)
 void launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st)
 {
     const uint64_t n4 = bytes / 16;
-    const uint64_t blocks = (n4 + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBlock), 0, st, static_cast<float2*>(dst),
-                       static_cast<const float2*>(src), n4);
-    SV_HIP(hipGetLastError());
+    // at most kMaxBlocks workgroups per launch
+    const uint64_t chunk = kMaxBlocks * kBlock;
+    for (uint64_t i0 = 0; i0 < n4; i0 += chunk) {
+        const uint64_t m = std::min(chunk, n4 - i0);
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           static_cast<float2*>(dst) + 2 * i0, static_cast<const float2*>(src) + 2 * i0, m);
+        SV_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace sv

@@ -47,6 +47,30 @@ class SvPauliTerm(C.Structure):
     _fields_ = [("x_mask", C.c_uint64), ("z_mask", C.c_uint64), ("coeff", C.c_double)]
 
 
+class SvBatchConfig(C.Structure):
+    _fields_ = [("tile_bits", C.c_int32), ("threads", C.c_int32), ("reg_min_bits", C.c_int32),
+                ("wg_per_cu", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+    @classmethod
+    def of(cls, d: dict) -> "SvBatchConfig":
+        return cls(*[int(d[f]) for f, _ in cls._fields_])
+
+
+class SvBatchTrial(C.Structure):
+    _fields_ = [("config", SvBatchConfig), ("ms", C.c_double), ("max_dev", C.c_double)]
+
+
+class SvFusionChoice(C.Structure):
+    _fields_ = [("max_k", C.c_int32), ("mode", C.c_int32), ("n_sweeps", C.c_int32), ("ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"max_k": int(self.max_k), "mode": int(self.mode), "n_sweeps": int(self.n_sweeps),
+                "ms": float(self.ms)}
+
+
 class SvError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(msg)
@@ -80,6 +104,14 @@ def lib() -> C.CDLL:
         "sv_adjoint_grad": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm), C.c_int,
                             vp, dp, dp, dp],
         "sv_batch_plan_create": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, vp, C.POINTER(vp)],
+        "sv_batch_default_config": [C.POINTER(SvBatchConfig)],
+        "sv_batch_plan_create_ex": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, C.POINTER(SvBatchConfig), vp,
+                                    C.POINTER(vp)],
+        "sv_batch_plan_info": [vp, C.POINTER(SvBatchConfig), ip, ip, ip],
+        "sv_batch_autotune": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, vp, C.c_int, vp,
+                              C.POINTER(SvBatchConfig), C.POINTER(SvBatchTrial), C.c_int, ip],
+        "sv_fused_autotune": [vp, C.POINTER(SvOp), C.c_int, dp, C.c_int, C.c_uint32, C.c_int,
+                              C.POINTER(SvFusionChoice), C.POINTER(SvFusionChoice), C.c_int, ip],
         "sv_batch_param_layout": [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
         "sv_batch_launch": [vp, vp, vp],
         "sv_batch_launch_pergate": [vp, vp, vp],
@@ -299,31 +331,51 @@ def fuse_plan(circuit, max_k: int = 5, params=None) -> List[Tuple[Tuple[int, ...
     return out
 
 
+def _batch_arrays(circuits, tables):
+    nc = len(circuits)
+    nq = _iarr([c.n for c in circuits])
+    nops = _iarr([t.n for t in tables])
+    npar = _iarr([c.n_params for c in circuits])
+    ops_arr = (C.POINTER(SvOp) * nc)(*[C.cast(t.arr, C.POINTER(SvOp)) for t in tables])
+    return nc, nq, ops_arr, nops, npar
+
+
+def default_batch_config() -> dict:
+    c = SvBatchConfig()
+    check(lib().sv_batch_default_config(C.byref(c)))
+    return c.as_dict()
+
+
 class BatchPlan:
     """Many independent circuits (uneven qubit counts) run by one persistent
     kernel launch captured in a hipGraph; every circuit starts from |0..0>
-    and yields all <Z_i>."""
+    and yields all <Z_i>. ``config`` (a dict with the fields of
+    ``sv_batch_config``) sets the launch shape; None takes the default."""
 
-    def __init__(self, circuits: Sequence, device=None):
+    def __init__(self, circuits: Sequence, device=None, config: Optional[dict] = None):
         import torch
 
         self.circuits = list(circuits)
         self.stream = torch.cuda.current_stream(device)
         self.tables = [OpTable(c.ops) for c in self.circuits]
-        nc = len(self.circuits)
-        nq = _iarr([c.n for c in self.circuits])
-        nops = _iarr([t.n for t in self.tables])
-        npar = _iarr([c.n_params for c in self.circuits])
-        ops_arr = (C.POINTER(SvOp) * nc)(*[C.cast(t.arr, C.POINTER(SvOp)) for t in self.tables])
+        nc, nq, ops_arr, nops, npar = _batch_arrays(self.circuits, self.tables)
         h = C.c_void_p()
-        check(lib().sv_batch_plan_create(nc, nq, ops_arr, nops, npar, C.c_void_p(self.stream.cuda_stream),
-                                         C.byref(h)))
+        cfg = C.byref(SvBatchConfig.of(config)) if config is not None else None
+        check(lib().sv_batch_plan_create_ex(nc, nq, ops_arr, nops, npar, cfg, C.c_void_p(self.stream.cuda_stream),
+                                            C.byref(h)))
         self.h = h
         offs = (C.c_int64 * nc)()
         total = C.c_int64()
         check(lib().sv_batch_param_layout(self.h, offs, C.byref(total)))
         self.offsets = [int(x) for x in offs]
         self.total = int(total.value)
+
+    def info(self) -> dict:
+        """Effective configuration, persistent grid, tile tasks and passes."""
+        cfg = SvBatchConfig()
+        grid, tasks, passes = C.c_int(), C.c_int(), C.c_int()
+        check(lib().sv_batch_plan_info(self.h, C.byref(cfg), C.byref(grid), C.byref(tasks), C.byref(passes)))
+        return {"config": cfg.as_dict(), "grid": grid.value, "n_tasks": tasks.value, "n_passes": passes.value}
 
     def pack(self, params_list=None):
         """Device FP64 parameter block in the plan's layout."""
@@ -362,3 +414,49 @@ class BatchPlan:
             self.free()
         except Exception:
             pass
+
+
+def batch_autotune(circuits: Sequence, reps: int = 3, device=None, params_list=None):
+    """Time the batch under the library's staged search over launch shapes.
+    Returns (best config dict, list of trials {config, ms, max_dev})."""
+    import torch
+
+    circuits = list(circuits)
+    stream = torch.cuda.current_stream(device)
+    tables = [OpTable(c.ops) for c in circuits]
+    nc, nq, ops_arr, nops, npar = _batch_arrays(circuits, tables)
+    total = sum(c.n_params for c in circuits)
+    flat = np.zeros(max(total, 1), dtype=np.float64)
+    off = 0
+    for i, c in enumerate(circuits):      # the layout is the circuits' parameter rows in order
+        flat[off: off + c.n_params] = c.params if params_list is None else params_list[i]
+        off += c.n_params
+    dparams = torch.from_numpy(flat).to(device=stream.device)
+    best = SvBatchConfig()
+    cap = 64
+    trials = (SvBatchTrial * cap)()
+    nt = C.c_int()
+    check(lib().sv_batch_autotune(nc, nq, ops_arr, nops, npar, C.c_void_p(dparams.data_ptr()), reps,
+                                  C.c_void_p(stream.cuda_stream), C.byref(best), trials, cap, C.byref(nt)))
+    out = [{"config": trials[i].config.as_dict(), "ms": float(trials[i].ms), "max_dev": float(trials[i].max_dev)}
+           for i in range(min(nt.value, cap))]
+    return best.as_dict(), out
+
+
+def fused_autotune(state: "State", circuit, modes: Sequence[int] = (FUSED_FP32_MFMA, FUSED_VALU), reps: int = 2,
+                   params=None):
+    """Time the circuit on ``state`` as plain sweeps and as fused blocks of
+    each width in the allowed modes (the state is overwritten). Returns (best
+    choice dict, list of trial dicts); mode -1 means plain per-gate sweeps."""
+    table = OpTable(circuit.ops)
+    p = np.ascontiguousarray(np.asarray(circuit.params if params is None else params, dtype=np.float64))
+    mask = 0
+    for m in modes:
+        mask |= 1 << int(m)
+    best = SvFusionChoice()
+    cap = 16
+    trials = (SvFusionChoice * cap)()
+    nt = C.c_int()
+    check(lib().sv_fused_autotune(state.h, table.ptr, table.n, _dptr(p) if len(p) else None, len(p), mask, reps,
+                                  C.byref(best), trials, cap, C.byref(nt)))
+    return best.as_dict(), [trials[i].as_dict() for i in range(min(nt.value, cap))]

@@ -92,3 +92,21 @@ def test_gate_validation_host_only(svmod, n, targets, controls, code):
     ta = (C.c_int * max(1, len(targets)))(*targets)
     ca = (C.c_int * max(1, len(controls)))(*controls)
     assert L.sv_check_gate(n, ta, len(targets), ca, len(controls)) == code
+
+
+def test_batch_config_default_and_validation_host_only(svmod):
+    """The default launch shape, and out-of-range shapes rejected before any
+    device work (no GPU needed)."""
+    assert svmod.default_batch_config() == {"tile_bits": 14, "threads": 1024, "reg_min_bits": 12, "wg_per_cu": 0}
+    circ = Cc.ghz(3)
+    table = svmod.OpTable(circ.ops)
+    ops_arr = (C.POINTER(svmod.SvOp) * 1)(C.cast(table.arr, C.POINTER(svmod.SvOp)))
+    bad = [(9, 1024, 12, 0), (15, 1024, 12, 0), (12, 128, 12, 0), (12, 256, 3, 0), (12, 256, 16, 0),
+           (12, 256, 12, -1), (12, 256, 12, 17)]
+    for cfg in bad:
+        h = C.c_void_p()
+        st = svmod.lib().sv_batch_plan_create_ex(1, svmod._iarr([3]), ops_arr, svmod._iarr([table.n]),
+                                                 svmod._iarr([0]), C.byref(svmod.SvBatchConfig(*cfg)), None,
+                                                 C.byref(h))
+        assert st == 1 and not h.value, cfg
+        assert b"must be" in svmod.lib().sv_last_error()
