@@ -31,7 +31,7 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 1;
 constexpr int kXs = 33;              // FP32 layout Xs[64][33]: [k][col]
 constexpr int kXt = 68;              // BF16 layout Xt[32][68]: [col][k]
 constexpr int kWaveLds = 64 * kXs > 32 * kXt ? 64 * kXs : 32 * kXt;   // floats per wave
@@ -557,9 +557,9 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
             if (cols[c] == q) a.bit_col[b] = 1 << c;
     }
     a.amat = f.amat;
-    // persistent grid: two workgroups per CU are resident (registers, LDS)
+    // persistent grid: eight single-wave workgroups per CU are resident (registers)
     const uint64_t want = (a.n_tiles + kWaves - 1) / kWaves;
-    const uint64_t cap = (uint64_t)device_info().cu_count * 2;
+    const uint64_t cap = (uint64_t)device_info().cu_count * 8;
     const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     if (f.mode == SV_FUSED_FP32_MFMA)
         hipLaunchKernelGGL(k_fused<0>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);

@@ -33,11 +33,12 @@ def _device_name() -> str:
     return torch.cuda.get_device_name(torch.cuda.current_device())
 
 
-def structure_key(kind: str, circuits: Sequence, extra: str = "") -> str:
+def structure_key(kind: str, circuits: Sequence, extra: str = "", device: Optional[str] = None) -> str:
     """Hash of what the timing depends on: per circuit the qubit count and
-    every gate's kind, targets and controls; plus the device name."""
+    every gate's kind, targets and controls; plus the device name (the
+    current GPU's unless given)."""
     h = hashlib.sha1()
-    h.update(f"{kind}|{_device_name()}|{extra}".encode())
+    h.update(f"{kind}|{device if device is not None else _device_name()}|{extra}".encode())
     for c in circuits:
         h.update(f"n{c.n}:".encode())
         for op in c.ops:
