@@ -61,6 +61,13 @@ def bind(lib: C.CDLL) -> C.CDLL:
     u64p = C.POINTER(C.c_uint64)
     lib.orc_apply_pauli_sum.argtypes = [dp, C.c_int, C.c_int, u64p, u64p, dp, dp]
     lib.orc_apply_pauli_sum.restype = None
+    lib.orc_prob_cdf.argtypes = [dp, C.c_int, dp]
+    lib.orc_prob_cdf.restype = None
+    i64p = C.POINTER(C.c_int64)
+    lib.orc_sample_exact.argtypes = [dp, C.c_int, dp, C.c_int64, i64p]
+    lib.orc_sample_exact.restype = None
+    lib.orc_sample_gaussian.argtypes = [dp, C.c_int, dp, C.c_double, dp]
+    lib.orc_sample_gaussian.restype = None
     return lib
 
 
@@ -301,3 +308,34 @@ def grad_adjoint(circuit, terms: Sequence[Term], params: np.ndarray | None = Non
     e0 = basis_state(n, 0)
     drift = float(np.linalg.norm(psi - e0))
     return L, grad, drift
+
+
+# ------------------------------------------------------------------ shots
+
+def prob_cdf(psi: np.ndarray, n: int) -> np.ndarray:
+    """cdf[b] = sum_{c <= b} |psi_c|^2 (compensated running sum)."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.empty(1 << n, dtype=np.float64)
+    load().orc_prob_cdf(_dptr(psi.view(np.float64)), n, _dptr(out))
+    return out
+
+
+def sample_exact(psi: np.ndarray, n: int, uniforms: np.ndarray) -> np.ndarray:
+    """Exact shots (Sec. 4.3.1): for each u the smallest b with
+    cdf[b] > u T (clamped below T); -1 for a zero state."""
+    cdf = prob_cdf(psi, n)
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    out = np.empty(len(u), dtype=np.int64)
+    load().orc_sample_exact(_dptr(cdf), n, _dptr(u), len(u), out.ctypes.data_as(C.POINTER(C.c_int64)))
+    return out
+
+
+def sample_gaussian(psi: np.ndarray, n: int, normals: np.ndarray, shots: float) -> np.ndarray:
+    """Gaussian shot histogram (Sec. 4.3.2): y = shots p + sqrt(shots) D S z
+    with the Householder reflection S (z's last entry is taken as 0)."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    z = np.ascontiguousarray(normals, dtype=np.float64)
+    assert len(z) == 1 << n
+    y = np.empty(1 << n, dtype=np.float64)
+    load().orc_sample_gaussian(_dptr(psi.view(np.float64)), n, _dptr(z), float(shots), _dptr(y))
+    return y

@@ -325,3 +325,79 @@ void orc_apply_pauli_sum(const cplx* psi, int n, int nt, const uint64_t* xm, con
         out[b] = acc;
     }
 }
+
+/* ---------------------------------------------------------------- shots */
+
+/* Running sum of the Z-basis probabilities (Sec. 2.2.1): cdf[b] =
+ * sum_{c <= b} |psi_c|^2, one Neumaier-compensated sum in index order. */
+void orc_prob_cdf(const cplx* psi, int n, double* cdf)
+{
+    const int64_t N = (int64_t)1 << n;
+    neum a = {0, 0};
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        neum_add(&a, re * re + im * im);
+        cdf[b] = neum_val(&a);
+    }
+}
+
+/* Exact shot sampling (Sec. 4.3.1): each shot s is a draw of the basis index
+ * b with probability p_b = |psi_b|^2 / T, T = cdf[N-1], by inverse CDF: the
+ * smallest b with cdf[b] > t_s, t_s = u_s T clamped below T (so a u_s that
+ * rounds up to T takes the last index of non-zero probability). The counts
+ * of the returned indices over the shots are one draw of the multinomial
+ * M(shots, p). A state of zero norm returns -1 for every shot. */
+void orc_sample_exact(const double* cdf, int n, const double* u, int64_t shots, int64_t* out)
+{
+    const int64_t N = (int64_t)1 << n;
+    const double T = cdf[N - 1];
+    for (int64_t s = 0; s < shots; ++s) {
+        double t = u[s] * T;
+        if (t >= T) t = nextafter(T, 0.0);
+        /* binary search for the first cdf > t */
+        int64_t lo = 0, hi = N;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > t) hi = mid;
+            else lo = mid + 1;
+        }
+        out[s] = lo < N ? lo : -1;
+    }
+}
+
+/* Gaussian approximation of the shot histogram (Sec. 4.3.2), as the
+ * reparameterised draw y = shots p + sqrt(shots) D S z with
+ *   p = |psi|^2 / T, u = sqrt(p), D = diag(u),
+ *   v = (e - u) / ||e - u||, e the last basis vector (v = 0 when u = e),
+ *   S = I - 2 v v^T (the Householder reflection that maps e to u),
+ *   z = (z_0, ..., z_{N-2}, 0).
+ * S z is applied as z - 2 v (v . z). Sums are Neumaier-compensated. */
+void orc_sample_gaussian(const cplx* psi, int n, const double* z, double shots, double* y)
+{
+    const int64_t N = (int64_t)1 << n;
+    neum tn = {0, 0};
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        neum_add(&tn, re * re + im * im);
+    }
+    const double T = neum_val(&tn);
+    /* ||e - u||^2 and v . z (z_last = 0) */
+    neum r2 = {0, 0}, vz = {0, 0};
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        const double u = sqrt((re * re + im * im) / T);
+        const double d = (b == N - 1 ? 1.0 : 0.0) - u;
+        neum_add(&r2, d * d);
+        if (b < N - 1) neum_add(&vz, d * z[b]);
+    }
+    const double r = sqrt(neum_val(&r2));
+    const double vdotz = r > 0 ? neum_val(&vz) / r : 0.0;
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        const double p = (re * re + im * im) / T;
+        const double u = sqrt(p);
+        const double v = r > 0 ? ((b == N - 1 ? 1.0 : 0.0) - u) / r : 0.0;
+        const double zb = b < N - 1 ? z[b] : 0.0;
+        y[b] = shots * p + sqrt(shots) * u * (zb - 2.0 * v * vdotz);
+    }
+}

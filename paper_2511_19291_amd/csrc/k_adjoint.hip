@@ -173,7 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_adj(KAdj a, double* part)
 
 // lam[c] = sum_t coeff_t i^{y_t} (-1)^{|(c ^ x_t) & z_t|} psi[c ^ x_t]
 // (O psi for O = sum_t coeff_t P_t, written as a gather so every output
-// amplitude is produced by one thread).
+// amplitude is produced by one thread). Terms arrive sorted by x_mask: each
+// distinct x_mask reads psi[c ^ x] once and applies the summed factor of its
+// terms.
 __global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t N, const PauliTermDev* terms, int nt)
 {
     const int row = blockIdx.y;
@@ -181,21 +183,24 @@ __global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t
     float2* lam = mrow(rl, row);
     for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (uint64_t)gridDim.x * kBlock) {
         double re = 0.0, im = 0.0;
-        for (int t = 0; t < nt; ++t) {
-            const PauliTermDev tm = terms[t];
-            const uint64_t src = c ^ tm.x_mask;
+        int t = 0;
+        while (t < nt) {
+            const uint64_t xm = terms[t].x_mask;
+            const uint64_t src = c ^ xm;
             const float2 v = psi[src];
-            double s = (__popcll(src & tm.z_mask) & 1) ? -tm.coeff : tm.coeff;
-            // multiply by i^y
-            double vr = v.x, vi = v.y;
-            switch (tm.y_count & 3) {
-            case 0: break;
-            case 1: { const double t0 = vr; vr = -vi; vi = t0; } break;
-            case 2: vr = -vr; vi = -vi; break;
-            case 3: { const double t0 = vr; vr = vi; vi = -t0; } break;
+            double fr = 0.0, fi = 0.0;       // sum of coeff * sign * i^y over the terms of this x_mask
+            for (; t < nt && terms[t].x_mask == xm; ++t) {
+                const PauliTermDev tm = terms[t];
+                const double sg = (__popcll(src & tm.z_mask) & 1) ? -tm.coeff : tm.coeff;
+                switch (tm.y_count & 3) {
+                case 0: fr += sg; break;
+                case 1: fi += sg; break;
+                case 2: fr -= sg; break;
+                default: fi -= sg; break;
+                }
             }
-            re += s * vr;
-            im += s * vi;
+            re += fr * v.x - fi * v.y;
+            im += fr * v.y + fi * v.x;
         }
         lam[c] = make_float2((float)re, (float)im);
     }

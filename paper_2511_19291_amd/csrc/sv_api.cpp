@@ -308,6 +308,9 @@ void upload_terms(sv_state s, const sv_pauli_term* obs, int n_obs, PauliTermDev*
         t[i].y_count = __builtin_popcountll(obs[i].x_mask & obs[i].z_mask);
         t[i].pad = 0;
     }
+    // grouped by x_mask: the gather reads each source amplitude once per group
+    std::stable_sort(t.begin(), t.end(),
+                     [](const PauliTermDev& a, const PauliTermDev& b) { return a.x_mask < b.x_mask; });
     const size_t bytes = t.size() * sizeof(PauliTermDev);
     if (bytes > s->dterms_cap) {
         if (s->dterms) {

@@ -33,6 +33,12 @@ MUTANTS = {
     "z_all bit test": ("neum_add(&acc[i], ((b >> i) & 1) ? -pb : pb);", "neum_add(&acc[i], ((b >> (n - 1 - i)) & 1) ? -pb : pb);"),
     "derivative scale": ("double dc = -0.5 * sin(prm[0] / 2), ds = 0.5 * cos(prm[0] / 2);",
                          "double dc = -sin(prm[0] / 2), ds = cos(prm[0] / 2);"),
+    "cdf tie rule": ("if (cdf[mid] > t) hi = mid;", "if (cdf[mid] >= t) hi = mid;"),
+    "householder factor": ("y[b] = shots * p + sqrt(shots) * u * (zb - 2.0 * v * vdotz);",
+                           "y[b] = shots * p + sqrt(shots) * u * (zb - v * vdotz);"),
+    "reflection target": ("const double v = r > 0 ? ((b == N - 1 ? 1.0 : 0.0) - u) / r : 0.0;",
+                          "const double v = r > 0 ? ((b == 0 ? 1.0 : 0.0) - u) / r : 0.0;"),
+    "last normal kept": ("const double zb = b < N - 1 ? z[b] : 0.0;", "const double zb = z[b];"),
 }
 
 
@@ -69,6 +75,27 @@ def _pins_pass() -> bool:
         p = np.abs(psi) ** 2
         b = np.arange(1 << n)
         if any(abs(z[i] - np.sum(p * (1 - 2 * ((b >> i) & 1)))) > 1e-12 for i in range(n)):
+            return False
+        # shots: exact draws vs the library routine of the definition (with a
+        # zero-probability first index and u = 0), the Gaussian draw vs the
+        # explicit reflection matrix
+        pz = np.abs(psi) ** 2
+        pz[0] = 0.0
+        psz = np.sqrt(pz)
+        us = np.concatenate([[0.0], rng.random(200)])
+        cs = np.cumsum(pz)
+        if not np.array_equal(oracle.sample_exact(psz, n, us), np.searchsorted(cs, us * cs[-1], side="right")):
+            return False
+        zs = rng.normal(size=1 << n)
+        pp = pz / pz.sum()
+        uu = np.sqrt(pp)
+        e = np.zeros(1 << n)
+        e[-1] = 1.0
+        vv = (e - uu) / np.linalg.norm(e - uu)
+        zz = zs.copy()
+        zz[-1] = 0.0
+        want = 100.0 * pp + 10.0 * uu * ((np.eye(1 << n) - 2 * np.outer(vv, vv)) @ zz)
+        if np.max(np.abs(oracle.sample_gaussian(psz, n, zs, 100.0) - want)) > 1e-9:
             return False
         circ = C.rxry_ring(4, 2, 8)
         terms = C.z_sum_terms(4)
