@@ -271,6 +271,8 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
                 "tune_s": round(time.perf_counter() - t0, 2),
             }
         fused[f"brickwork{nq}"] = entry
+        if nq == n:
+            res["shots"] = shots_extra(st, circ, blocks, stream)
         st.free()
         del st
         torch.cuda.empty_cache()
@@ -341,6 +343,43 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     }
     print("# batched done", file=sys.stderr, flush=True)
     return res
+
+
+def shots_extra(st, circ, blocks, stream) -> dict:
+    """Shot noise (Sec. 4.3) on the 30-qubit brickwork output state: 2^20
+    exact draws (inverse CDF) and one Gaussian histogram of 10^9 shots
+    (all 2^n bins)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_19291_amd import sv
+
+    n = st.n
+    st.reset()
+    st.apply_fused(blocks, sv.FUSED_FP32_MFMA)
+    rng = np.random.default_rng(41)
+    nshots = 1 << 20
+    u = torch.as_tensor(rng.random(nshots), device=st.tensor.device)
+    st.sample_exact(u)
+    exact_ms = min(_timed_ms(lambda: st.sample_exact(u), stream) for _ in range(3))
+    g = torch.Generator(device=st.tensor.device)
+    g.manual_seed(5)
+    z = torch.randn(1 << n, dtype=torch.float64, device=st.tensor.device, generator=g)
+    y = st.sample_gaussian(z, 1e9)
+    gauss_ms = min(_timed_ms(lambda: st.sample_gaussian(z, 1e9), stream) for _ in range(3))
+    ysum = float(y.sum())
+    del y, z, u
+    torch.cuda.empty_cache()
+    print("# shots done", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{n}-qubit brickwork output state (fused FP32), exact: {nshots} draws; "
+                    "gaussian: 1e9 shots over all 2^n bins",
+        "exact_ms": round(exact_ms, 3), "exact_shots_per_s": round(nshots / (exact_ms / 1e3), 1),
+        "exact_alg_GBps": round(16 * (1 << n) / (exact_ms / 1e3) / 1e9, 1),
+        "gaussian_ms": round(gauss_ms, 3),
+        "gaussian_alg_GBps": round(40 * (1 << n) / (gauss_ms / 1e3) / 1e9, 1),
+        "gaussian_sum_minus_shots": ysum - 1e9,
+    }
 
 
 def cpu_baseline(circ, seconds: float) -> dict:

@@ -227,6 +227,49 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
                           const sv_pauli_term* obs, int n_obs, void* lambda_buffer,
                           double* grad_out, double* loss_out, double* drift_out);
 
+/* ----------------------------------------------------------------- shots */
+
+/* Exact shot sampling (Sec. 4.3.1). Draw n_shots basis indices from row
+ * `row`, each with probability p_b = |psi_b|^2 / T, T = sum_c |psi_c|^2:
+ *   out[s] = the smallest b with CDF(b) > t_s, CDF(b) = sum_{c <= b} |psi_c|^2,
+ *   t_s = u_s * T, clamped to the largest double below T
+ * (inverse-CDF sampling; the counts of the returned indices over all shots
+ * are one draw of the multinomial M(n_shots, p)).
+ *   dev_uniforms: device doubles [n_shots] in [0, 1): the random numbers of
+ *     the draws, from the caller's generator (read only).
+ *   dev_out: device int64 [n_shots], written; -1 for every shot of a state
+ *     of zero norm.
+ * The running sums are FP64 in a fixed blocking and order (deterministic);
+ * they differ from an exact sum by rounding only, so a u_s within ~1e-15
+ * (relative) of a CDF step may select the neighbouring index. Work: one read
+ * sweep over the row plus one read of each 4096-amplitude block that holds a
+ * shot. Scratch device memory (about 12 B per 4096 amplitudes + 16 B per
+ * shot) is kept in the state. Asynchronous on the state's stream.
+ * Errors: SV_ERR_INVALID_ARGUMENT (row out of range, n_shots outside
+ * 0..2^31-1, NULL pointers), SV_ERR_OUT_OF_MEMORY, SV_ERR_HIP. */
+sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64_t n_shots,
+                          int64_t* dev_out);
+
+/* Gaussian approximation of the shot histogram (Sec. 4.3.2), the
+ * reparameterised (differentiable) draw
+ *   y = shots p + sqrt(shots) D S z,
+ * p = |psi|^2 / T for row `row`, D = diag(sqrt p), S = I - 2 v v^T with
+ * v = (e - sqrt p) / ||e - sqrt p||, e the last basis vector (v = 0 when
+ * sqrt p = e), z = (z_0, ..., z_{N-2}, 0). S is the Householder reflection
+ * that maps e to sqrt p, so S z has covariance I - sqrt p sqrt p^T and y has
+ * the multinomial's mean shots p and covariance shots (diag p - p p^T);
+ * sum_b y_b = shots up to rounding.
+ *   dev_normals: device doubles [2^n], 16-byte aligned: standard normal
+ *     draws of the caller (entry 2^n - 1 is not read).
+ *   shots: the number of shots n (> 0, need not be an integer).
+ *   dev_y: device doubles [2^n], 16-byte aligned, written.
+ * FP64 throughout; deterministic. Two sweeps (a reduction, then y).
+ * Asynchronous on the state's stream.
+ * Errors: SV_ERR_INVALID_ARGUMENT (row, shots <= 0, NULL or misaligned
+ * pointers), SV_ERR_HIP. */
+sv_status sv_sample_gaussian(sv_state s, int row, const double* dev_normals, double shots,
+                             double* dev_y);
+
 /* -------------------------------------------------------------- batching */
 
 typedef struct sv_batch_plan_s* sv_batch_plan;

@@ -1,0 +1,393 @@
+// k_shots.hip -- shot noise on the GPU state (Sec. 4.3).
+//
+// Exact sampling (Sec. 4.3.1). A shot is a draw of the basis index b with
+// probability p_b = |psi_b|^2 / T; given the caller's uniform u it is the
+// smallest b whose running probability sum exceeds u T (u T clamped below
+// T). On the GPU:
+//   1. block sums: the state is cut into blocks of 2^12 amplitudes and each
+//      block's probability mass is summed in FP64 (one read sweep);
+//   2. an inclusive scan of the block sums in a fixed order (so T and every
+//      block's offset are deterministic);
+//   3. each shot finds its block by binary search over the scanned sums
+//      (an L2-resident array) and is bucketed by block (counting sort);
+//   4. each block that holds at least one shot is read once more, its
+//      in-block running sum is built in LDS in a fixed order, and each of its
+//      shots finds its index there by binary search.
+// The counts of the indices over all shots are one draw of the multinomial
+// M(shots, p). This is the paper's hierarchical view restricted to one
+// device: the blocks play the role of the groups whose masses q_j are known
+// first, and the within-group draw is conditional on the group.
+//
+// Gaussian approximation (Sec. 4.3.2): y = shots p + sqrt(shots) D S z with
+// D = diag(sqrt p), S = I - 2 v v^T the reflection that maps the last basis
+// vector e to u = sqrt p (v = (e - u) / ||e - u||), z_last = 0. Applied
+// matrix-free: S z = z - 2 v (v . z). One FP64 reduction sweep for T and
+// sum_b |psi_b| z_b, then one elementwise sweep.
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+constexpr int kShotBits = 12;          // amplitudes per block
+constexpr int kST = 256;               // threads per workgroup of the shot kernels
+constexpr int kScanChunk = kST * 8;    // elements per workgroup of the scan
+
+__device__ __forceinline__ double prob(float2 v) { return (double)v.x * v.x + (double)v.y * v.y; }
+
+// Fixed-order sum over the workgroup (result valid in every thread).
+__device__ double wg_sum256(double v, double* sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// 1. probability mass of each block of 2^bb amplitudes (bb <= kShotBits)
+__global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ psi, int bb, double* __restrict__ mass)
+{
+    __shared__ double sh[kST / 64];
+    const uint64_t base = (uint64_t)blockIdx.x << bb;
+    const uint32_t bs = 1u << bb;
+    double acc = 0.0;
+    if (bs >= 2) {
+        const float4* p4 = reinterpret_cast<const float4*>(psi + base);
+        for (uint32_t i = threadIdx.x; i < bs / 2; i += kST) {
+            const float4 v = p4[i];
+            acc += prob(make_float2(v.x, v.y)) + prob(make_float2(v.z, v.w));
+        }
+    } else if (threadIdx.x == 0) {
+        acc = prob(psi[base]);
+    }
+    const double s = wg_sum256(acc, sh);
+    if (threadIdx.x == 0) mass[blockIdx.x] = s;
+}
+
+// 2. inclusive scan, chunks of kScanChunk elements: thread t owns the
+// elements [8t, 8t + 8) of its chunk (sequential), then a Hillis-Steele scan
+// of the 256 thread totals. Writes the chunk's total to tot[chunk].
+template <class T>
+__global__ __launch_bounds__(kST) void k_scan_chunk(T* __restrict__ x, uint64_t n, T* __restrict__ tot)
+{
+    __shared__ T sh[kST];
+    const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * 8;
+    T v[8];
+    T run = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        v[i] = c0 + i < n ? x[c0 + i] : (T)0;
+        run += v[i];
+        v[i] = run;
+    }
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < kST; off <<= 1) {
+        const T add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : (T)0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const T before = threadIdx.x > 0 ? sh[threadIdx.x - 1] : (T)0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (c0 + i < n) x[c0 + i] = before + v[i];
+    if (threadIdx.x == kST - 1 && tot) tot[blockIdx.x] = sh[kST - 1];
+}
+
+template <class T>
+__global__ __launch_bounds__(kST) void k_scan_add(T* __restrict__ x, uint64_t n, const T* __restrict__ tot)
+{
+    if (blockIdx.x == 0) return;
+    const T off = tot[blockIdx.x - 1];
+    const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kScanChunk; i += kST)
+        if (c0 + i < n) x[c0 + i] += off;
+}
+
+__global__ __launch_bounds__(kST) void k_zero_u32(uint32_t* __restrict__ x, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kST + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kST) x[i] = 0;
+}
+
+// 3a. block of each shot: the first block whose inclusive mass exceeds t
+__global__ __launch_bounds__(kST) void k_shot_locate(const double* __restrict__ pinc, uint32_t nb,
+                                                     const double* __restrict__ u, int64_t shots,
+                                                     uint32_t* __restrict__ blk, double* __restrict__ rem,
+                                                     uint32_t* __restrict__ cnt, int64_t* __restrict__ out)
+{
+    const int64_t s = (int64_t)blockIdx.x * kST + threadIdx.x;
+    if (s >= shots) return;
+    const double T = pinc[nb - 1];
+    double t = u[s] * T;
+    if (t >= T) t = nextafter(T, 0.0);
+    uint32_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (pinc[mid] > t) hi = mid;
+        else lo = mid + 1;
+    }
+    if (lo == nb) {
+        // zero state: no index has probability
+        blk[s] = nb;
+        out[s] = -1;
+        return;
+    }
+    blk[s] = lo;
+    rem[s] = t - (lo > 0 ? pinc[lo - 1] : 0.0);
+    atomicAdd(cnt + lo, 1u);
+}
+
+// 3b. counting sort of the shots by block (order inside a bucket is free:
+// each shot's result depends on its own uniform only)
+__global__ __launch_bounds__(kST) void k_shot_scatter(const uint32_t* __restrict__ blk, int64_t shots, uint32_t nb,
+                                                      const uint32_t* __restrict__ cinc, const uint32_t* __restrict__ cnt,
+                                                      uint32_t* __restrict__ fill, uint32_t* __restrict__ order)
+{
+    const int64_t s = (int64_t)blockIdx.x * kST + threadIdx.x;
+    if (s >= shots) return;
+    const uint32_t b = blk[s];
+    if (b >= nb) return;
+    const uint32_t pos = cinc[b] - cnt[b] + atomicAdd(fill + b, 1u);
+    order[pos] = (uint32_t)s;
+}
+
+// 4. per block with shots: in-block running sum in LDS, then each shot's
+// index by binary search (first running sum > rem; if rounding leaves rem at
+// or above the block's own total, the block's last index of non-zero
+// probability)
+__global__ __launch_bounds__(kST) void k_shot_resolve(const float2* __restrict__ psi, int bb, uint32_t nb,
+                                                      const uint32_t* __restrict__ cinc, const uint32_t* __restrict__ cnt,
+                                                      const uint32_t* __restrict__ order, const double* __restrict__ rem,
+                                                      int64_t* __restrict__ out)
+{
+    __shared__ double ps[1 << kShotBits];
+    __shared__ double sh[kST];
+    __shared__ int s_last;
+    const uint32_t bs = 1u << bb;
+    const uint32_t per = bs > kST ? bs / kST : 1;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint32_t nshot = cnt[b];
+        if (nshot == 0) continue;
+        const uint64_t base = (uint64_t)b << bb;
+        for (uint32_t i = threadIdx.x; i < bs; i += kST) ps[i] = prob(psi[base + i]);
+        if (threadIdx.x == 0) s_last = -1;
+        __syncthreads();
+        // thread t owns [t per, (t + 1) per) (threads beyond the block own nothing)
+        const uint32_t i0 = threadIdx.x * per;
+        double run = 0.0;
+        int last = -1;
+        if (i0 < bs)
+            for (uint32_t i = 0; i < per; ++i) {
+                const double p = ps[i0 + i];
+                if (p > 0.0) last = (int)(i0 + i);
+                run += p;
+                ps[i0 + i] = run;
+            }
+        if (last >= 0) atomicMax(&s_last, last);
+        sh[threadIdx.x] = run;
+        __syncthreads();
+        for (int off = 1; off < kST; off <<= 1) {
+            const double add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0.0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        const double before = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+        if (i0 < bs)
+            for (uint32_t i = 0; i < per; ++i) ps[i0 + i] += before;
+        __syncthreads();
+        const uint32_t first = cinc[b] - nshot;
+        for (uint32_t j = threadIdx.x; j < nshot; j += kST) {
+            const uint32_t s = order[first + j];
+            const double r = rem[s];
+            uint32_t lo = 0, hi = bs;
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (ps[mid] > r) hi = mid;
+                else lo = mid + 1;
+            }
+            const int idx = lo < bs ? (int)lo : s_last;
+            out[s] = idx >= 0 ? (int64_t)(base + (uint32_t)idx) : -1;
+        }
+        __syncthreads();
+    }
+}
+
+// Gaussian: partial sums of T = sum |psi|^2 and A = sum_{b < N-1} |psi_b| z_b
+__global__ __launch_bounds__(kST) void k_gauss_partial(const float2* __restrict__ psi, const double* __restrict__ z,
+                                                       uint64_t N, double* __restrict__ part)
+{
+    __shared__ double sh[kST / 64];
+    double t = 0.0, a = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kST + threadIdx.x; i < N / 2; i += (uint64_t)gridDim.x * kST) {
+        const float4 v = reinterpret_cast<const float4*>(psi)[i];
+        const double2 zz = reinterpret_cast<const double2*>(z)[i];
+        const double p0 = prob(make_float2(v.x, v.y)), p1 = prob(make_float2(v.z, v.w));
+        t += p0 + p1;
+        a += sqrt(p0) * zz.x;
+        if (2 * i + 1 < N - 1) a += sqrt(p1) * zz.y;
+    }
+    const double st = wg_sum256(t, sh);
+    const double sa = wg_sum256(a, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = st;
+        part[gridDim.x + blockIdx.x] = sa;
+    }
+}
+
+// scalars: [0] T, [1] r = ||e - u||, [2] v . z
+__global__ __launch_bounds__(kST) void k_gauss_final(const float2* __restrict__ psi, uint64_t N,
+                                                     const double* __restrict__ part, int g, double* __restrict__ sc)
+{
+    __shared__ double sh[kST / 64];
+    double t = 0.0, a = 0.0;
+    for (int i = threadIdx.x; i < g; i += kST) {
+        t += part[i];
+        a += part[g + i];
+    }
+    const double T = wg_sum256(t, sh);
+    const double A = wg_sum256(a, sh);
+    if (threadIdx.x == 0) {
+        const double pl = prob(psi[N - 1]);
+        const double ul = sqrt(pl / T);
+        // ||e - u||^2 = sum_{b < N-1} u_b^2 + (1 - u_last)^2
+        const double r2 = (T - pl) / T + (1.0 - ul) * (1.0 - ul);
+        const double r = sqrt(r2);
+        sc[0] = T;
+        sc[1] = r;
+        // v . z = sum_{b < N-1} (-u_b / r) z_b (z_last = 0)
+        sc[2] = r > 0.0 ? -(A / sqrt(T)) / r : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kST) void k_gauss_y(const float2* __restrict__ psi, const double* __restrict__ z,
+                                                 uint64_t N, double shots, const double* __restrict__ sc,
+                                                 double* __restrict__ y)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kST + threadIdx.x;
+    if (i >= N / 2) return;
+    const double T = sc[0], r = sc[1], vz = sc[2];
+    const double sq = sqrt(shots);
+    const float4 v = reinterpret_cast<const float4*>(psi)[i];
+    const double2 zz = reinterpret_cast<const double2*>(z)[i];
+    double out[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint64_t b = 2 * i + h;
+        const double p = prob(h ? make_float2(v.z, v.w) : make_float2(v.x, v.y)) / T;
+        const double u = sqrt(p);
+        const bool lastb = b == N - 1;
+        const double vb = r > 0.0 ? ((lastb ? 1.0 : 0.0) - u) / r : 0.0;
+        const double zb = lastb ? 0.0 : (h ? zz.y : zz.x);
+        out[h] = shots * p + sq * u * (zb - 2.0 * vb * vz);
+    }
+    reinterpret_cast<double2*>(y)[i] = make_double2(out[0], out[1]);
+}
+
+template <class T>
+void scan_inclusive(T* x, uint64_t n, T* tmp, hipStream_t st)
+{
+    const uint64_t chunks = (n + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_chunk<T>, dim3((unsigned)chunks), dim3(kST), 0, st, x, n, chunks > 1 ? tmp : (T*)nullptr);
+    SV_HIP(hipGetLastError());
+    if (chunks > 1) {
+        scan_inclusive<T>(tmp, chunks, tmp + chunks, st);
+        hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)chunks), dim3(kST), 0, st, x, n, (const T*)tmp);
+        SV_HIP(hipGetLastError());
+    }
+}
+
+// room for the recursive scan's chunk totals of an n-element scan
+uint64_t scan_tmp(uint64_t n)
+{
+    uint64_t t = 0;
+    while (n > (uint64_t)kScanChunk) {
+        n = (n + kScanChunk - 1) / kScanChunk;
+        t += n;
+    }
+    return t + 1;
+}
+
+int shot_block_bits(int n) { return n < kShotBits ? n : kShotBits; }
+
+}  // namespace
+
+size_t shot_scratch_bytes(int n, int64_t shots)
+{
+    const uint64_t nb = 1ull << (n - shot_block_bits(n));
+    const uint64_t st = scan_tmp(nb);
+    return (nb + st) * sizeof(double)                 // scanned masses + scan totals
+           + (3 * nb + st) * sizeof(uint32_t)         // counts, fill, (count scan totals)
+           + (uint64_t)shots * (sizeof(double) + 2 * sizeof(uint32_t)) + 64;
+}
+
+void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
+{
+    const int bb = shot_block_bits(a.n);
+    const uint64_t nb = 1ull << (a.n - bb);
+    const uint64_t stmp = scan_tmp(nb);
+    char* p = static_cast<char*>(a.scratch);
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += (bytes + 7) & ~size_t(7);
+        return q;
+    };
+    double* mass = reinterpret_cast<double*>(take(nb * sizeof(double)));
+    double* dtmp = reinterpret_cast<double*>(take(stmp * sizeof(double)));
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(take(nb * sizeof(uint32_t)));
+    uint32_t* cinc = reinterpret_cast<uint32_t*>(take(nb * sizeof(uint32_t)));
+    uint32_t* fill = reinterpret_cast<uint32_t*>(take(nb * sizeof(uint32_t)));
+    uint32_t* utmp = reinterpret_cast<uint32_t*>(take(stmp * sizeof(uint32_t)));
+    double* rem = reinterpret_cast<double*>(take((size_t)a.shots * sizeof(double)));
+    uint32_t* blk = reinterpret_cast<uint32_t*>(take((size_t)a.shots * sizeof(uint32_t)));
+    uint32_t* order = reinterpret_cast<uint32_t*>(take((size_t)a.shots * sizeof(uint32_t)));
+
+    hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, mass);
+    SV_HIP(hipGetLastError());
+    scan_inclusive<double>(mass, nb, dtmp, st);
+    if (a.shots == 0) return;
+    const unsigned zg = (unsigned)std::min<uint64_t>((nb + kST - 1) / kST, 4096);
+    hipLaunchKernelGGL(k_zero_u32, dim3(zg), dim3(kST), 0, st, cnt, nb);
+    hipLaunchKernelGGL(k_zero_u32, dim3(zg), dim3(kST), 0, st, fill, nb);
+    SV_HIP(hipGetLastError());
+    const unsigned sg = (unsigned)((a.shots + kST - 1) / kST);
+    hipLaunchKernelGGL(k_shot_locate, dim3(sg), dim3(kST), 0, st, mass, (uint32_t)nb, a.u, a.shots, blk, rem, cnt,
+                       a.out);
+    SV_HIP(hipGetLastError());
+    SV_HIP(hipMemcpyAsync(cinc, cnt, nb * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    scan_inclusive<uint32_t>(cinc, nb, utmp, st);
+    hipLaunchKernelGGL(k_shot_scatter, dim3(sg), dim3(kST), 0, st, blk, a.shots, (uint32_t)nb, cinc, cnt, fill, order);
+    SV_HIP(hipGetLastError());
+    const unsigned rg = (unsigned)std::min<uint64_t>(nb, (uint64_t)device_info().cu_count * 8);
+    hipLaunchKernelGGL(k_shot_resolve, dim3(rg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, cnt, order, rem,
+                       a.out);
+    SV_HIP(hipGetLastError());
+}
+
+uint64_t gauss_scratch_doubles(int n)
+{
+    (void)n;
+    return 2 * (uint64_t)device_info().cu_count * 8 + 4;
+}
+
+void launch_sample_gaussian(const GaussLaunch& a, hipStream_t st)
+{
+    const uint64_t N = 1ull << a.n;
+    const int g = (int)std::max<uint64_t>(1, std::min<uint64_t>((N / 2 + kST - 1) / kST, (uint64_t)device_info().cu_count * 8));
+    double* part = a.scratch;
+    double* sc = a.scratch + 2 * g;
+    hipLaunchKernelGGL(k_gauss_partial, dim3(g), dim3(kST), 0, st, a.psi, a.z, N, part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gauss_final, dim3(1), dim3(kST), 0, st, a.psi, N, part, g, sc);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gauss_y, dim3((unsigned)((N / 2 + kST - 1) / kST)), dim3(kST), 0, st, a.psi, a.z, N, a.shots,
+                       sc, a.y);
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace sv

@@ -667,6 +667,48 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
     });
 }
 
+sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64_t n_shots, int64_t* dev_out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(row >= 0 && row < s->batch, SV_ERR_INVALID_ARGUMENT, "row out of range");
+        need(n_shots >= 0 && n_shots <= 2147483647ll, SV_ERR_INVALID_ARGUMENT, "n_shots must be 0..2^31-1");
+        need(n_shots == 0 || (dev_uniforms != nullptr && dev_out != nullptr), SV_ERR_INVALID_ARGUMENT,
+             "NULL device pointer");
+        const size_t bytes = shot_scratch_bytes(s->n, n_shots);
+        ensure_scratch(s, (bytes + sizeof(double) - 1) / sizeof(double));
+        ShotLaunch a{};
+        a.psi = s->psi + (uint64_t)row * s->N;
+        a.n = s->n;
+        a.u = dev_uniforms;
+        a.shots = n_shots;
+        a.out = dev_out;
+        a.scratch = s->scratch;
+        launch_sample_exact(a, s->stream);
+    });
+}
+
+sv_status sv_sample_gaussian(sv_state s, int row, const double* dev_normals, double shots, double* dev_y)
+{
+    return guarded([&] {
+        check_state(s);
+        need(row >= 0 && row < s->batch, SV_ERR_INVALID_ARGUMENT, "row out of range");
+        need(shots > 0 && std::isfinite(shots), SV_ERR_INVALID_ARGUMENT, "shots must be positive");
+        need(dev_normals != nullptr && dev_y != nullptr, SV_ERR_INVALID_ARGUMENT, "NULL device pointer");
+        need(((uintptr_t)dev_normals & 15) == 0 && ((uintptr_t)dev_y & 15) == 0, SV_ERR_INVALID_ARGUMENT,
+             "device arrays must be 16-byte aligned");
+        ensure_scratch(s, gauss_scratch_doubles(s->n));
+        GaussLaunch a{};
+        a.psi = s->psi + (uint64_t)row * s->N;
+        a.n = s->n;
+        a.z = dev_normals;
+        a.shots = shots;
+        a.y = dev_y;
+        a.scratch = s->scratch;
+        launch_sample_gaussian(a, s->stream);
+    });
+}
+
 sv_status sv_stream_copy(void* dst, const void* src, uint64_t bytes, void* stream)
 {
     return guarded([&] {

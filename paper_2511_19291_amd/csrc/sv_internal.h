@@ -117,6 +117,29 @@ struct PauliTermDev {
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
                             hipStream_t st);
 
+// ------------------------------------------------------------ shots
+struct ShotLaunch {
+    const float2* psi;        // one row of 2^n amplitudes
+    int n;
+    const double* u;          // device uniforms [shots]
+    int64_t shots;
+    int64_t* out;             // device indices [shots]
+    void* scratch;            // shot_scratch_bytes(n, shots) bytes
+};
+size_t shot_scratch_bytes(int n, int64_t shots);
+void launch_sample_exact(const ShotLaunch& a, hipStream_t st);
+
+struct GaussLaunch {
+    const float2* psi;        // one row
+    int n;
+    const double* z;          // device normals [2^n]
+    double shots;
+    double* y;                // device output [2^n]
+    double* scratch;          // gauss_scratch_doubles(n) doubles
+};
+uint64_t gauss_scratch_doubles(int n);
+void launch_sample_gaussian(const GaussLaunch& a, hipStream_t st);
+
 struct AdjLaunch {
     Rows psi;                 // rows of psi
     Rows lam;                 // rows of lambda (same count)

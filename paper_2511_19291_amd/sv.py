@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
         "sv_batch_launch_pergate": [vp, vp, vp],
         "sv_batch_plan_free": [vp],
         "sv_stream_copy": [vp, vp, u64, vp],
+        "sv_sample_exact": [vp, C.c_int, vp, i64, vp],
+        "sv_sample_gaussian": [vp, C.c_int, vp, C.c_double, vp],
         "sv_check_gate": [C.c_int, ip, C.c_int, ip, C.c_int],
     }
     for name, args in sig.items():
@@ -294,6 +296,31 @@ class State:
         return out
 
     # -- gradients
+    def sample_exact(self, uniforms, row: int = 0):
+        """Exact shots (Sec. 4.3.1): one basis index per uniform in [0, 1)
+        (a device float64 tensor, or anything torch.as_tensor takes).
+        Returns a device int64 tensor; asynchronous on the state's stream."""
+        import torch
+
+        u = torch.as_tensor(uniforms, dtype=torch.float64, device=self.tensor.device).contiguous()
+        out = torch.empty(u.numel(), dtype=torch.int64, device=self.tensor.device)
+        check(lib().sv_sample_exact(self.h, row, C.c_void_p(u.data_ptr()), u.numel(), C.c_void_p(out.data_ptr())))
+        self._keep = u          # the kernels read u after this call returns
+        return out
+
+    def sample_gaussian(self, normals, shots: float, row: int = 0):
+        """Gaussian shot histogram (Sec. 4.3.2): y = shots p + sqrt(shots) D S z
+        for device float64 normals z of length 2^n. Returns a device float64
+        tensor of length 2^n."""
+        import torch
+
+        z = torch.as_tensor(normals, dtype=torch.float64, device=self.tensor.device).contiguous()
+        assert z.numel() == 1 << self.n
+        y = torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device)
+        check(lib().sv_sample_gaussian(self.h, row, C.c_void_p(z.data_ptr()), float(shots), C.c_void_p(y.data_ptr())))
+        self._keep = z
+        return y
+
     def adjoint_grad(self, circuit, terms: Sequence[Tuple[float, int, int]], params=None,
                      lambda_tensor=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         """The state must hold the forward output of ``circuit``. Returns
