@@ -309,6 +309,42 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     torch.cuda.empty_cache()
     print("# adjoint done", file=sys.stderr, flush=True)
 
+    # -- the paper's profiling workload: RY encoding + 3 x [CNOT ring, RY],
+    #    batch 16, Adam on the inputs; 5 iterations, the last one timed
+    prof = {}
+    from paper_2511_19291_amd.autograd import MeasureAllZ
+    for nq in (18, 24):
+        circ, rows = C.profiling_ladder(nq, 3, 16, seed=7)
+        layer = MeasureAllZ(circ, 16)
+        x = torch.tensor(rows[:, :nq].copy(), dtype=torch.float64, requires_grad=True)
+        theta = torch.tensor(rows[:, nq:])
+        opt = torch.optim.Adam([x], lr=0.05)
+        losses, times = [], []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            opt.zero_grad()
+            loss = layer(torch.cat([x, theta], dim=1)).abs().sum()
+            loss.backward()
+            opt.step()
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            losses.append(loss.item())
+        prof[f"n{nq}"] = {"gates": len(circ.ops), "batch": 16, "final_step_ms": round(times[-1], 2),
+                          "median_step_ms": round(float(np.median(times)), 2),
+                          "loss_first": round(losses[0], 6), "loss_last": round(losses[-1], 6),
+                          "state_bytes": 16 * 8 * (1 << nq), "adjoint_buffer_bytes": 16 * 8 * (1 << nq)}
+        layer.state.free()
+        del layer
+        torch.cuda.empty_cache()
+    res["profiling_ladder"] = {
+        "workload": "paper's profiling ansatz: RY(x) encoding, 3 x [CNOT ring, RY(theta)], batch 16, "
+                    "loss sum |<Z_i>|, Adam (lr 0.05) on the inputs, 5 iterations; times are wall ms per "
+                    "iteration (forward + adjoint backward + optimizer step)",
+        **prof,
+    }
+    print("# profiling ladder done", file=sys.stderr, flush=True)
+
     # -- batched: 256 uneven circuits in one graph launch vs per-gate launches;
     #    the launch shape is picked by the library's autotuner
     circs = C.batch_workload(256, 10, 20, 6, 4)

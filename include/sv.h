@@ -227,6 +227,19 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
                           const sv_pauli_term* obs, int n_obs, void* lambda_buffer,
                           double* grad_out, double* loss_out, double* drift_out);
 
+/* sv_adjoint_grad with a loss whose observable weights differ per row:
+ * L_r = sum_t coeff_rows[r * n_obs + t] <P_t>_r (the terms' own coeff fields
+ * are ignored). This is the backward of any function of the rows' Pauli
+ * expectations: with coeff_rows = dF/d<P_t>_r it returns dF/dtheta (e.g.
+ * the rows' <Z_i> feeding a loss in PyTorch). coeff_rows: host doubles
+ * [batch][n_obs], not NULL. Outputs and errors as sv_adjoint_grad (loss_out
+ * receives L_r). */
+sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                                   int64_t params_batch_stride, int n_params,
+                                   const sv_pauli_term* obs, int n_obs, const double* coeff_rows,
+                                   void* lambda_buffer, double* grad_out, double* loss_out,
+                                   double* drift_out);
+
 /* ----------------------------------------------------------------- shots */
 
 /* Exact shot sampling (Sec. 4.3.1). Draw n_shots basis indices from row

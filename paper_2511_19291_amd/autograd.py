@@ -56,3 +56,47 @@ class QuantumExpval(torch.nn.Module):
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
         return AdjointExpval.apply(params, self.circuit, self.terms, self.state)
+
+
+class ExpvalZ(torch.autograd.Function):
+    """<Z_i> of every qubit for every batch row, differentiable in the rows'
+    parameters (inputs and angles alike). Backward: with g = dF/d<Z_i>_r from
+    the upstream graph, the library's adjoint runs once for all rows with the
+    observable sum_i g[r, i] Z_i of row r (``sv_adjoint_grad_weighted``)."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, circuit, state: "sv.State"):
+        p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, -1))
+        state.reset()
+        state.run(circuit, params=p if state.batch > 1 else p[0])
+        z = state.expval_z_all()[:, : circuit.n]
+        ctx.circuit = circuit
+        ctx.state = state
+        ctx.p = p
+        ctx.shape = params.shape
+        return torch.from_numpy(np.ascontiguousarray(z)).to(device=params.device, dtype=params.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_z: torch.Tensor):
+        n = ctx.circuit.n
+        terms = [(1.0, 0, 1 << i) for i in range(n)]
+        g = np.ascontiguousarray(grad_z.detach().to("cpu", torch.float64).numpy().reshape(ctx.state.batch, n))
+        p = ctx.p if ctx.state.batch > 1 else ctx.p[0]
+        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, terms, params=p, coeff_rows=g)
+        out = torch.from_numpy(grad.reshape(ctx.shape)).to(device=grad_z.device, dtype=grad_z.dtype)
+        return out, None, None
+
+
+class MeasureAllZ(torch.nn.Module):
+    """A fixed circuit on a batch of states; forward(params [batch, P]) ->
+    [batch, n] of <Z_i> (exact, shots = 0), differentiable through the
+    adjoint backward (the appendix example's measure_allZ on an invertible
+    device)."""
+
+    def __init__(self, circuit, batch: int = 1, device=None):
+        super().__init__()
+        self.circuit = circuit
+        self.state = sv.State(circuit.n, batch, device=device)
+
+    def forward(self, params: torch.Tensor) -> torch.Tensor:
+        return ExpvalZ.apply(params, self.circuit, self.state)

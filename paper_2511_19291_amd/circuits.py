@@ -188,6 +188,33 @@ def encoded_ansatz(n: int, layers: int, rng: np.random.Generator) -> Circuit:
     return b.build(f"encoded_ansatz_n{n}_l{layers}", feature_idx=feats)
 
 
+def profiling_ladder(n: int, blocks: int = 3, batch: int = 16, seed: int = 6):
+    """The paper's profiling workload (Sec. 5, Fig. 3; the appendix example):
+    an RY(x_q) input encoding on every qubit, then ``blocks`` x [CNOT ring
+    q -> (q + 1) mod n for q = 0..n-1, RY(theta_q) on every qubit]. The
+    inputs x are trainable and differ per batch row (uniform in [0, pi/3) as
+    in the example); the ansatz angles theta are shared by all rows (uniform in
+    [0, 2 pi)). Draw order: theta in gate order, then x row by row.
+
+    Returns (circuit, rows): the circuit's parameters are row 0's, and rows is
+    the [batch, n + blocks n] parameter matrix (inputs first)."""
+    rng = _rng(seed)
+    b = _Builder(n)
+    for q in range(n):
+        b.gate("ry", [q], values=[0.0])
+    for _ in range(blocks):
+        for q in range(n):
+            b.gate("x", [(q + 1) % n], [q])
+        for q in range(n):
+            b.gate("ry", [q], values=[0.0])
+    theta = rng.uniform(0.0, 2 * np.pi, size=blocks * n)
+    x = rng.uniform(0.0, np.pi / 3, size=(batch, n))
+    rows = np.concatenate([x, np.broadcast_to(theta, (batch, blocks * n))], axis=1)
+    circ = b.build(f"profiling_ladder_n{n}_b{blocks}", feature_idx=tuple(range(n)))
+    circ.params = rows[0].copy()
+    return circ, np.ascontiguousarray(rows)
+
+
 def batch_workload(n_circuits: int = 256, nmin: int = 10, nmax: int = 20,
                    layers: int = 6, seed: int = 4) -> List[Circuit]:
     """Many uneven-size circuits: qubit counts uniform on {nmin..nmax}, each an

@@ -176,9 +176,11 @@ __global__ __launch_bounds__(kBlock) void k_adj(KAdj a, double* part)
 // amplitude is produced by one thread). Terms arrive sorted by x_mask: each
 // distinct x_mask reads psi[c ^ x] once and applies the summed factor of its
 // terms.
-__global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t N, const PauliTermDev* terms, int nt)
+__global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t N, const PauliTermDev* terms, int nt,
+                                                   const double* coeff_rows)
 {
     const int row = blockIdx.y;
+    const double* crow = coeff_rows ? coeff_rows + (uint64_t)row * nt : nullptr;
     const float2* psi = mrow(rp, row);
     float2* lam = mrow(rl, row);
     for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (uint64_t)gridDim.x * kBlock) {
@@ -191,7 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t
             double fr = 0.0, fi = 0.0;       // sum of coeff * sign * i^y over the terms of this x_mask
             for (; t < nt && terms[t].x_mask == xm; ++t) {
                 const PauliTermDev tm = terms[t];
-                const double sg = (__popcll(src & tm.z_mask) & 1) ? -tm.coeff : tm.coeff;
+                const double cf = crow ? crow[tm.orig] : tm.coeff;
+                const double sg = (__popcll(src & tm.z_mask) & 1) ? -cf : cf;
                 switch (tm.y_count & 3) {
                 case 0: fr += sg; break;
                 case 1: fi += sg; break;
@@ -266,11 +269,12 @@ void launch_adj_step(const AdjLaunch& g, double* part, hipStream_t st)
 }
 
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
-                            hipStream_t st)
+                            const double* coeff_rows, hipStream_t st)
 {
     const uint64_t N = 1ull << n;
     const uint64_t blocks = std::min<uint64_t>((N + kBlock - 1) / kBlock, (uint64_t)device_info().cu_count * 16);
-    hipLaunchKernelGGL(k_pauli_sum, dim3((unsigned)blocks, psi.nrows), dim3(kBlock), 0, st, psi, lam, N, terms, nt);
+    hipLaunchKernelGGL(k_pauli_sum, dim3((unsigned)blocks, psi.nrows), dim3(kBlock), 0, st, psi, lam, N, terms, nt,
+                       coeff_rows);
     SV_HIP(hipGetLastError());
 }
 

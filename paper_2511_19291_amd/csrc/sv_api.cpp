@@ -298,7 +298,10 @@ void ensure_lambda(sv_state s, void* user, float2** lam)
     *lam = s->lam;
 }
 
-void upload_terms(sv_state s, const sv_pauli_term* obs, int n_obs, PauliTermDev** out)
+// Terms (and optional per-row coefficients, [rows][n_obs] in the caller's
+// term order) to device memory kept in the state.
+void upload_terms(sv_state s, const sv_pauli_term* obs, int n_obs, const double* coeff_rows, int rows,
+                  PauliTermDev** out, const double** dcoeff)
 {
     std::vector<PauliTermDev> t(n_obs);
     for (int i = 0; i < n_obs; ++i) {
@@ -306,25 +309,43 @@ void upload_terms(sv_state s, const sv_pauli_term* obs, int n_obs, PauliTermDev*
         t[i].z_mask = obs[i].z_mask;
         t[i].coeff = obs[i].coeff;
         t[i].y_count = __builtin_popcountll(obs[i].x_mask & obs[i].z_mask);
-        t[i].pad = 0;
+        t[i].orig = i;
     }
     // grouped by x_mask: the gather reads each source amplitude once per group
     std::stable_sort(t.begin(), t.end(),
                      [](const PauliTermDev& a, const PauliTermDev& b) { return a.x_mask < b.x_mask; });
-    const size_t bytes = t.size() * sizeof(PauliTermDev);
+    const size_t tbytes = (t.size() * sizeof(PauliTermDev) + 15) & ~size_t(15);
+    const size_t cbytes = coeff_rows ? (size_t)rows * n_obs * sizeof(double) : 0;
+    const size_t bytes = tbytes + cbytes;
     if (bytes > s->dterms_cap) {
         if (s->dterms) {
             SV_HIP(hipStreamSynchronize(s->stream));
             SV_HIP(hipFree(s->dterms));
             s->dterms = nullptr;
+            s->dterms_cap = 0;
         }
         SV_HIP(hipMalloc(&s->dterms, bytes));
         s->dterms_cap = bytes;
     }
-    SV_HIP(hipMemcpyAsync(s->dterms, t.data(), bytes, hipMemcpyHostToDevice, s->stream));
-    // the host vector dies at return: make the copy complete first
+    unsigned char* d = static_cast<unsigned char*>(s->dterms);
+    SV_HIP(hipMemcpyAsync(d, t.data(), t.size() * sizeof(PauliTermDev), hipMemcpyHostToDevice, s->stream));
+    if (coeff_rows) SV_HIP(hipMemcpyAsync(d + tbytes, coeff_rows, cbytes, hipMemcpyHostToDevice, s->stream));
+    // the host vector dies at return: make the copies complete first
     SV_HIP(hipStreamSynchronize(s->stream));
-    *out = static_cast<PauliTermDev*>(s->dterms);
+    *out = reinterpret_cast<PauliTermDev*>(d);
+    *dcoeff = coeff_rows ? reinterpret_cast<const double*>(d + tbytes) : nullptr;
+}
+
+// True when every row's parameters of this op are bitwise equal to row 0's
+// (then one launch serves all rows).
+bool same_params_all_rows(const sv_op& op, const OpInfo& oi, const double* params, int64_t stride, int rows)
+{
+    for (int r = 1; r < rows; ++r)
+        for (int d = 0; d < oi.np; ++d) {
+            const double a = params[op.param[d]], b = params[r * stride + op.param[d]];
+            if (std::memcmp(&a, &b, sizeof(double)) != 0) return false;
+        }
+    return true;
 }
 
 void check_terms(int n, const sv_pauli_term* terms, int nt)
@@ -477,7 +498,7 @@ sv_status sv_run(sv_state s, const sv_op* ops, int n_ops, const double* params, 
         for (int i = 0; i < n_ops; ++i) {
             const sv_op& op = ops[i];
             cd m[16];
-            if (!per_row || info[i].np == 0) {
+            if (!per_row || info[i].np == 0 || same_params_all_rows(op, info[i], params, params_batch_stride, s->batch)) {
                 op_matrix(op, info[i], params, m);
                 dispatch(all_rows(s), info[i].k, op.targets, op.n_controls, op.controls, m, s->stream);
             } else {
@@ -552,9 +573,13 @@ sv_status sv_expval_pauli(sv_state s, const sv_pauli_term* terms, int n_terms, d
     });
 }
 
-sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double* params,
-                          int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
-                          void* lambda_buffer, double* grad_out, double* loss_out, double* drift_out)
+}  // extern "C"
+
+namespace {
+
+sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* params, int64_t params_batch_stride,
+                       int n_params, const sv_pauli_term* obs, int n_obs, const double* coeff_rows,
+                       void* lambda_buffer, double* grad_out, double* loss_out, double* drift_out)
 {
     return guarded([&] {
         check_state(s);
@@ -572,7 +597,8 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
         float2* lam = nullptr;
         ensure_lambda(s, lambda_buffer, &lam);
         PauliTermDev* dterms = nullptr;
-        upload_terms(s, obs, n_obs, &dterms);
+        const double* dcoeff = nullptr;
+        upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
 
         // slots: one per (parameterised op, row, derivative)
         struct Slot { int row; int param; };
@@ -593,7 +619,7 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
 
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
-        launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, s->stream);
+        launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
         const Rows both{s->psi, lam, B, 2 * B, s->N};
@@ -609,16 +635,18 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
                 dispatch(both, oi.k, op.targets, op.n_controls, op.controls, md, s->stream);
                 continue;
             }
-            const int nrl = per_row ? B : 1;
+            // rows whose parameters of this op are all equal share one launch
+            const bool op_rows = per_row && !same_params_all_rows(op, oi, params, params_batch_stride, B);
+            const int nrl = op_rows ? B : 1;
             for (int rl = 0; rl < nrl; ++rl) {
-                const double* pr = params + (per_row ? rl * params_batch_stride : 0);
+                const double* pr = params + (op_rows ? rl * params_batch_stride : 0);
                 double prm[3];
                 op_params(op, oi, pr, prm);
                 cd m[16], md[16];
                 kind_matrix(op.kind, prm, m);
                 dagger(oi.k, m, md);
                 AdjLaunch a{};
-                if (per_row) {
+                if (op_rows) {
                     a.psi = one_row(s, s->psi, rl);
                     a.lam = one_row(s, lam, rl);
                 } else {
@@ -643,9 +671,9 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
                 }
                 a.grid = G;
                 launch_adj_step(a, part + cur * G, s->stream);
-                const int rows_here = per_row ? 1 : B;
+                const int rows_here = op_rows ? 1 : B;
                 for (int r = 0; r < rows_here; ++r)
-                    for (int d = 0; d < oi.np; ++d) slots.push_back(Slot{per_row ? rl : r, op.param[d]});
+                    for (int d = 0; d < oi.np; ++d) slots.push_back(Slot{op_rows ? rl : r, op.param[d]});
                 cur += (uint64_t)rows_here * oi.np;
             }
         }
@@ -665,6 +693,32 @@ sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double*
             if (drift_out) drift_out[r] = std::sqrt(std::max(0.0, h_drift[r]));
         }
     });
+}
+
+
+}  // namespace
+
+extern "C" {
+
+sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                          int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                          void* lambda_buffer, double* grad_out, double* loss_out, double* drift_out)
+{
+    return adjoint_impl(s, ops, n_ops, params, params_batch_stride, n_params, obs, n_obs, nullptr, lambda_buffer,
+                        grad_out, loss_out, drift_out);
+}
+
+sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                                   int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                                   const double* coeff_rows, void* lambda_buffer, double* grad_out,
+                                   double* loss_out, double* drift_out)
+{
+    if (coeff_rows == nullptr) {
+        g_last_error = "coeff_rows is NULL";
+        return SV_ERR_INVALID_ARGUMENT;
+    }
+    return adjoint_impl(s, ops, n_ops, params, params_batch_stride, n_params, obs, n_obs, coeff_rows, lambda_buffer,
+                        grad_out, loss_out, drift_out);
 }
 
 sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64_t n_shots, int64_t* dev_out)

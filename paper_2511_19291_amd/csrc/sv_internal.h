@@ -111,11 +111,13 @@ struct PauliTermDev {
     uint64_t x_mask, z_mask;
     double coeff;
     int y_count;
-    int pad;
+    int orig;                 // index of the term in the caller's list
 };
-// lam <- O psi, O = sum of terms (device array of nt terms).
+// lam <- O psi, O = sum of terms (device array of nt terms). coeff_rows:
+// NULL, or device [rows][nt] coefficients (caller's term order) replacing
+// each term's coeff row by row.
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
-                            hipStream_t st);
+                            const double* coeff_rows, hipStream_t st);
 
 // ------------------------------------------------------------ shots
 struct ShotLaunch {
