@@ -8,6 +8,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <tuple>
 #include <vector>
 
 #include "sv_internal.h"
@@ -76,27 +77,6 @@ void absorb(Blk& b, const cd* M, int k, const int* targets, int nc, const int* c
     b.gates += 1;
 }
 
-// a (x) b: the qubits of a become the more significant bits
-Blk kron(const Blk& a, const Blk& b)
-{
-    Blk o;
-    o.qs = a.qs;
-    o.qs.insert(o.qs.end(), b.qs.begin(), b.qs.end());
-    o.mask = a.mask | b.mask;
-    o.gates = a.gates + b.gates;
-    const int da = 1 << a.qs.size(), db = 1 << b.qs.size(), d = da * db;
-    o.m.assign((size_t)d * d, 0.0);
-    for (int ra = 0; ra < da; ++ra)
-        for (int ca = 0; ca < da; ++ca) {
-            const cd x = a.m[(size_t)ra * da + ca];
-            if (x == cd(0.0)) continue;
-            for (int rb = 0; rb < db; ++rb)
-                for (int cb = 0; cb < db; ++cb)
-                    o.m[(size_t)(ra * db + rb) * d + (ca * db + cb)] = x * b.m[(size_t)rb * db + cb];
-        }
-    return o;
-}
-
 Blk identity_on(const std::vector<int>& qs)
 {
     Blk b;
@@ -117,15 +97,36 @@ struct PlanGate {
     uint64_t mask;
 };
 
-// Group gates into blocks of <= max_k qubits. Open blocks hold disjoint
-// qubit sets, so they commute and may be closed in any order; a gate joins
-// the open blocks it touches (merging them) when the union fits, otherwise
-// the fullest touched blocks are closed until it fits. No gate moves past
-// another gate on a shared qubit, so the block sequence equals the circuit.
-std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
+// A planned block before its matrix is formed: the qubit list (qs[0] = most
+// significant bit of the matrix index) and the circuit's gates in the order
+// they are multiplied in.
+struct PlanBlock {
+    std::vector<int> qs;
+    std::vector<int> gates;
+    uint64_t mask = 0;
+};
+
+void add_qubits(PlanBlock& b, const PlanGate& g)
 {
-    std::vector<Blk> out, open;
-    for (const PlanGate& g : gates) {
+    for (int j = 0; j < g.k + g.nc; ++j) {
+        const int q = j < g.k ? g.targets[j] : g.controls[j - g.k];
+        if (!((b.mask >> q) & 1)) {
+            b.qs.push_back(q);
+            b.mask |= 1ull << q;
+        }
+    }
+}
+
+// Planner A (open blocks). Open blocks hold disjoint qubit sets, so they
+// commute and may be closed in any order; a gate joins the open blocks it
+// touches (merging them) when the union fits, otherwise the fullest touched
+// blocks are closed until it fits. No gate moves past another gate on a
+// shared qubit, so the block sequence equals the circuit.
+std::vector<PlanBlock> plan_open_blocks(const std::vector<PlanGate>& gates, int max_k)
+{
+    std::vector<PlanBlock> out, open;
+    for (int gi = 0; gi < (int)gates.size(); ++gi) {
+        const PlanGate& g = gates[gi];
         std::vector<int> hit;
         for (int i = 0; i < (int)open.size(); ++i)
             if (open[i].mask & g.mask) hit.push_back(i);
@@ -142,40 +143,115 @@ std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
                 if (best < 0 || open[keep[j]].qs.size() > open[keep[best]].qs.size()) best = j;
             keep.erase(keep.begin() + best);
         }
-        std::vector<int> closing;
-        for (int i : hit)
-            if (std::find(keep.begin(), keep.end(), i) == keep.end()) closing.push_back(i);
-        // merge the kept blocks, extend by the gate's new qubits, absorb the gate
-        Blk b;
-        bool first = true;
+        // merge the kept blocks (disjoint qubits: their gates commute) and add the gate
+        PlanBlock b;
         for (int i : keep) {
-            b = first ? open[i] : kron(b, open[i]);
-            first = false;
+            b.qs.insert(b.qs.end(), open[i].qs.begin(), open[i].qs.end());
+            b.gates.insert(b.gates.end(), open[i].gates.begin(), open[i].gates.end());
+            b.mask |= open[i].mask;
         }
-        std::vector<int> fresh;
-        uint64_t have = first ? 0 : b.mask;
-        for (int j = 0; j < g.k + g.nc; ++j) {
-            const int q = j < g.k ? g.targets[j] : g.controls[j - g.k];
-            if (!((have >> q) & 1)) {
-                fresh.push_back(q);
-                have |= 1ull << q;
-            }
-        }
-        if (first) b = identity_on(fresh);
-        else if (!fresh.empty()) b = kron(b, identity_on(fresh));
-        absorb(b, g.m, g.k, g.targets, g.nc, g.controls);
-        // rebuild the open list: closed blocks go out first, in creation order
-        std::vector<Blk> next;
+        add_qubits(b, g);
+        b.gates.push_back(gi);
+        // closed blocks go out first, in creation order
+        std::vector<PlanBlock> next;
         for (int i = 0; i < (int)open.size(); ++i) {
             const bool is_hit = std::find(hit.begin(), hit.end(), i) != hit.end();
-            const bool is_closing = std::find(closing.begin(), closing.end(), i) != closing.end();
-            if (is_closing) out.push_back(std::move(open[i]));
+            const bool is_kept = std::find(keep.begin(), keep.end(), i) != keep.end();
+            if (is_hit && !is_kept) out.push_back(std::move(open[i]));
             else if (!is_hit) next.push_back(std::move(open[i]));
         }
         next.push_back(std::move(b));
         open = std::move(next);
     }
-    for (Blk& b : open) out.push_back(std::move(b));
+    for (PlanBlock& b : open) out.push_back(std::move(b));
+    return out;
+}
+
+// Planner B (frontier growth). Blocks are built one at a time from the
+// gates whose predecessors (the previous gate on each of their qubits) are
+// all placed already: the block repeatedly takes the ready gate that adds
+// the fewest new qubits while the block stays within max_k qubits, ties
+// broken by `variant` (0: circuit order; 1: most shared qubits, then order;
+// 2: lowest qubit, then order). A gate is only ever placed after all its
+// predecessors, so the block sequence equals the circuit.
+std::vector<PlanBlock> plan_frontier(const std::vector<PlanGate>& gates, int max_k, int variant)
+{
+    const int G = (int)gates.size();
+    std::vector<std::vector<int>> succ(G);
+    std::vector<int> indeg(G, 0);
+    {
+        std::vector<int> last(64, -1);
+        for (int i = 0; i < G; ++i) {
+            std::vector<int> pred;
+            for (int q = 0; q < 64; ++q)
+                if ((gates[i].mask >> q) & 1) {
+                    if (last[q] >= 0 && std::find(pred.begin(), pred.end(), last[q]) == pred.end()) pred.push_back(last[q]);
+                    last[q] = i;
+                }
+            for (int p : pred) succ[p].push_back(i);
+            indeg[i] = (int)pred.size();
+        }
+    }
+    std::vector<int> ready;
+    for (int i = 0; i < G; ++i)
+        if (indeg[i] == 0) ready.push_back(i);
+    std::vector<PlanBlock> out;
+    while (!ready.empty()) {
+        PlanBlock b;
+        for (;;) {
+            int best = -1;
+            long key0 = 0, key1 = 0, key2 = 0;
+            for (int j = 0; j < (int)ready.size(); ++j) {
+                const PlanGate& g = gates[ready[j]];
+                const uint64_t u = b.mask | g.mask;
+                if (__builtin_popcountll(u) > max_k) continue;
+                const long k0 = __builtin_popcountll(g.mask & ~b.mask);
+                long k1 = 0;
+                if (variant == 1) k1 = -(long)__builtin_popcountll(g.mask & b.mask);
+                else if (variant == 2) k1 = __builtin_ctzll(g.mask);
+                const long k2 = ready[j];
+                if (best < 0 || std::tie(k0, k1, k2) < std::tie(key0, key1, key2)) {
+                    best = j;
+                    key0 = k0;
+                    key1 = k1;
+                    key2 = k2;
+                }
+            }
+            if (best < 0) break;
+            const int gi = ready[best];
+            ready.erase(ready.begin() + best);
+            add_qubits(b, gates[gi]);
+            b.gates.push_back(gi);
+            for (int s : succ[gi])
+                if (--indeg[s] == 0) ready.push_back(s);
+        }
+        out.push_back(std::move(b));
+    }
+    return out;
+}
+
+// The block's matrix: the product of its gates, in order, over its qubits.
+Blk build_block(const PlanBlock& pb, const std::vector<PlanGate>& gates)
+{
+    Blk b = identity_on(pb.qs);
+    for (int gi : pb.gates) {
+        const PlanGate& g = gates[gi];
+        absorb(b, g.m, g.k, g.targets, g.nc, g.controls);
+    }
+    return b;
+}
+
+// Every planner, the plan with the fewest blocks (ties: the first).
+std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
+{
+    std::vector<PlanBlock> best = plan_open_blocks(gates, max_k);
+    for (int v = 0; v < 3; ++v) {
+        std::vector<PlanBlock> p = plan_frontier(gates, max_k, v);
+        if (p.size() < best.size()) best = std::move(p);
+    }
+    std::vector<Blk> out;
+    out.reserve(best.size());
+    for (const PlanBlock& pb : best) out.push_back(build_block(pb, gates));
     return out;
 }
 

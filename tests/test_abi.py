@@ -65,12 +65,30 @@ def test_fusion_plan_reproduces_circuit(svmod, n, seed):
         np.testing.assert_allclose(psi, oracle.run(circ), atol=1e-12)
 
 
+@pytest.mark.parametrize("name", ["qft", "ring", "hea", "brickwork", "ghz"])
+def test_fusion_plan_reproduces_structured_circuits(svmod, name):
+    """The same check on structured circuits, where the frontier planner and
+    the open-block planner take turns at giving the fewest blocks."""
+    import oracle
+    circ = {"qft": lambda: Cc.qft(9, 77), "ring": lambda: Cc.rxry_ring(9, 3, 2), "hea": lambda: Cc.hea_ladder(9, 3, 4),
+            "brickwork": lambda: Cc.brickwork_u3_cz(10, 6, 5), "ghz": lambda: Cc.ghz(10)}[name]()
+    for max_k in (2, 3, 5):
+        blocks = svmod.fuse_plan(circ, max_k)
+        assert all(len(t) <= max_k for t, _ in blocks)
+        psi = oracle.basis_state(circ.n)
+        for t, m in blocks:
+            oracle.apply_matrix(psi, circ.n, m, list(t))
+        np.testing.assert_allclose(psi, oracle.run(circ), atol=1e-12)
+
+
 def test_fusion_plan_brickwork_block_count(svmod):
-    """32-qubit brickwork (950 gates) fuses into far fewer 5-qubit sweeps."""
-    circ = Cc.brickwork_u3_cz(32, 20, 3)
-    blocks = svmod.fuse_plan(circ, 5)
-    assert len(blocks) <= 100
-    assert sum(len(t) == 5 for t, _ in blocks) >= 0.8 * len(blocks)
+    """The brickwork workloads fuse into far fewer 5-qubit sweeps: 890 gates
+    at 30 qubits -> 52 blocks, 950 at 32 -> 56 (the frontier planner; the
+    open-block planner alone gives 72 and 80)."""
+    for n, seed, most in ((30, 2, 52), (32, 3, 56)):
+        blocks = svmod.fuse_plan(Cc.brickwork_u3_cz(n, 20, seed), 5)
+        assert len(blocks) <= most
+        assert sum(len(t) == 5 for t, _ in blocks) >= 0.8 * len(blocks)
 
 
 def test_fusion_plan_rejects_bad_input(svmod):
