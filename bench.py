@@ -247,6 +247,14 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
                            "ms_per_block": round(per_block, 4),
                            "GBps_per_block": round(16 * (1 << nq) / (per_block / 1e3) / 1e9, 1),
                            "TFLOPs_per_block": round(8 * 32 * (1 << nq) / (per_block / 1e3) / 1e12, 2)}
+        # six-qubit blocks off qubits 0..5 (BF16x3 only), five-qubit blocks elsewhere
+        blocks6 = sv.fuse_plan(circ, 6)
+        st.reset()
+        st.apply_fused(blocks6[:2], sv.FUSED_BF16X3)
+        ms6 = _timed_ms(lambda: (st.reset(), st.apply_fused(blocks6, sv.FUSED_BF16X3)), stream)
+        entry["bf16x3_k6"] = {"blocks": len(blocks6), "six_qubit_blocks": sum(len(t) == 6 for t, _ in blocks6),
+                              "ms": round(ms6, 2), "gates_per_s": round(len(circ.ops) / (ms6 / 1e3), 1),
+                              "ms_per_block": round(ms6 / len(blocks6), 4)}
         if with_plain:
             table = sv.OpTable(circ.ops)
             p = np.ascontiguousarray(circ.params)
@@ -254,7 +262,7 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
             entry["plain_ms"] = round(ms, 2)
         else:
             entry["plain_ms"] = round(len(circ.ops) / plain_gates_per_s * 1e3, 2)
-        for name in ("fp32_mfma", "bf16x3"):
+        for name in ("fp32_mfma", "bf16x3", "bf16x3_k6"):
             entry[name]["speedup_vs_plain"] = round(entry["plain_ms"] / entry[name]["ms"], 2)
         if nq == n:
             # fusion width and arithmetic picked by the library's autotuner

@@ -59,7 +59,7 @@ typedef enum sv_status {
 /* Limits of the kernels. */
 #define SV_MAX_QUBITS 34          /* 2^34 complex64 = 128 GiB per row */
 #define SV_MAX_GATE_TARGETS 2     /* sv_apply_gate / sv_run: k <= 2 */
-#define SV_MAX_FUSED_TARGETS 5    /* sv_apply_fused: k <= 5 */
+#define SV_MAX_FUSED_TARGETS 6    /* sv_apply_fused: k <= 6 */
 #define SV_MAX_CONTROLS 3
 
 typedef struct sv_state_s* sv_state;
@@ -163,21 +163,33 @@ typedef struct sv_block {
 
 /* Apply the blocks in order to every row. Each block is one sweep over the
  * state: the 2^k amplitudes that differ only in the target bits form a
- * column, and the block computes Y = M X over all 2^(n-k) columns.
- * Errors: SV_ERR_INVALID_ARGUMENT (bad mode, k outside 1..5 or n < k + 5
- * for the MFMA modes), SV_ERR_QUBIT_*, SV_ERR_HIP. */
+ * column, and the block computes Y = M X over all 2^(n-k) columns (Alg. 1
+ * with |Q| = k).
+ *   k <= 5: every mode; the matrix-core modes pad the block to five qubits
+ *     (M (x) I on the lowest free qubits) and need n >= 10; SV_FUSED_VALU
+ *     takes k <= 5 as given.
+ *   k = 6: SV_FUSED_BF16X3 only, every target >= 6, 12 <= n <= 32.
+ * The block matrices are copied to device memory held by the state (the
+ * call returns once the host data is consumed).
+ * Errors: SV_ERR_INVALID_ARGUMENT (bad mode, k outside 1..6, n < 10 for the
+ * matrix-core modes), SV_ERR_UNSUPPORTED (a six-qubit block outside its
+ * conditions), SV_ERR_QUBIT_*, SV_ERR_HIP. */
 sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_blocks, int mode);
 
 /* Host-only fusion planner (no GPU work): group the gates of a circuit, in
  * order, into blocks of at most max_k qubits (controls count as qubits) and
  * multiply each block's gates into one complex128 matrix. Gates on disjoint
  * qubits may move past each other; no gate moves past one it shares a qubit
- * with, so the block sequence equals the circuit.
+ * with, so the block sequence equals the circuit. Several planners run (an
+ * open-block grouping and frontier growth with three tie-breaking rules) and
+ * the plan with the fewest blocks is returned. With max_k = 6, blocks of six
+ * qubits stay off qubits 0..5 (the condition of sv_apply_fused's six-qubit
+ * form); a block touching one of them holds at most five.
  *   out_blocks[max_blocks]: block descriptors; their matrix pointers point
  *     into out_matrices.
  *   out_matrices: room for max_blocks * 4^max_k complex128 (2 doubles each).
  *   *n_blocks_out: number of blocks written.
- * Errors: SV_ERR_INVALID_ARGUMENT (max_k outside 1..5, too little room). */
+ * Errors: SV_ERR_INVALID_ARGUMENT (max_k outside 1..6, too little room). */
 sv_status sv_fuse_plan(int n_qubits, const sv_op* ops, int n_ops, const double* params,
                        int n_params, int max_k, sv_block* out_blocks, int max_blocks,
                        double* out_matrices, int* n_blocks_out);
@@ -395,9 +407,10 @@ typedef struct sv_fusion_choice {
 
 /* Autotuner of the fusion width: times the circuit (host params, the same
  * for every row) on the state s as plain sweeps, as SV_FUSED_VALU blocks of
- * max_k = 2..5, and (n >= 10) as five-qubit matrix-core blocks in the modes
- * that mode_mask allows (bit 1 << SV_FUSED_*; plain sweeps are always tried),
- * and returns the fastest. The state's contents are overwritten (reset it
+ * max_k = 2..5, (n >= 10) as five-qubit matrix-core blocks in the modes that
+ * mode_mask allows, and (12 <= n <= 32, BF16X3 allowed) as six-qubit blocks
+ * (bit 1 << SV_FUSED_* of mode_mask; plain sweeps are always tried), and
+ * returns the fastest. The state's contents are overwritten (reset it
  * afterwards). A width that some gate of the circuit exceeds is skipped.
  *   reps: timed applications per candidate (after one warm-up).
  * Synchronous. Errors as sv_run / sv_fuse_plan / sv_apply_fused. */

@@ -233,13 +233,15 @@ sv_status sv_fused_autotune(sv_state s, const sv_op* ops, int n_ops, const doubl
             done.push_back(c);
         };
         if (mode_mask & (1u << SV_FUSED_VALU))
-            for (int k = 2; k <= SV_MAX_FUSED_TARGETS; ++k) try_fused(k, SV_FUSED_VALU);
-        // the matrix-core forms pad every block to five qubits, so the widest
-        // plan (fewest sweeps) is the only one worth timing
+            for (int k = 2; k <= 5; ++k) try_fused(k, SV_FUSED_VALU);
+        // the matrix-core forms pad every block of up to five qubits to five,
+        // so of those widths the widest plan (fewest sweeps) is the one to time
         if (s->n >= 10) {
-            if (mode_mask & (1u << SV_FUSED_FP32_MFMA)) try_fused(SV_MAX_FUSED_TARGETS, SV_FUSED_FP32_MFMA);
-            if (mode_mask & (1u << SV_FUSED_BF16X3)) try_fused(SV_MAX_FUSED_TARGETS, SV_FUSED_BF16X3);
+            if (mode_mask & (1u << SV_FUSED_FP32_MFMA)) try_fused(5, SV_FUSED_FP32_MFMA);
+            if (mode_mask & (1u << SV_FUSED_BF16X3)) try_fused(5, SV_FUSED_BF16X3);
         }
+        // six-qubit blocks (BF16x3, off qubits 0..5)
+        if (s->n >= 12 && s->n <= 32 && (mode_mask & (1u << SV_FUSED_BF16X3))) try_fused(6, SV_FUSED_BF16X3);
         const sv_fusion_choice* b = &done.front();
         for (const sv_fusion_choice& c : done)
             if (c.ms < b->ms) b = &c;

@@ -122,6 +122,11 @@ void add_qubits(PlanBlock& b, const PlanGate& g)
 // touches (merging them) when the union fits, otherwise the fullest touched
 // blocks are closed until it fits. No gate moves past another gate on a
 // shared qubit, so the block sequence equals the circuit.
+// Widest block allowed on a qubit set: max_k, except that six-qubit blocks
+// must keep off qubits 0..5 (the six-qubit matrix-core form streams those as
+// its columns); a block touching one of them holds at most five qubits.
+int width_limit(uint64_t mask, int max_k) { return max_k == 6 && (mask & 63) ? 5 : max_k; }
+
 std::vector<PlanBlock> plan_open_blocks(const std::vector<PlanGate>& gates, int max_k)
 {
     std::vector<PlanBlock> out, open;
@@ -130,14 +135,14 @@ std::vector<PlanBlock> plan_open_blocks(const std::vector<PlanGate>& gates, int 
         std::vector<int> hit;
         for (int i = 0; i < (int)open.size(); ++i)
             if (open[i].mask & g.mask) hit.push_back(i);
-        auto union_size = [&](const std::vector<int>& keep) {
+        auto over = [&](const std::vector<int>& keep) {
             uint64_t u = g.mask;
             for (int i : keep) u |= open[i].mask;
-            return __builtin_popcountll(u);
+            return __builtin_popcountll(u) > width_limit(u, max_k);
         };
         std::vector<int> keep = hit;
         // close the fullest touched blocks until the gate fits
-        while (union_size(keep) > max_k) {
+        while (over(keep)) {
             int best = -1;
             for (int j = 0; j < (int)keep.size(); ++j)
                 if (best < 0 || open[keep[j]].qs.size() > open[keep[best]].qs.size()) best = j;
@@ -204,7 +209,7 @@ std::vector<PlanBlock> plan_frontier(const std::vector<PlanGate>& gates, int max
             for (int j = 0; j < (int)ready.size(); ++j) {
                 const PlanGate& g = gates[ready[j]];
                 const uint64_t u = b.mask | g.mask;
-                if (__builtin_popcountll(u) > max_k) continue;
+                if (__builtin_popcountll(u) > width_limit(u, max_k)) continue;
                 const long k0 = __builtin_popcountll(g.mask & ~b.mask);
                 long k1 = 0;
                 if (variant == 1) k1 = -(long)__builtin_popcountll(g.mask & b.mask);
@@ -301,7 +306,7 @@ extern "C" sv_status sv_fuse_plan(int n_qubits, const sv_op* ops, int n_ops, con
 {
     try {
         need(n_qubits >= 1 && n_qubits <= SV_MAX_QUBITS, SV_ERR_INVALID_ARGUMENT, "n_qubits must be in [1, 34]");
-        need(max_k >= 1 && max_k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "max_k must be 1..5");
+        need(max_k >= 1 && max_k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "max_k must be 1..6");
         need(n_ops >= 0 && (n_ops == 0 || ops), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
         need(out_blocks && out_matrices && n_blocks_out, SV_ERR_INVALID_ARGUMENT, "output pointer is NULL");
         std::vector<PlanGate> gates;
@@ -359,7 +364,7 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
         const bool mfma = mode != SV_FUSED_VALU;
         for (int i = 0; i < n_blocks; ++i) {
             const sv_block& b = blocks[i];
-            need(b.k >= 1 && b.k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "block k must be 1..5");
+            need(b.k >= 1 && b.k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "block k must be 1..6");
             need(b.matrix != nullptr, SV_ERR_INVALID_ARGUMENT, "block matrix is NULL");
             uint64_t seen = 0;
             for (int j = 0; j < b.k; ++j) {
@@ -368,18 +373,42 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
                 seen |= 1ull << b.targets[j];
             }
             if (mfma) need(s->n >= 10, SV_ERR_INVALID_ARGUMENT, "the MFMA fused modes need n >= 10");
+            if (b.k == 6) {
+                need(mode == SV_FUSED_BF16X3, SV_ERR_UNSUPPORTED, "six-qubit blocks run in the BF16X3 mode only");
+                need((seen & 63) == 0, SV_ERR_UNSUPPORTED, "six-qubit blocks need every target >= 6");
+                need(s->n >= 12 && s->n <= 32, SV_ERR_UNSUPPORTED, "six-qubit blocks need 12 <= n <= 32");
+            }
         }
         if (n_blocks == 0) return SV_OK;
-        // per-block device payload
-        const size_t per = mfma ? (size_t)2 * 64 * 64 * sizeof(float)
-                                : (size_t)32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t) + 8 * sizeof(int);
-        std::vector<unsigned char> host((size_t)n_blocks * per, 0);
-        std::vector<std::array<int, 5>> tgt(n_blocks);
+        // per-block device payload (16-byte multiples)
+        const size_t per5 = mfma ? (size_t)2 * 64 * 64 * sizeof(float)
+                                 : (size_t)32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t) + 8 * sizeof(int);
+        std::vector<size_t> off(n_blocks + 1, 0);
+        for (int i = 0; i < n_blocks; ++i)
+            off[i + 1] = off[i] + ((blocks[i].k == 6 ? fused6_matrix_bytes() : per5) + 15) / 16 * 16;
+        std::vector<unsigned char> host(off[n_blocks], 0);
+        std::vector<std::array<int, 6>> tgt(n_blocks);
         for (int i = 0; i < n_blocks; ++i) {
             const sv_block& b = blocks[i];
             const int k = b.k, D = 1 << k;
-            unsigned char* dst = host.data() + (size_t)i * per;
-            if (mfma) {
+            unsigned char* dst = host.data() + off[i];
+            if (k == 6) {
+                // real 128 x 128 embedding, split into BF16 hi and lo parts
+                std::vector<float> hi(128 * 128), lo(128 * 128);
+                for (int r = 0; r < 64; ++r)
+                    for (int c = 0; c < 64; ++c) {
+                        const double* e = b.matrix + 2 * ((size_t)r * 64 + c);
+                        const float re = (float)e[0], im = (float)e[1];
+                        const float v[4] = {re, -im, im, re};
+                        const int at[4] = {r * 128 + c, r * 128 + 64 + c, (64 + r) * 128 + c, (64 + r) * 128 + 64 + c};
+                        for (int q = 0; q < 4; ++q) {
+                            hi[at[q]] = bf16_round(v[q]);
+                            lo[at[q]] = bf16_round(v[q] - hi[at[q]]);
+                        }
+                    }
+                fused6_layout(hi.data(), lo.data(), reinterpret_cast<uint16_t*>(dst));
+                for (int j = 0; j < 6; ++j) tgt[i][j] = b.targets[j];
+            } else if (mfma) {
                 // pad to five targets with identity qubits (lowest free qubits,
                 // appended as the least significant bits of the matrix index)
                 int t5[5], kk = k;
@@ -433,8 +462,16 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
         SV_HIP(hipMemcpyAsync(s->dfused, host.data(), host.size(), hipMemcpyHostToDevice, s->stream));
         unsigned char* dev = static_cast<unsigned char*>(s->dfused);
         for (int i = 0; i < n_blocks; ++i) {
-            unsigned char* p = dev + (size_t)i * per;
-            if (mfma) {
+            unsigned char* p = dev + off[i];
+            if (blocks[i].k == 6) {
+                Fused6Launch f{};
+                f.psi = s->psi;
+                f.N = s->N;
+                f.nrows = s->batch;
+                for (int j = 0; j < 6; ++j) f.targets[j] = tgt[i][j];
+                f.amat = reinterpret_cast<const uint16_t*>(p);
+                launch_fused_wide6(f, s->stream);
+            } else if (mfma) {
                 FusedLaunch f{};
                 f.psi = s->psi;
                 f.N = s->N;

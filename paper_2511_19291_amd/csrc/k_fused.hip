@@ -21,6 +21,8 @@
 //      the left operand (the block matrix) stays in registers for the whole
 //      sweep;
 //   3. results -> LDS -> coalesced float4 stores in memory order.
+#include <cstring>
+
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -444,6 +446,121 @@ __global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
     }
 }
 
+// Six-qubit blocks on the matrix cores (split BF16x3 only: at 2 x 6 = 12
+// products per k-step the FP32 form would be bound by its MFMA rate). The
+// complex 64 x 64 block is the real 128 x 128 embedding A~ = [[Mr, -Mi],
+// [Mi, Mr]]; its BF16 hi and lo parts sit in LDS (rows padded to 136 so the
+// 16-byte fragment reads of consecutive rows fall in different banks). A
+// wave's tile is 64 rows (the targets, all >= 6) x 64 columns (qubits 0..5):
+// each lane loads 16 B (two adjacent columns) of 32 rows -- rows 16 s' + 8 h
+// + q, s' < 4, q < 8, the rows whose real and imaginary parts it supplies as
+// the right operand of v_mfma_f32_32x32x16_bf16 -- and splits them into BF16
+// hi/lo once. Output rows are produced in two halves (rows 0..31, then
+// 32..63): real rows from A~ row block p, imaginary rows from block 2 + p,
+// for the even and the odd columns (four accumulators); each half is stored
+// as soon as it is complete, so only half of the accumulators are live.
+// Row offsets split into a wave-uniform part and the lane's part as in the
+// five-qubit wide form. Offsets fit 32 bits (n <= 32).
+constexpr int kA6 = 136;               // padded row length of the 128 x 128 BF16 operand
+
+struct KFusedWide6 {
+    float2* psi;
+    uint64_t N;
+    uint64_t n_tiles;
+    int pos[12];               // tile bits ascending: 0..5 and the six targets
+    uint32_t toff[6];          // 1 << target j (T[0] = most significant row bit)
+    const uint16_t* amat;      // BF16 bits: hi [128][kA6] then lo [128][kA6]
+};
+
+__global__ __launch_bounds__(256) void k_fused_wide6(KFusedWide6 a)
+{
+    __shared__ __align__(16) uint16_t as[2 * 128 * kA6];
+    for (int i = threadIdx.x; i < 2 * 128 * kA6 / 8; i += 256)
+        reinterpret_cast<uint4*>(as)[i] = reinterpret_cast<const uint4*>(a.amat)[i];
+    __syncthreads();
+    const __bf16* ahi = reinterpret_cast<const __bf16*>(as);
+    const __bf16* alo = ahi + 128 * kA6;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = lane >> 5, c32 = lane & 31;
+    float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+    // row r (6 bits, bit 5 = T[0]): uniform part of its offset
+    auto urow = [&](int r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if ((r >> (5 - j)) & 1) o += a.toff[j];
+        return o;
+    };
+    const uint32_t lane_in = 2 * c32 + (h ? a.toff[2] : 0u);    // bit 3 of the operand rows
+    const uint32_t lane_out = 2 * c32 + (h ? a.toff[3] : 0u);   // bit 2 of the accumulator rows
+
+    const uint64_t waves_total = (uint64_t)gridDim.x * 4;
+    for (uint64_t tile = xcd_block(blockIdx.x, gridDim.x) * 4 + wave; tile < a.n_tiles; tile += waves_total) {
+        // keep the block matrix in LDS: re-read its fragments every tile
+        // instead of holding all 256 registers' worth across the loop
+        asm volatile("" ::: "memory");
+        float2* tp = psi + insert_zeros(tile, a.pos, 12);
+        // right operands for k-step s (k = 16 s + 8 h + q): s < 4 real parts
+        // of rows 16 s + 8 h + q, s >= 4 imaginary parts of rows 16 (s - 4) + 8 h + q;
+        // [s][0] even column, [s][1] odd column
+        bf16x8 bh[8][2], bl[8][2];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            float4 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = ld4(tp + urow(16 * g + q) + lane_in);
+            float re0[8], re1[8], im0[8], im1[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                re0[q] = v[q].x;
+                im0[q] = v[q].y;
+                re1[q] = v[q].z;
+                im1[q] = v[q].w;
+            }
+            auto split = [&](const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+                float l[8];
+                hi = to_bf16(x);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) l[q] = x[q] - (float)hi[q];
+                lo = to_bf16(l);
+            };
+            split(re0, bh[g][0], bl[g][0]);
+            split(re1, bh[g][1], bl[g][1]);
+            split(im0, bh[4 + g][0], bl[4 + g][0]);
+            split(im1, bh[4 + g][1], bl[4 + g][1]);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            f32x16 re_e = {0}, im_e = {0}, re_o = {0}, im_o = {0};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k0 = 16 * s + 8 * h;
+                const bf16x8 hr = *reinterpret_cast<const bf16x8*>(ahi + (32 * p + c32) * kA6 + k0);
+                const bf16x8 lr = *reinterpret_cast<const bf16x8*>(alo + (32 * p + c32) * kA6 + k0);
+                const bf16x8 hm = *reinterpret_cast<const bf16x8*>(ahi + (64 + 32 * p + c32) * kA6 + k0);
+                const bf16x8 lm = *reinterpret_cast<const bf16x8*>(alo + (64 + 32 * p + c32) * kA6 + k0);
+                re_e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lr, bh[s][0], re_e, 0, 0, 0);
+                im_e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lm, bh[s][0], im_e, 0, 0, 0);
+                re_o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lr, bh[s][1], re_o, 0, 0, 0);
+                im_o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lm, bh[s][1], im_o, 0, 0, 0);
+                re_e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr, bl[s][0], re_e, 0, 0, 0);
+                im_e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hm, bl[s][0], im_e, 0, 0, 0);
+                re_o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr, bl[s][1], re_o, 0, 0, 0);
+                im_o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hm, bl[s][1], im_o, 0, 0, 0);
+                re_e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr, bh[s][0], re_e, 0, 0, 0);
+                im_e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hm, bh[s][0], im_e, 0, 0, 0);
+                re_o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hr, bh[s][1], re_o, 0, 0, 0);
+                im_o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hm, bh[s][1], im_o, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                st4(tp + urow(32 * p + 8 * (q >> 2) + (q & 3)) + lane_out, make_float4(re_e[q], im_e[q], re_o[q], im_o[q]));
+        }
+    }
+}
+
 // Plain FP32 vector form: one thread per column, the block matrix in LDS.
 template <int K>
 __global__ __launch_bounds__(256) void k_fused_valu(float2* psi, uint64_t N, uint64_t n_cols, int npos,
@@ -565,6 +682,49 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         hipLaunchKernelGGL(k_fused<0>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);
     else
         hipLaunchKernelGGL(k_fused<1>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);
+    SV_HIP(hipGetLastError());
+}
+
+size_t fused6_matrix_bytes() { return (size_t)2 * 128 * kA6 * sizeof(uint16_t); }
+
+void fused6_layout(const float* embed, const float* embed_lo, uint16_t* out)
+{
+    // embed / embed_lo: row-major real 128 x 128 hi and lo parts (already
+    // rounded to BF16 values); out: BF16 bits in the padded LDS layout
+    auto bits = [](float x) {
+        uint32_t u;
+        std::memcpy(&u, &x, 4);
+        return (uint16_t)(u >> 16);
+    };
+    for (int part = 0; part < 2; ++part) {
+        const float* src = part == 0 ? embed : embed_lo;
+        uint16_t* dst = out + (size_t)part * 128 * kA6;
+        for (int r = 0; r < 128; ++r)
+            for (int c = 0; c < kA6; ++c) dst[r * kA6 + c] = c < 128 ? bits(src[r * 128 + c]) : 0;
+    }
+}
+
+void launch_fused_wide6(const Fused6Launch& f, hipStream_t st)
+{
+    const int nq = __builtin_ctzll(f.N);
+    KFusedWide6 d{};
+    d.psi = f.psi;
+    d.N = f.N;
+    d.n_tiles = 1ull << (nq - 12);
+    int t6[6];
+    for (int j = 0; j < 6; ++j) {
+        t6[j] = f.targets[j];
+        d.toff[j] = 1u << f.targets[j];
+    }
+    std::sort(t6, t6 + 6);
+    for (int b = 0; b < 6; ++b) d.pos[b] = b;
+    for (int b = 0; b < 6; ++b) d.pos[6 + b] = t6[b];
+    d.amat = f.amat;
+    // persistent grid: two workgroups per CU are resident (234 registers, 68 KiB of LDS each)
+    const uint64_t want = (d.n_tiles + 3) / 4;
+    const uint64_t cap = (uint64_t)device_info().cu_count * 2;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+    hipLaunchKernelGGL(k_fused_wide6, dim3(grid, f.nrows), dim3(256), 0, st, d);
     SV_HIP(hipGetLastError());
 }
 

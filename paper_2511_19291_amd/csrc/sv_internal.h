@@ -171,6 +171,20 @@ struct FusedLaunch {
 };
 void launch_fused_mfma(const FusedLaunch& f, hipStream_t st);
 
+// Six-qubit blocks (BF16x3, all targets >= 6, 12 <= n <= 32).
+struct Fused6Launch {
+    float2* psi;
+    uint64_t N;
+    int nrows;
+    int targets[6];
+    const uint16_t* amat;     // device: fused6_matrix_bytes() in the kernel's layout
+};
+size_t fused6_matrix_bytes();
+// BF16 hi / lo parts of the real 128 x 128 embedding (row-major floats
+// holding BF16 values) -> the kernel's padded layout.
+void fused6_layout(const float* embed_hi, const float* embed_lo, uint16_t* out);
+void launch_fused_wide6(const Fused6Launch& f, hipStream_t st);
+
 struct FusedValuLaunch {
     float2* psi;
     uint64_t N;

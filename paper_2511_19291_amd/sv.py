@@ -40,7 +40,7 @@ class SvOp(C.Structure):
 
 
 class SvBlock(C.Structure):
-    _fields_ = [("k", C.c_int32), ("targets", C.c_int32 * 5), ("matrix", C.POINTER(C.c_double))]
+    _fields_ = [("k", C.c_int32), ("targets", C.c_int32 * 6), ("matrix", C.POINTER(C.c_double))]
 
 
 class SvPauliTerm(C.Structure):

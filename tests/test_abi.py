@@ -94,7 +94,7 @@ def test_fusion_plan_brickwork_block_count(svmod):
 def test_fusion_plan_rejects_bad_input(svmod):
     circ = Cc.random_circuit(4, 10, 1)
     with pytest.raises(svmod.SvError):
-        svmod.fuse_plan(circ, 6)
+        svmod.fuse_plan(circ, 7)
     bad = Cc.Circuit(4, [Cc.Op("x", (4,))], np.zeros(0))
     with pytest.raises(svmod.SvError):
         svmod.fuse_plan(bad, 5)

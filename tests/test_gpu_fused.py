@@ -123,3 +123,56 @@ def test_fused24_error_vs_fp64_oracle(sv, fused24_reference, mode):
           f"d<sumZ> {abs(z[:n].sum() - zr.sum()):.2e}")
     assert err <= AMP_TOL
     assert abs(z[:n].sum() - zr.sum()) <= 2 * n * dn + 1e-12
+
+
+@pytest.mark.parametrize("n,targets", [
+    (12, (11, 10, 9, 8, 7, 6)),       # the smallest state: one tile row per wave
+    (12, (6, 7, 8, 9, 10, 11)),       # reversed target order
+    (18, (17, 6, 12, 9, 15, 7)),      # scattered, unsorted
+    (21, (20, 19, 6, 13, 8, 16)),
+])
+def test_six_qubit_block_random_unitary(sv, n, targets):
+    """A Haar-random 64x64 unitary on six targets >= 6 (BF16x3 six-qubit
+    form): pins the 128x128 operand layout, both output halves and the
+    even/odd column accumulators, on two batch rows."""
+    rng = np.random.default_rng(n * 11 + sum(targets))
+    psi0 = pins.random_state(n, rng)
+    m = pins.haar_unitary(64, rng)
+    st = _upload(sv, n, psi0, batch=2)
+    st.apply_fused([(targets, m)], svmod.FUSED_BF16X3)
+    ref = psi0.astype(np.complex64).astype(np.complex128)
+    oracle.apply_matrix(ref, n, m, list(targets))
+    out = st.to_numpy()
+    for r in range(2):
+        assert np.max(np.abs(out[r] - ref)) <= AMP_TOL
+
+
+@pytest.mark.parametrize("n", [12, 16, 20])
+def test_planned_six_qubit_brickwork_vs_unfused_oracle(sv, n):
+    """Brickwork planned with max_k = 6 (six-qubit blocks off qubits 0..5,
+    five-qubit blocks elsewhere) in BF16x3 equals the oracle's state, with
+    fewer blocks than the five-qubit plan."""
+    circ = C.brickwork_u3_cz(n, 20, 3)
+    blocks = svmod.fuse_plan(circ, 6)
+    assert any(len(t) == 6 for t, _ in blocks)
+    assert len(blocks) < len(svmod.fuse_plan(circ, 5))
+    st = sv.State(n).reset()
+    st.apply_fused(blocks, svmod.FUSED_BF16X3)
+    ref = oracle.run(circ)
+    assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
+
+
+def test_six_qubit_block_conditions(sv):
+    rng = np.random.default_rng(4)
+    m = pins.haar_unitary(64, rng)
+    st = sv.State(14).reset()
+    for mode in (svmod.FUSED_FP32_MFMA, svmod.FUSED_VALU):
+        with pytest.raises(svmod.SvError) as e:
+            st.apply_fused([((13, 12, 11, 10, 9, 8), m)], mode)
+        assert e.value.status == 4                     # unsupported
+    with pytest.raises(svmod.SvError) as e:
+        st.apply_fused([((13, 12, 11, 10, 9, 5), m)], svmod.FUSED_BF16X3)
+    assert e.value.status == 4
+    with pytest.raises(svmod.SvError) as e:
+        sv.State(11).reset().apply_fused([((10, 9, 8, 7, 6, 5), m)], svmod.FUSED_BF16X3)
+    assert e.value.status in (1, 4)
