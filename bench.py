@@ -462,8 +462,8 @@ def run_pmc_probe(n: int) -> int:
     """Short fixed sequence for hardware counters: 4 dense U3 sweeps on
     targets >= 7 of an n-qubit state (k_gate<1, 2, 1, true>), four fused
     5-qubit blocks in each matrix-core mode (one direct, two wide, one
-    LDS-staged launch), then one plain copy of the state (8 * 2^n bytes read,
-    the same written) to scale the counters."""
+    LDS-staged launch), one six-qubit BF16x3 block, then one plain copy of the
+    state (8 * 2^n bytes read, the same written) to scale the counters."""
     import numpy as np
     import torch
 
@@ -486,6 +486,10 @@ def run_pmc_probe(n: int) -> int:
     blocks = [((9, 8, 7, 6, 5), m), ((n - 1, 20, 14, 10, 6), m), ((11, 10, 9, 8, 7), m), ((n - 1, 12, 3, 2, 0), m)]
     st.apply_fused(blocks, sv.FUSED_FP32_MFMA)
     st.apply_fused(blocks, sv.FUSED_BF16X3)
+    # one six-qubit block (BF16x3)
+    z6 = rng.normal(size=(64, 64)) + 1j * rng.normal(size=(64, 64))
+    q6, r6 = np.linalg.qr(z6)
+    st.apply_fused([((n - 1, 20, 14, 10, 7, 6), q6 * (np.diag(r6) / np.abs(np.diag(r6))))], sv.FUSED_BF16X3)
     torch.cuda.synchronize()
     dst = torch.empty_like(st.tensor)
     sv.check(sv.lib().sv_stream_copy(dst.data_ptr(), st.tensor.data_ptr(), 8 * (1 << n),
