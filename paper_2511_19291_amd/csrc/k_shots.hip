@@ -10,9 +10,10 @@
 //      block's offset are deterministic);
 //   3. each shot finds its block by binary search over the scanned sums
 //      (an L2-resident array) and is bucketed by block (counting sort);
-//   4. each block that holds at least one shot is read once more, its
-//      in-block running sum is built in LDS in a fixed order, and each of its
-//      shots finds its index there by binary search.
+//   4. each block that holds at least one shot is read once more by one
+//      wave: the lanes' masses are scanned with shuffles in a fixed order,
+//      and each of its shots finds its lane by binary search and its index
+//      by a sequential walk through that lane's amplitudes.
 // The counts of the indices over all shots are one draw of the multinomial
 // M(shots, p). This is the paper's hierarchical view restricted to one
 // device: the blocks play the role of the groups whose masses q_j are known
@@ -156,65 +157,99 @@ __global__ __launch_bounds__(kST) void k_shot_scatter(const uint32_t* __restrict
     order[pos] = (uint32_t)s;
 }
 
-// 4. per block with shots: in-block running sum in LDS, then each shot's
-// index by binary search (first running sum > rem; if rounding leaves rem at
-// or above the block's own total, the block's last index of non-zero
-// probability)
+// 4. per block with shots, one wave per block. Lane l owns the `per`
+// contiguous amplitudes [per l, per (l + 1)) of the block (per = 64 for
+// blocks of 4096); the lanes' masses are scanned across the wave with
+// shuffles in a fixed order. Each shot of the block finds its lane by binary
+// search over the lanes' inclusive sums (shuffles: every lane takes part in
+// every step), then its index by re-reading that lane's amplitudes in the
+// same order: the first index whose running sum exceeds the remainder; if
+// rounding leaves none, the last index of non-zero probability in the lane
+// (or, past the last lane, in the block).
+__device__ __forceinline__ double lane_prob(const float2* __restrict__ p, uint32_t i) { return prob(p[i]); }
+
 __global__ __launch_bounds__(kST) void k_shot_resolve(const float2* __restrict__ psi, int bb, uint32_t nb,
                                                       const uint32_t* __restrict__ cinc, const uint32_t* __restrict__ cnt,
                                                       const uint32_t* __restrict__ order, const double* __restrict__ rem,
                                                       int64_t* __restrict__ out)
 {
-    __shared__ double ps[1 << kShotBits];
-    __shared__ double sh[kST];
-    __shared__ int s_last;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * (kST / 64) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (kST / 64);
     const uint32_t bs = 1u << bb;
-    const uint32_t per = bs > kST ? bs / kST : 1;
-    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t per = bs >= 64 ? bs / 64 : 1;
+    const uint32_t nl = bs >= 64 ? 64 : bs;            // lanes that own amplitudes
+    for (uint32_t b = wave; b < nb; b += nwaves) {
         const uint32_t nshot = cnt[b];
         if (nshot == 0) continue;
-        const uint64_t base = (uint64_t)b << bb;
-        for (uint32_t i = threadIdx.x; i < bs; i += kST) ps[i] = prob(psi[base + i]);
-        if (threadIdx.x == 0) s_last = -1;
-        __syncthreads();
-        // thread t owns [t per, (t + 1) per) (threads beyond the block own nothing)
-        const uint32_t i0 = threadIdx.x * per;
-        double run = 0.0;
+        const float2* blk = psi + ((uint64_t)b << bb);
+        const float2* mine = blk + (uint64_t)lane * per;
+        double sum = 0.0;
         int last = -1;
-        if (i0 < bs)
-            for (uint32_t i = 0; i < per; ++i) {
-                const double p = ps[i0 + i];
-                if (p > 0.0) last = (int)(i0 + i);
-                run += p;
-                ps[i0 + i] = run;
+        if ((uint32_t)lane < nl) {
+            if (per >= 2) {
+                const float4* m4 = reinterpret_cast<const float4*>(mine);
+                for (uint32_t i = 0; i < per / 2; ++i) {
+                    const float4 v = m4[i];
+                    const double p0 = prob(make_float2(v.x, v.y)), p1 = prob(make_float2(v.z, v.w));
+                    sum += p0;
+                    if (p0 > 0.0) last = (int)(lane * per + 2 * i);
+                    sum += p1;
+                    if (p1 > 0.0) last = (int)(lane * per + 2 * i + 1);
+                }
+            } else {
+                sum = lane_prob(mine, 0);
+                if (sum > 0.0) last = lane;
             }
-        if (last >= 0) atomicMax(&s_last, last);
-        sh[threadIdx.x] = run;
-        __syncthreads();
-        for (int off = 1; off < kST; off <<= 1) {
-            const double add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0.0;
-            __syncthreads();
-            sh[threadIdx.x] += add;
-            __syncthreads();
         }
-        const double before = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
-        if (i0 < bs)
-            for (uint32_t i = 0; i < per; ++i) ps[i0 + i] += before;
-        __syncthreads();
+        // inclusive scan over the lanes (Hillis-Steele, fixed order)
+        double incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double t = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += t;
+        }
+        int blast = last;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) blast = max(blast, __shfl_xor(blast, off, 64));
         const uint32_t first = cinc[b] - nshot;
-        for (uint32_t j = threadIdx.x; j < nshot; j += kST) {
-            const uint32_t s = order[first + j];
-            const double r = rem[s];
-            uint32_t lo = 0, hi = bs;
-            while (lo < hi) {
+        for (uint32_t j0 = 0; j0 < nshot; j0 += 64) {
+            const bool have = j0 + lane < nshot;
+            const uint32_t s = have ? order[first + j0 + lane] : 0;
+            const double r = have ? rem[s] : 0.0;
+            // first lane whose inclusive sum exceeds r
+            uint32_t lo = 0, hi = nl;
+#pragma unroll
+            for (int step = 0; step < 7; ++step) {
                 const uint32_t mid = lo + (hi - lo) / 2;
-                if (ps[mid] > r) hi = mid;
-                else lo = mid + 1;
+                const double im = __shfl(incl, (int)min(mid, 63u), 64);
+                if (lo < hi) {
+                    if (im > r) hi = mid;
+                    else lo = mid + 1;
+                }
             }
-            const int idx = lo < bs ? (int)lo : s_last;
-            out[s] = idx >= 0 ? (int64_t)(base + (uint32_t)idx) : -1;
+            const double excl = __shfl(incl, (int)(lo > 0 ? min(lo - 1, 63u) : 0u), 64);
+            if (!have) continue;
+            int idx = blast;
+            if (lo < nl) {
+                const double need = r - (lo > 0 ? excl : 0.0);
+                const float2* ch = blk + (uint64_t)lo * per;
+                double run = 0.0;
+                int lastc = -1;
+                idx = -1;
+                for (uint32_t i = 0; i < per; ++i) {
+                    const double p = lane_prob(ch, i);
+                    run += p;
+                    if (p > 0.0) lastc = (int)(lo * per + i);
+                    if (run > need) {
+                        idx = (int)(lo * per + i);
+                        break;
+                    }
+                }
+                if (idx < 0) idx = lastc >= 0 ? lastc : blast;
+            }
+            out[s] = idx >= 0 ? (int64_t)(((uint64_t)b << bb) + (uint32_t)idx) : -1;
         }
-        __syncthreads();
     }
 }
 
@@ -363,7 +398,7 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
     scan_inclusive<uint32_t>(cinc, nb, utmp, st);
     hipLaunchKernelGGL(k_shot_scatter, dim3(sg), dim3(kST), 0, st, blk, a.shots, (uint32_t)nb, cinc, cnt, fill, order);
     SV_HIP(hipGetLastError());
-    const unsigned rg = (unsigned)std::min<uint64_t>(nb, (uint64_t)device_info().cu_count * 8);
+    const unsigned rg = (unsigned)std::min<uint64_t>((nb + 3) / 4, (uint64_t)device_info().cu_count * 8);
     hipLaunchKernelGGL(k_shot_resolve, dim3(rg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, cnt, order, rem,
                        a.out);
     SV_HIP(hipGetLastError());
