@@ -302,6 +302,18 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     t0 = time.perf_counter()
     loss, grad, drift = st.adjoint_grad(circ, terms)
     bwd_ms = min(bwd_ms, (time.perf_counter() - t0) * 1e3)
+    # blocked backward: one sweep per block of gates on 4 or 5 qubits
+    blocked = {}
+    for lb in (4, 5):
+        st.reset()
+        st.run_ops(table, 0, len(circ.ops), p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss_b, grad_b, drift_b = st.adjoint_grad(circ, terms, block_qubits=lb)
+        ms_b = (time.perf_counter() - t0) * 1e3
+        blocked[f"block{lb}"] = {"backward_ms": round(ms_b, 2), "backward_over_forward": round(ms_b / fwd_ms, 3),
+                                 "max_grad_diff_vs_per_gate": float(np.max(np.abs(grad_b[0] - grad[0]))),
+                                 "drift": float(drift_b[0])}
     n_par = circ.n_params
     shift_ms = 2 * n_par * fwd_ms
     res["adjoint"] = {
@@ -311,6 +323,7 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         "param_shift_ms_est": round(shift_ms, 1),
         "speedup_vs_param_shift": round(shift_ms / bwd_ms, 1),
         "loss": float(loss[0]), "grad_norm": float(np.linalg.norm(grad[0])), "drift": float(drift[0]),
+        "blocked": blocked,
     }
     st.free()
     del st

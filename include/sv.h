@@ -252,6 +252,26 @@ sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, cons
                                    void* lambda_buffer, double* grad_out, double* loss_out,
                                    double* drift_out);
 
+/* The same backward with the gates grouped into blocks of at most
+ * block_qubits (4 or 5) qubits by the fusion planner: one sweep per block
+ * loads the 2^block_qubits amplitudes of psi and lambda that differ only in
+ * the block's qubits, and un-applies the block's gates one by one in
+ * registers, adding each derivative term on the way (the per-gate recursion
+ * above, gate by gate, in far fewer sweeps). Derivatives of Pauli rotations
+ * (RX, RY, RZ, RXX, RYY, RZZ, with or without controls) are Im <lam|P|psi> / 2
+ * with pairwise products in FP32 and the accumulation in FP64; the others
+ * use G = dU/dtheta U^* in FP64 as above.
+ *   coeff_rows: NULL (the terms' coeff) or per-row weights as in
+ *     sv_adjoint_grad_weighted.
+ * Outputs and errors as sv_adjoint_grad, plus SV_ERR_INVALID_ARGUMENT for a
+ * block width other than 4 or 5 or n below it, and SV_ERR_UNSUPPORTED for
+ * SV_MATRIX ops on more than two targets. */
+sv_status sv_adjoint_grad_blocked(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                                  int64_t params_batch_stride, int n_params,
+                                  const sv_pauli_term* obs, int n_obs, const double* coeff_rows,
+                                  int block_qubits, void* lambda_buffer, double* grad_out,
+                                  double* loss_out, double* drift_out);
+
 /* ----------------------------------------------------------------- shots */
 
 /* Exact shot sampling (Sec. 4.3.1). Draw n_shots basis indices from row

@@ -106,14 +106,15 @@ struct PlanBlock {
     uint64_t mask = 0;
 };
 
+// The gate's qubits not yet in the block join it (ascending).
 void add_qubits(PlanBlock& b, const PlanGate& g)
 {
-    for (int j = 0; j < g.k + g.nc; ++j) {
-        const int q = j < g.k ? g.targets[j] : g.controls[j - g.k];
-        if (!((b.mask >> q) & 1)) {
-            b.qs.push_back(q);
-            b.mask |= 1ull << q;
-        }
+    uint64_t fresh = g.mask & ~b.mask;
+    while (fresh) {
+        const int q = __builtin_ctzll(fresh);
+        fresh &= fresh - 1;
+        b.qs.push_back(q);
+        b.mask |= 1ull << q;
     }
 }
 
@@ -247,18 +248,37 @@ Blk build_block(const PlanBlock& pb, const std::vector<PlanGate>& gates)
 }
 
 // Every planner, the plan with the fewest blocks (ties: the first).
-std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
+std::vector<PlanBlock> best_plan(const std::vector<PlanGate>& gates, int max_k)
 {
     std::vector<PlanBlock> best = plan_open_blocks(gates, max_k);
     for (int v = 0; v < 3; ++v) {
         std::vector<PlanBlock> p = plan_frontier(gates, max_k, v);
         if (p.size() < best.size()) best = std::move(p);
     }
+    return best;
+}
+
+std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
+{
+    const std::vector<PlanBlock> best = best_plan(gates, max_k);
     std::vector<Blk> out;
     out.reserve(best.size());
     for (const PlanBlock& pb : best) out.push_back(build_block(pb, gates));
     return out;
 }
+
+}  // namespace
+
+std::vector<GateBlock> plan_gate_blocks(const std::vector<uint64_t>& masks, int max_k)
+{
+    std::vector<PlanGate> gates(masks.size());
+    for (size_t i = 0; i < masks.size(); ++i) gates[i].mask = masks[i];
+    std::vector<GateBlock> out;
+    for (PlanBlock& b : best_plan(gates, max_k)) out.push_back(GateBlock{std::move(b.qs), std::move(b.gates)});
+    return out;
+}
+
+namespace {
 
 uint16_t bf16_rne_bits(float x)
 {

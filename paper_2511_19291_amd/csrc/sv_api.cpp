@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -696,6 +697,217 @@ sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* pa
 }
 
 
+// The backward over blocks of gates on at most lb qubits (one sweep per
+// block, k_adj_block). Same quantities as adjoint_impl, gate by gate.
+sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                               int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                               const double* coeff_rows, int lb, void* lambda_buffer, double* grad_out,
+                               double* loss_out, double* drift_out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(lb == 4 || lb == 5, SV_ERR_INVALID_ARGUMENT, "block width must be 4 or 5");
+        need(s->n >= lb, SV_ERR_INVALID_ARGUMENT, "the state has fewer qubits than the block width");
+        need(n_ops >= 0 && (n_ops == 0 || ops != nullptr), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
+        need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
+        need(n_params == 0 || grad_out != nullptr, SV_ERR_INVALID_ARGUMENT, "grad_out is NULL");
+        need(params_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative params stride");
+        check_terms(s->n, obs, n_obs);
+        std::vector<OpInfo> info(n_ops);
+        std::vector<uint64_t> masks(n_ops);
+        for (int i = 0; i < n_ops; ++i) {
+            const sv_op& op = ops[i];
+            info[i] = check_op(s->n, op, n_params);
+            need(op.kind != SV_MATRIX || info[i].k <= 2, SV_ERR_UNSUPPORTED, "matrix ops of more than two targets");
+            need(info[i].np <= (info[i].k == 1 ? 3 : 1), SV_ERR_UNSUPPORTED, "two-target kinds with several parameters");
+            for (int j = 0; j < info[i].k; ++j) masks[i] |= 1ull << op.targets[j];
+            for (int j = 0; j < op.n_controls; ++j) masks[i] |= 1ull << op.controls[j];
+        }
+        check_not_capturing(s->stream);
+
+        const int B = s->batch;
+        const bool per_row = params_batch_stride != 0 && B > 1;
+        float2* lam = nullptr;
+        ensure_lambda(s, lambda_buffer, &lam);
+        PauliTermDev* dterms = nullptr;
+        const double* dcoeff = nullptr;
+        upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
+
+        // ---- plan on the host: launches (block, row set, gate range) and their gate tables
+        struct Launch {
+            int row;                      // -1: all rows
+            std::array<int, kAdjBlockMaxBits> q;
+            size_t first;                 // first entry in the gate table
+            int ngates;
+            int nslots;
+            std::vector<int> slot_param;  // parameter of each slot
+        };
+        std::vector<Launch> launches;
+        std::vector<AdjBlockGate> table;
+        const std::vector<GateBlock> blocks = plan_gate_blocks(masks, lb);
+        for (int bi = (int)blocks.size() - 1; bi >= 0; --bi) {
+            const GateBlock& gb = blocks[bi];
+            // local qubits: the block's, padded with the lowest free qubits, ascending
+            uint64_t used = 0;
+            for (int q : gb.qs) used |= 1ull << q;
+            for (int q = 0; q < s->n && __builtin_popcountll(used) < lb; ++q) used |= 1ull << q;
+            std::array<int, kAdjBlockMaxBits> lq{};
+            int nq = 0;
+            for (int q = 0; q < s->n; ++q)
+                if ((used >> q) & 1) lq[nq++] = q;
+            auto local = [&](int q) {
+                for (int i = 0; i < lb; ++i)
+                    if (lq[i] == q) return i;
+                return -1;
+            };
+            bool rows_differ = false;
+            if (per_row)
+                for (int gi : gb.gates)
+                    if (info[gi].np > 0 && !same_params_all_rows(ops[gi], info[gi], params, params_batch_stride, B))
+                        rows_differ = true;
+            const int nrl = rows_differ ? B : 1;
+            for (int rl = 0; rl < nrl; ++rl) {
+                const double* prow = params + (rows_differ ? rl * params_batch_stride : 0);
+                Launch L{};
+                L.row = rows_differ ? rl : -1;
+                L.q = lq;
+                L.first = table.size();
+                auto close = [&] {
+                    if (L.ngates > 0) launches.push_back(L);
+                    L.first = table.size();
+                    L.ngates = 0;
+                    L.nslots = 0;
+                    L.slot_param.clear();
+                };
+                for (int t = (int)gb.gates.size() - 1; t >= 0; --t) {
+                    const int gi = gb.gates[t];
+                    const sv_op& op = ops[gi];
+                    const OpInfo& oi = info[gi];
+                    if (L.nslots + oi.np > kAdjBlockMaxSlots) close();
+                    const int D = 1 << oi.k;
+                    double prm[3];
+                    op_params(op, oi, prow, prm);
+                    cd m[16], md[16];
+                    op_matrix(op, oi, prow, m);
+                    dagger(oi.k, m, md);
+                    AdjBlockGate g{};
+                    g.nt = oi.k;
+                    g.t0 = local(op.targets[0]);
+                    g.t1 = oi.k == 2 ? local(op.targets[1]) : 0;
+                    for (int j = 0; j < op.n_controls; ++j) g.cmask |= 1 << local(op.controls[j]);
+                    for (int q = 0; q < D * D; ++q) g.u[q] = f2(md[q]);
+                    bool diag = true;
+                    for (int r = 0; r < D; ++r)
+                        for (int c = 0; c < D; ++c)
+                            if (r != c && md[r * D + c] != cd(0.0)) diag = false;
+                    const bool exch = oi.k == 1 && md[0] == cd(0.0) && md[3] == cd(0.0) && md[1] == cd(1.0) &&
+                                      md[2] == cd(1.0);
+                    g.form = exch ? 2 : (diag ? 1 : 0);
+                    g.nd = oi.np;
+                    switch (op.kind) {
+                    case SV_RX: g.pauli = 1; break;
+                    case SV_RY: g.pauli = 2; break;
+                    case SV_RZ: g.pauli = 3; break;
+                    case SV_RXX: g.pauli = 4; break;
+                    case SV_RYY: g.pauli = 5; break;
+                    case SV_RZZ: g.pauli = 6; break;
+                    default: g.pauli = 0; break;
+                    }
+                    for (int d = 0; d < oi.np; ++d) {
+                        g.slot[d] = L.nslots++;
+                        L.slot_param.push_back(op.param[d]);
+                        if (g.pauli) continue;
+                        cd dm[16];
+                        kind_dmatrix(op.kind, prm, d, dm);
+                        for (int r = 0; r < D; ++r)
+                            for (int c = 0; c < D; ++c) {
+                                cd acc = 0.0;
+                                for (int j = 0; j < D; ++j) acc += dm[r * D + j] * md[j * D + c];
+                                g.g[d][r * D + c] = make_double2(acc.real(), acc.imag());
+                            }
+                    }
+                    table.push_back(g);
+                    ++L.ngates;
+                }
+                close();
+            }
+        }
+
+        // ---- device buffers: gate table, partials, slot sums
+        const int G = adj_block_grid(s->n, lb);
+        uint64_t nslot_total = 0, part_max = 1;
+        for (const Launch& L : launches) {
+            const int rows_here = L.row < 0 ? B : 1;
+            nslot_total += (uint64_t)rows_here * L.nslots;
+            part_max = std::max<uint64_t>(part_max, (uint64_t)rows_here * L.nslots * 4 * G);
+        }
+        const uint64_t red = std::max<uint64_t>(inner_parts(s->n, B), drift_parts(s->n, B));
+        const uint64_t table_doubles = (table.size() * sizeof(AdjBlockGate) + 7) / 8 + 2;
+        const uint64_t table_at = (part_max + red + 1) & ~1ull;       // 16-byte aligned
+        ensure_scratch(s, table_at + table_doubles);
+        double* part = s->scratch;
+        double* rscratch = s->scratch + part_max;
+        AdjBlockGate* dtable = reinterpret_cast<AdjBlockGate*>(s->scratch + table_at);
+        if (!table.empty())
+            SV_HIP(hipMemcpyAsync(dtable, table.data(), table.size() * sizeof(AdjBlockGate), hipMemcpyHostToDevice,
+                                  s->stream));
+        const uint64_t nout = std::max<uint64_t>(nslot_total, 1) + 3ull * B;
+        ensure_dout(s, nout + 2ull * B);
+        double* d_slots = s->dout;
+        double* d_loss = s->dout + std::max<uint64_t>(nslot_total, 1);
+        double* d_drift = d_loss + 2ull * B;
+
+        const Rows prow{s->psi, s->psi, B, B, s->N};
+        const Rows lrow{lam, lam, B, B, s->N};
+        launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
+
+        struct Slot { int row; int param; };
+        std::vector<Slot> slots;
+        slots.reserve(nslot_total);
+        uint64_t cur = 0;
+        for (const Launch& L : launches) {
+            AdjBlockLaunch a{};
+            if (L.row >= 0) {
+                a.psi = one_row(s, s->psi, L.row);
+                a.lam = one_row(s, lam, L.row);
+            } else {
+                a.psi = prow;
+                a.lam = lrow;
+            }
+            for (int i = 0; i < lb; ++i) {
+                a.q[i] = L.q[i];
+                a.qbit[i] = 1ull << L.q[i];
+            }
+            a.lb = lb;
+            a.ngates = L.ngates;
+            a.gates = dtable + L.first;
+            a.nslots = L.nslots;
+            a.grid = G;
+            launch_adj_block(a, part, s->stream);
+            const int rows_here = L.row < 0 ? B : 1;
+            if (L.nslots > 0) {
+                launch_sum_slots(part, 4 * G, rows_here * L.nslots, d_slots + cur, s->stream);
+                for (int r = 0; r < rows_here; ++r)
+                    for (int q = 0; q < L.nslots; ++q) slots.push_back(Slot{L.row >= 0 ? L.row : r, L.slot_param[q]});
+                cur += (uint64_t)rows_here * L.nslots;
+            }
+        }
+        launch_drift(prow, s->n, rscratch, d_drift, s->stream);
+        SV_HIP(hipMemcpyAsync(s->hout, s->dout, nout * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        SV_HIP(hipStreamSynchronize(s->stream));
+        const double* h_slots = s->hout;
+        const double* h_loss = s->hout + std::max<uint64_t>(nslot_total, 1);
+        const double* h_drift = h_loss + 2ull * B;
+        if (n_params > 0) std::fill(grad_out, grad_out + (size_t)B * n_params, 0.0);
+        for (uint64_t q = 0; q < cur; ++q) grad_out[(size_t)slots[q].row * n_params + slots[q].param] += 2.0 * h_slots[q];
+        for (int r = 0; r < B; ++r) {
+            if (loss_out) loss_out[r] = h_loss[2 * r];
+            if (drift_out) drift_out[r] = std::sqrt(std::max(0.0, h_drift[r]));
+        }
+    });
+}
+
 }  // namespace
 
 extern "C" {
@@ -719,6 +931,15 @@ sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, cons
     }
     return adjoint_impl(s, ops, n_ops, params, params_batch_stride, n_params, obs, n_obs, coeff_rows, lambda_buffer,
                         grad_out, loss_out, drift_out);
+}
+
+sv_status sv_adjoint_grad_blocked(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                                  int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                                  const double* coeff_rows, int block_qubits, void* lambda_buffer, double* grad_out,
+                                  double* loss_out, double* drift_out)
+{
+    return adjoint_blocked_impl(s, ops, n_ops, params, params_batch_stride, n_params, obs, n_obs, coeff_rows,
+                                block_qubits, lambda_buffer, grad_out, loss_out, drift_out);
 }
 
 sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64_t n_shots, int64_t* dev_out)

@@ -142,6 +142,46 @@ struct GaussLaunch {
 uint64_t gauss_scratch_doubles(int n);
 void launch_sample_gaussian(const GaussLaunch& a, hipStream_t st);
 
+// ------------------------------------------------------------ blocked adjoint
+// Block planning on qubit masks only (the fusion planners): per block its
+// qubits and its gates (indices into the mask list, circuit order).
+struct GateBlock {
+    std::vector<int> qs;
+    std::vector<int> gates;
+};
+std::vector<GateBlock> plan_gate_blocks(const std::vector<uint64_t>& masks, int max_k);
+
+constexpr int kAdjBlockMaxBits = 5;       // local bits of a column (16 or 32 amplitudes)
+constexpr int kAdjBlockMaxSlots = 64;     // derivative slots per block launch
+
+// One gate of a block, in local bit positions.
+struct AdjBlockGate {
+    int nt;                   // 1 or 2 targets
+    int t0, t1;               // local target bits (t0 = most significant matrix bit)
+    int cmask;                // local control bits
+    int nd;                   // derivatives (0..3; at most 1 for two targets)
+    int slot[3];              // slot of each derivative within the launch
+    int form;                 // U^*: 0 dense, 1 diagonal, 2 plain exchange (X)
+    int pauli;                // derivative of exp(-i theta P / 2): 1 X, 2 Y, 3 Z, 4 XX, 5 YY, 6 ZZ; 0 general
+    float2 u[16];             // U^* (complex64)
+    double2 g[3][16];         // G_d = dU/dtheta_d U^* (complex128), general derivatives
+};
+
+struct AdjBlockLaunch {
+    Rows psi;
+    Rows lam;
+    uint64_t qbit[kAdjBlockMaxBits]; // 1 << qubit of each local bit (ascending qubits)
+    int q[kAdjBlockMaxBits];
+    int lb;                          // local bits: 4 or 5
+    int ngates;
+    const AdjBlockGate* gates;       // device, in un-apply order (the block's last gate first)
+    int nslots;
+    int grid;                        // workgroups per row
+};
+// partials: part[(row * nslots + s) * (4 * grid) + wave]
+void launch_adj_block(const AdjBlockLaunch& a, double* part, hipStream_t st);
+int adj_block_grid(int n, int lb);
+
 struct AdjLaunch {
     Rows psi;                 // rows of psi
     Rows lam;                 // rows of lambda (same count)

@@ -105,6 +105,8 @@ def lib() -> C.CDLL:
                             vp, dp, dp, dp],
         "sv_adjoint_grad_weighted": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm),
                                      C.c_int, dp, vp, dp, dp, dp],
+        "sv_adjoint_grad_blocked": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm),
+                                    C.c_int, dp, C.c_int, vp, dp, dp, dp],
         "sv_batch_plan_create": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, vp, C.POINTER(vp)],
         "sv_batch_default_config": [C.POINTER(SvBatchConfig)],
         "sv_batch_plan_create_ex": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, C.POINTER(SvBatchConfig), vp,
@@ -324,11 +326,13 @@ class State:
         return y
 
     def adjoint_grad(self, circuit, terms: Sequence[Tuple[float, int, int]], params=None,
-                     lambda_tensor=None, coeff_rows=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+                     lambda_tensor=None, coeff_rows=None, block_qubits: int = 0) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         """The state must hold the forward output of ``circuit``. Returns
         (loss [batch], grad [batch, n_params], drift [batch]) and leaves the
         recomputed start state in the state. ``coeff_rows`` ([batch, n_terms])
-        replaces the terms' coefficients row by row."""
+        replaces the terms' coefficients row by row. ``block_qubits`` 4 or 5
+        runs the blocked backward (one sweep per block of gates), 0 the
+        per-gate one."""
         table = OpTable(circuit.ops)
         p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
         grad = np.zeros((self.batch, max(npar, 1)), dtype=np.float64)
@@ -336,7 +340,14 @@ class State:
         drift = np.zeros(self.batch, dtype=np.float64)
         lam = C.c_void_p(lambda_tensor.data_ptr()) if lambda_tensor is not None else None
         pp = _dptr(p) if npar else None
-        if coeff_rows is None:
+        if block_qubits:
+            cr = None
+            if coeff_rows is not None:
+                cr = np.ascontiguousarray(np.asarray(coeff_rows, dtype=np.float64).reshape(self.batch, len(terms)))
+            check(lib().sv_adjoint_grad_blocked(self.h, table.ptr, table.n, pp, stride, npar, pauli_terms(terms),
+                                                len(terms), _dptr(cr) if cr is not None else None, block_qubits, lam,
+                                                _dptr(grad), _dptr(loss), _dptr(drift)))
+        elif coeff_rows is None:
             check(lib().sv_adjoint_grad(self.h, table.ptr, table.n, pp, stride, npar, pauli_terms(terms), len(terms),
                                         lam, _dptr(grad), _dptr(loss), _dptr(drift)))
         else:
