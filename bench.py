@@ -302,9 +302,9 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     t0 = time.perf_counter()
     loss, grad, drift = st.adjoint_grad(circ, terms)
     bwd_ms = min(bwd_ms, (time.perf_counter() - t0) * 1e3)
-    # blocked backward: one sweep per block of gates on 4 or 5 qubits
+    # blocked backward: one sweep per block of gates on 3, 4 or 5 qubits
     blocked = {}
-    for lb in (4, 5):
+    for lb in (3, 4, 5):
         st.reset()
         st.run_ops(table, 0, len(circ.ops), p)
         torch.cuda.synchronize()

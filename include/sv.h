@@ -253,7 +253,7 @@ sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, cons
                                    double* drift_out);
 
 /* The same backward with the gates grouped into blocks of at most
- * block_qubits (4 or 5) qubits by the fusion planner: one sweep per block
+ * block_qubits (3, 4 or 5) qubits by the fusion planner: one sweep per block
  * loads the 2^block_qubits amplitudes of psi and lambda that differ only in
  * the block's qubits, and un-applies the block's gates one by one in
  * registers, adding each derivative term on the way (the per-gate recursion
@@ -264,7 +264,7 @@ sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, cons
  *   coeff_rows: NULL (the terms' coeff) or per-row weights as in
  *     sv_adjoint_grad_weighted.
  * Outputs and errors as sv_adjoint_grad, plus SV_ERR_INVALID_ARGUMENT for a
- * block width other than 4 or 5 or n below it, and SV_ERR_UNSUPPORTED for
+ * block width outside 3..5 or n below it, and SV_ERR_UNSUPPORTED for
  * SV_MATRIX ops on more than two targets. */
 sv_status sv_adjoint_grad_blocked(sv_state s, const sv_op* ops, int n_ops, const double* params,
                                   int64_t params_batch_stride, int n_params,

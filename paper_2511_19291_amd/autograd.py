@@ -5,7 +5,9 @@ Forward: reset the state to |0..0>, run the circuit with the given
 parameters, return L = sum_t coeff_t <P_t> per batch row. Backward: the
 library un-applies the gates from the forward output (x = U^* y) and
 accumulates dL/dtheta in FP64; nothing is stored between the passes except
-the final state itself. The state object therefore holds one pending
+the final state itself. By default the backward groups the gates into
+4-qubit blocks (one sweep per block, ``sv_adjoint_grad_blocked``) when every
+gate fits; ``block_qubits=0`` selects the per-gate backward. The state object therefore holds one pending
 forward at a time: run backward before the next forward on the same state.
 """
 
@@ -19,9 +21,25 @@ import torch
 from . import sv
 
 
+def default_block_qubits(circuit) -> int:
+    """Block width of the blocked adjoint backward for this circuit: 4 (the
+    fastest measured) when every gate fits in four qubits and n >= 4, else 0
+    (the per-gate backward)."""
+    if circuit.n < 4:
+        return 0
+    for op in circuit.ops:
+        if len(op.targets) + len(op.controls) > 4:
+            return 0
+        if len(op.targets) == 2 and op.params and op.kind not in ("rxx", "ryy", "rzz"):
+            return 0
+    return 4
+
+
 class AdjointExpval(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, params: torch.Tensor, circuit, terms: Sequence[Tuple[float, int, int]], state: "sv.State"):
+    def forward(ctx, params: torch.Tensor, circuit, terms: Sequence[Tuple[float, int, int]], state: "sv.State",
+                block_qubits: int = 0):
+        ctx.block_qubits = block_qubits
         p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy())
         state.reset()
         state.run(circuit, params=p)
@@ -37,25 +55,27 @@ class AdjointExpval(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, ctx.terms, params=ctx.p)
+        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, ctx.terms, params=ctx.p, block_qubits=ctx.block_qubits)
         go = grad_out.detach().to("cpu", torch.float64).reshape(-1, 1).numpy()
         g = grad * go                              # [batch, n_params]
         g = torch.from_numpy(g.reshape(ctx.shape)).to(device=grad_out.device, dtype=grad_out.dtype)
-        return g, None, None, None
+        return g, None, None, None, None
 
 
 class QuantumExpval(torch.nn.Module):
     """A fixed circuit and observable; forward(params) -> L (per batch row),
     differentiable through the adjoint backward."""
 
-    def __init__(self, circuit, terms: Sequence[Tuple[float, int, int]], batch: int = 1, device=None):
+    def __init__(self, circuit, terms: Sequence[Tuple[float, int, int]], batch: int = 1, device=None,
+                 block_qubits=None):
         super().__init__()
         self.circuit = circuit
         self.terms = list(terms)
         self.state = sv.State(circuit.n, batch, device=device)
+        self.block_qubits = default_block_qubits(circuit) if block_qubits is None else block_qubits
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
-        return AdjointExpval.apply(params, self.circuit, self.terms, self.state)
+        return AdjointExpval.apply(params, self.circuit, self.terms, self.state, self.block_qubits)
 
 
 class ExpvalZ(torch.autograd.Function):
@@ -65,7 +85,8 @@ class ExpvalZ(torch.autograd.Function):
     observable sum_i g[r, i] Z_i of row r (``sv_adjoint_grad_weighted``)."""
 
     @staticmethod
-    def forward(ctx, params: torch.Tensor, circuit, state: "sv.State"):
+    def forward(ctx, params: torch.Tensor, circuit, state: "sv.State", block_qubits: int = 0):
+        ctx.block_qubits = block_qubits
         p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, -1))
         state.reset()
         state.run(circuit, params=p if state.batch > 1 else p[0])
@@ -82,9 +103,9 @@ class ExpvalZ(torch.autograd.Function):
         terms = [(1.0, 0, 1 << i) for i in range(n)]
         g = np.ascontiguousarray(grad_z.detach().to("cpu", torch.float64).numpy().reshape(ctx.state.batch, n))
         p = ctx.p if ctx.state.batch > 1 else ctx.p[0]
-        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, terms, params=p, coeff_rows=g)
+        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, terms, params=p, coeff_rows=g, block_qubits=ctx.block_qubits)
         out = torch.from_numpy(grad.reshape(ctx.shape)).to(device=grad_z.device, dtype=grad_z.dtype)
-        return out, None, None
+        return out, None, None, None
 
 
 class MeasureAllZ(torch.nn.Module):
@@ -93,10 +114,11 @@ class MeasureAllZ(torch.nn.Module):
     adjoint backward (the appendix example's measure_allZ on an invertible
     device)."""
 
-    def __init__(self, circuit, batch: int = 1, device=None):
+    def __init__(self, circuit, batch: int = 1, device=None, block_qubits=None):
         super().__init__()
         self.circuit = circuit
         self.state = sv.State(circuit.n, batch, device=device)
+        self.block_qubits = default_block_qubits(circuit) if block_qubits is None else block_qubits
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
-        return ExpvalZ.apply(params, self.circuit, self.state)
+        return ExpvalZ.apply(params, self.circuit, self.state, self.block_qubits)

@@ -272,7 +272,11 @@ std::vector<Blk> plan(const std::vector<PlanGate>& gates, int max_k)
 std::vector<GateBlock> plan_gate_blocks(const std::vector<uint64_t>& masks, int max_k)
 {
     std::vector<PlanGate> gates(masks.size());
-    for (size_t i = 0; i < masks.size(); ++i) gates[i].mask = masks[i];
+    for (size_t i = 0; i < masks.size(); ++i) {
+        // the planners need every gate to fit a block on its own
+        need(__builtin_popcountll(masks[i]) <= max_k, SV_ERR_UNSUPPORTED, "a gate has more qubits than the block width");
+        gates[i].mask = masks[i];
+    }
     std::vector<GateBlock> out;
     for (PlanBlock& b : best_plan(gates, max_k)) out.push_back(GateBlock{std::move(b.qs), std::move(b.gates)});
     return out;

@@ -2,7 +2,7 @@
 //
 // The per-gate backward (k_adjoint.hip) un-applies one gate per sweep over
 // psi and lambda (Sec. 4.4: the layer input is recomputed as x = U^* y). When
-// a run of gates acts on at most LB = 4 or 5 qubits, all of its steps are
+// a run of gates acts on at most LB = 3, 4 or 5 qubits, all of its steps are
 // local to the 2^LB amplitudes that differ only in those qubits (a column):
 // one sweep loads each column of psi_l and lambda_l into registers, and for
 // the block's gates from last to first adds the derivative terms and
@@ -67,43 +67,24 @@ __device__ __forceinline__ double grad_general(const double2* __restrict__ g, co
     return acc;
 }
 
-// Im <l|P|x> over a group for P a Pauli on the group's target bits:
-// pauli = 1 X, 2 Y, 3 Z (one target) or 4 XX, 5 YY, 6 ZZ (two targets)
-template <int D>
-__device__ __forceinline__ float grad_pauli(int pauli, const float2 (&x)[D], const float2 (&l)[D])
+// Im <l|P|x> over a group for the Pauli P (compile-time): 1 X, 2 Y, 3 Z
+// (one target) or 4 XX, 5 YY, 6 ZZ (two targets; member r = (bit of t0,
+// bit of t1): XX maps r to 3 - r, YY the same with signs -, +, +, -, ZZ is
+// diagonal with signs (-1)^popcount(r))
+template <int PK, int D>
+__device__ __forceinline__ float grad_pauli(const float2 (&x)[D], const float2 (&l)[D])
 {
-    if constexpr (D == 2) {
-        switch (pauli) {
-        case 1: return im_cb(l[0], x[1]) + im_cb(l[1], x[0]);
-        case 2: return -re_cb(l[0], x[1]) + re_cb(l[1], x[0]);
-        default: return im_cb(l[0], x[0]) - im_cb(l[1], x[1]);
-        }
-    } else {
-        // member r = (bit of t0, bit of t1); XX: r <-> 3 - r; YY: i^2 sign
-        // (-1)^(bits equal); ZZ: sign (-1)^(popcount r)
-        switch (pauli) {
-        case 4: return im_cb(l[0], x[3]) + im_cb(l[1], x[2]) + im_cb(l[2], x[1]) + im_cb(l[3], x[0]);
-        case 5: return -im_cb(l[0], x[3]) + im_cb(l[1], x[2]) + im_cb(l[2], x[1]) - im_cb(l[3], x[0]);
-        default: return im_cb(l[0], x[0]) - im_cb(l[1], x[1]) - im_cb(l[2], x[2]) + im_cb(l[3], x[3]);
-        }
-    }
+    if constexpr (PK == 1) return im_cb(l[0], x[1]) + im_cb(l[1], x[0]);
+    else if constexpr (PK == 2) return -re_cb(l[0], x[1]) + re_cb(l[1], x[0]);
+    else if constexpr (PK == 3) return im_cb(l[0], x[0]) - im_cb(l[1], x[1]);
+    else if constexpr (PK == 4) return im_cb(l[0], x[3]) + im_cb(l[1], x[2]) + im_cb(l[2], x[1]) + im_cb(l[3], x[0]);
+    else if constexpr (PK == 5) return -im_cb(l[0], x[3]) + im_cb(l[1], x[2]) + im_cb(l[2], x[1]) - im_cb(l[3], x[0]);
+    else return im_cb(l[0], x[0]) - im_cb(l[1], x[1]) - im_cb(l[2], x[2]) + im_cb(l[3], x[3]);
 }
 
 template <int D>
-__device__ __forceinline__ void unapply(int form, const float2* __restrict__ u, float2 (&x)[D])
+__device__ __forceinline__ void unapply_dense(const float2 (&u)[D * D], float2 (&x)[D])
 {
-    if (form == 2) {
-        // plain exchange of the two members (X)
-        const float2 t = x[0];
-        x[0] = x[1];
-        x[1] = t;
-        return;
-    }
-    if (form == 1) {
-#pragma unroll
-        for (int i = 0; i < D; ++i) x[i] = cmul(u[i * D + i], x[i]);
-        return;
-    }
     float2 y[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -116,16 +97,28 @@ __device__ __forceinline__ void unapply(int form, const float2* __restrict__ u, 
     for (int i = 0; i < D; ++i) x[i] = y[i];
 }
 
+// Gate modes (uniform over a launch, resolved before the column loop so the
+// unrolled group loop carries no branches): exchange (X, controlled or not,
+// no parameter), dense U^* without derivative, dense U^* with the Pauli
+// derivative PK, dense U^* with general FP64 derivatives.
+enum { kModeExchange = 0, kModeDense = 1, kModePauli = 2, kModeGeneral = 3 };
+
 // One gate on the column: derivative terms (on psi_l, lambda_l), then
 // psi <- U^* psi, lambda <- U^* lambda. Groups: the amplitudes whose local
 // index differs only in the target bits, with every control bit set.
-template <int L, int NT, int T0, int T1>
+template <int L, int NT, int T0, int T1, int MODE, int PK>
 __device__ __forceinline__ void column_gate(const AdjBlockGate& G, float2 (&x)[L], float2 (&l)[L], double (&part)[3])
 {
     constexpr int D = 1 << NT;
     constexpr int tm = NT == 1 ? (1 << T0) : ((1 << T0) | (1 << T1));
-    const int cm = G.cmask, nd = G.nd, pauli = G.pauli, form = G.form;
+    const int cm = G.cmask;
+    float2 u[D * D];
+    if constexpr (MODE != kModeExchange) {
+#pragma unroll
+        for (int q = 0; q < D * D; ++q) u[q] = G.u[q];
+    }
     float pp = 0.f;
+    double gacc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < L; ++j) {
         if (j & tm) continue;
@@ -146,22 +139,61 @@ __device__ __forceinline__ void column_gate(const AdjBlockGate& G, float2 (&x)[L
             xs[r] = x[idx[r]];
             ls[r] = l[idx[r]];
         }
-        if (pauli) {
-            pp += grad_pauli<D>(pauli, xs, ls);
-        } else {
+        if constexpr (MODE == kModePauli) pp += grad_pauli<PK, D>(xs, ls);
+        if constexpr (MODE == kModeGeneral) {
 #pragma unroll
             for (int d = 0; d < (NT == 1 ? 3 : 1); ++d)
-                if (d < nd) part[d] += grad_general<D>(G.g[d], xs, ls);
+                if (d < G.nd) gacc[d] += grad_general<D>(G.g[d], xs, ls);
         }
-        unapply<D>(form, G.u, xs);
-        unapply<D>(form, G.u, ls);
+        if constexpr (MODE == kModeExchange) {
+            x[idx[0]] = xs[1];
+            x[idx[1]] = xs[0];
+            l[idx[0]] = ls[1];
+            l[idx[1]] = ls[0];
+        } else {
+            unapply_dense<D>(u, xs);
+            unapply_dense<D>(u, ls);
 #pragma unroll
-        for (int r = 0; r < D; ++r) {
-            x[idx[r]] = xs[r];
-            l[idx[r]] = ls[r];
+            for (int r = 0; r < D; ++r) {
+                x[idx[r]] = xs[r];
+                l[idx[r]] = ls[r];
+            }
         }
     }
-    if (pauli) part[0] = 0.5 * (double)pp;
+    if constexpr (MODE == kModePauli) part[0] = 0.5 * (double)pp;
+    if constexpr (MODE == kModeGeneral)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) part[d] = gacc[d];
+}
+
+template <int L, int NT, int T0, int T1>
+__device__ __forceinline__ void gate_modes(const AdjBlockGate& G, float2 (&x)[L], float2 (&l)[L], double (&part)[3])
+{
+    if constexpr (NT == 1) {
+        if (G.nd == 0) {
+            if (G.form == 2) column_gate<L, 1, T0, 0, kModeExchange, 0>(G, x, l, part);
+            else column_gate<L, 1, T0, 0, kModeDense, 0>(G, x, l, part);
+        } else {
+            switch (G.pauli) {
+            case 1: column_gate<L, 1, T0, 0, kModePauli, 1>(G, x, l, part); break;
+            case 2: column_gate<L, 1, T0, 0, kModePauli, 2>(G, x, l, part); break;
+            case 3: column_gate<L, 1, T0, 0, kModePauli, 3>(G, x, l, part); break;
+            default: column_gate<L, 1, T0, 0, kModeGeneral, 0>(G, x, l, part); break;
+            }
+        }
+    } else {
+        if (G.nd == 0) {
+            column_gate<L, 2, T0, T1, kModeDense, 0>(G, x, l, part);
+        } else {
+            // the two-target kinds with a parameter are the Pauli rotations
+            // RXX, RYY, RZZ (the host refuses anything else)
+            switch (G.pauli) {
+            case 4: column_gate<L, 2, T0, T1, kModePauli, 4>(G, x, l, part); break;
+            case 5: column_gate<L, 2, T0, T1, kModePauli, 5>(G, x, l, part); break;
+            default: column_gate<L, 2, T0, T1, kModePauli, 6>(G, x, l, part); break;
+            }
+        }
+    }
 }
 
 template <int L>
@@ -169,24 +201,31 @@ __device__ __forceinline__ void dispatch_gate(const AdjBlockGate& G, float2 (&x)
 {
     if (G.nt == 1) {
         switch (G.t0) {
-        case 0: column_gate<L, 1, 0, 0>(G, x, l, part); break;
-        case 1: column_gate<L, 1, 1, 0>(G, x, l, part); break;
-        case 2: column_gate<L, 1, 2, 0>(G, x, l, part); break;
-        case 3: column_gate<L, 1, 3, 0>(G, x, l, part); break;
+        case 0: gate_modes<L, 1, 0, 0>(G, x, l, part); break;
+        case 1: gate_modes<L, 1, 1, 0>(G, x, l, part); break;
+        case 2: gate_modes<L, 1, 2, 0>(G, x, l, part); break;
+        case 3:
+            if constexpr (L >= 16) gate_modes<L, 1, 3, 0>(G, x, l, part);
+            break;
         default:
-            if constexpr (L == 32) column_gate<L, 1, 4, 0>(G, x, l, part);
+            if constexpr (L == 32) gate_modes<L, 1, 4, 0>(G, x, l, part);
             break;
         }
         return;
     }
-#define SV_ADJ2(a, b) case a * 8 + b: column_gate<L, 2, a, b>(G, x, l, part); break;
-    if constexpr (L == 16) {
+#define SV_ADJ2(a, b) case a * 8 + b: gate_modes<L, 2, a, b>(G, x, l, part); break;
+    if constexpr (L == 8) {
+        switch (G.t0 * 8 + G.t1) {
+        SV_ADJ2(0, 1) SV_ADJ2(0, 2) SV_ADJ2(1, 0) SV_ADJ2(1, 2) SV_ADJ2(2, 0)
+        default: gate_modes<L, 2, 2, 1>(G, x, l, part); break;
+        }
+    } else if constexpr (L == 16) {
         switch (G.t0 * 8 + G.t1) {
         SV_ADJ2(0, 1) SV_ADJ2(0, 2) SV_ADJ2(0, 3)
         SV_ADJ2(1, 0) SV_ADJ2(1, 2) SV_ADJ2(1, 3)
         SV_ADJ2(2, 0) SV_ADJ2(2, 1) SV_ADJ2(2, 3)
         SV_ADJ2(3, 0) SV_ADJ2(3, 1)
-        default: column_gate<L, 2, 3, 2>(G, x, l, part); break;
+        default: gate_modes<L, 2, 3, 2>(G, x, l, part); break;
         }
     } else {
         switch (G.t0 * 8 + G.t1) {
@@ -195,7 +234,7 @@ __device__ __forceinline__ void dispatch_gate(const AdjBlockGate& G, float2 (&x)
         SV_ADJ2(2, 0) SV_ADJ2(2, 1) SV_ADJ2(2, 3) SV_ADJ2(2, 4)
         SV_ADJ2(3, 0) SV_ADJ2(3, 1) SV_ADJ2(3, 2) SV_ADJ2(3, 4)
         SV_ADJ2(4, 0) SV_ADJ2(4, 1) SV_ADJ2(4, 2)
-        default: column_gate<L, 2, 4, 3>(G, x, l, part); break;
+        default: gate_modes<L, 2, 4, 3>(G, x, l, part); break;
         }
     }
 #undef SV_ADJ2
@@ -272,7 +311,9 @@ int adj_block_grid(int n, int lb)
 
 void launch_adj_block(const AdjBlockLaunch& a, double* part, hipStream_t st)
 {
-    if (a.lb == 4)
+    if (a.lb == 3)
+        hipLaunchKernelGGL(k_adj_block<3>, dim3(a.grid, a.psi.nrows), dim3(256), 0, st, a, part);
+    else if (a.lb == 4)
         hipLaunchKernelGGL(k_adj_block<4>, dim3(a.grid, a.psi.nrows), dim3(256), 0, st, a, part);
     else
         hipLaunchKernelGGL(k_adj_block<5>, dim3(a.grid, a.psi.nrows), dim3(256), 0, st, a, part);

@@ -706,7 +706,7 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
 {
     return guarded([&] {
         check_state(s);
-        need(lb == 4 || lb == 5, SV_ERR_INVALID_ARGUMENT, "block width must be 4 or 5");
+        need(lb >= 3 && lb <= 5, SV_ERR_INVALID_ARGUMENT, "block width must be 3, 4 or 5");
         need(s->n >= lb, SV_ERR_INVALID_ARGUMENT, "the state has fewer qubits than the block width");
         need(n_ops >= 0 && (n_ops == 0 || ops != nullptr), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
         need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
@@ -720,8 +720,12 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
             info[i] = check_op(s->n, op, n_params);
             need(op.kind != SV_MATRIX || info[i].k <= 2, SV_ERR_UNSUPPORTED, "matrix ops of more than two targets");
             need(info[i].np <= (info[i].k == 1 ? 3 : 1), SV_ERR_UNSUPPORTED, "two-target kinds with several parameters");
+            need(info[i].k == 1 || info[i].np == 0 || op.kind == SV_RXX || op.kind == SV_RYY || op.kind == SV_RZZ,
+                 SV_ERR_UNSUPPORTED, "parameterised two-target ops other than RXX, RYY, RZZ");
             for (int j = 0; j < info[i].k; ++j) masks[i] |= 1ull << op.targets[j];
             for (int j = 0; j < op.n_controls; ++j) masks[i] |= 1ull << op.controls[j];
+            need(__builtin_popcountll(masks[i]) <= lb, SV_ERR_UNSUPPORTED,
+                 "op " + std::to_string(i) + " acts on more qubits than the block width");
         }
         check_not_capturing(s->stream);
 

@@ -151,7 +151,7 @@ struct GateBlock {
 };
 std::vector<GateBlock> plan_gate_blocks(const std::vector<uint64_t>& masks, int max_k);
 
-constexpr int kAdjBlockMaxBits = 5;       // local bits of a column (16 or 32 amplitudes)
+constexpr int kAdjBlockMaxBits = 5;       // local bits of a column (8, 16 or 32 amplitudes)
 constexpr int kAdjBlockMaxSlots = 64;     // derivative slots per block launch
 
 // One gate of a block, in local bit positions.
@@ -172,7 +172,7 @@ struct AdjBlockLaunch {
     Rows lam;
     uint64_t qbit[kAdjBlockMaxBits]; // 1 << qubit of each local bit (ascending qubits)
     int q[kAdjBlockMaxBits];
-    int lb;                          // local bits: 4 or 5
+    int lb;                          // local bits: 3, 4 or 5
     int ngates;
     const AdjBlockGate* gates;       // device, in un-apply order (the block's last gate first)
     int nslots;

@@ -1,5 +1,5 @@
 """GPU parity of the blocked adjoint backward (one sweep per block of gates
-on 4 or 5 qubits, gates un-applied in registers) against the oracle's exact
+on 3, 4 or 5 qubits, gates un-applied in registers) against the oracle's exact
 gradients, and against the per-gate GPU backward.
 
 Tolerance as the per-gate adjoint: relative 1e-4 (2-norm and per
@@ -25,7 +25,7 @@ def _close(g, ref, rel=REL):
     assert np.max(np.abs(g - ref)) <= rel * max(np.max(np.abs(ref)), 1e-12)
 
 
-@pytest.mark.parametrize("lb", [4, 5])
+@pytest.mark.parametrize("lb", [3, 4, 5])
 def test_ring14_vs_parameter_shift(sv, lb):
     circ = C.WORKLOADS["ring14"]()
     terms = C.z_sum_terms(14)
@@ -37,14 +37,14 @@ def test_ring14_vs_parameter_shift(sv, lb):
     assert abs(st.to_numpy()[0][0] - 1) < 1e-4
 
 
-@pytest.mark.parametrize("lb", [4, 5])
+@pytest.mark.parametrize("lb", [3, 4, 5])
 @pytest.mark.parametrize("n,seed", [(6, 1), (9, 2), (12, 3)])
 def test_every_kind_vs_oracle_adjoint(sv, lb, n, seed):
     """Random circuits of every kind (controls, two-target kinds, U3 with
     three parameters, phase gates): the oracle's FP64 adjoint (itself pinned
     against parameter shift and central differences) is the reference.
     Observables with X and Y strings exercise the complex co-state."""
-    circ = C.random_circuit(n, 90, 40 + seed + lb, max_controls=2)
+    circ = C.random_circuit(n, 90, 40 + seed + lb, max_controls=2 if lb > 3 else 1)
     rng = np.random.default_rng(seed)
     terms = [(float(rng.normal()), int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n))) for _ in range(4)]
     st = sv.State(n).reset().run(circ)
@@ -63,7 +63,7 @@ def test_blocked_matches_per_gate(sv):
     st = sv.State(16)
     st.reset().run(circ)
     _, g_gate, _ = st.adjoint_grad(circ, terms)
-    for lb in (4, 5):
+    for lb in (3, 4, 5):
         st.reset().run(circ)
         _, g_blk, d = st.adjoint_grad(circ, terms, block_qubits=lb)
         _close(g_blk[0], g_gate[0], rel=2e-5)
@@ -108,7 +108,17 @@ def test_bad_block_width(sv):
     circ = C.WORKLOADS["ring14"]()
     st = sv.State(14).reset().run(circ)
     with pytest.raises(svmod.SvError):
-        st.adjoint_grad(circ, C.z_sum_terms(14), block_qubits=3)
+        st.adjoint_grad(circ, C.z_sum_terms(14), block_qubits=2)
     st3 = sv.State(3).reset()
     with pytest.raises(svmod.SvError):
         st3.adjoint_grad(C.ghz(3), C.z_sum_terms(3), block_qubits=4)
+    with pytest.raises(svmod.SvError):
+        st.adjoint_grad(circ, C.z_sum_terms(14), block_qubits=6)
+    # a gate wider than the block (two targets, two controls) is refused
+    b = C._Builder(6)
+    b.gate("rxx", [0, 1], [2, 3], values=[0.3])
+    wide = b.build("wide_gate")
+    st6 = sv.State(6).reset().run(wide)
+    with pytest.raises(svmod.SvError) as e:
+        st6.adjoint_grad(wide, C.z_sum_terms(6), block_qubits=3)
+    assert e.value.status == 4

@@ -56,10 +56,12 @@ def test_weighted_adjoint_vs_parameter_shift(sv, shared):
     assert np.all(drift < 1e-4)
 
 
-def test_expvalz_forward_and_backward(sv):
+@pytest.mark.parametrize("block_qubits", [None, 0, 3, 5])
+def test_expvalz_forward_and_backward(sv, block_qubits):
+    """None: the default (blocked, 4 qubits); 0: the per-gate backward."""
     n, B = 8, 3
     circ, rows = C.profiling_ladder(n, 3, B, seed=4)
-    layer = MeasureAllZ(circ, B)
+    layer = MeasureAllZ(circ, B, block_qubits=block_qubits)
     x = torch.tensor(rows, dtype=torch.float64, requires_grad=True)
     z = layer(x)
     for r in range(B):
