@@ -87,7 +87,7 @@ class ExpvalZ(torch.autograd.Function):
     @staticmethod
     def forward(ctx, params: torch.Tensor, circuit, state: "sv.State", block_qubits: int = 0):
         ctx.block_qubits = block_qubits
-        p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, -1))
+        p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, circuit.n_params))
         state.reset()
         state.run(circuit, params=p if state.batch > 1 else p[0])
         z = state.expval_z_all()[:, : circuit.n]

@@ -1,0 +1,40 @@
+"""Host-side checks of the front end's gate schema (no GPU): every entry
+names a library kind with matching arity, and the functional, module and
+device-method forms are generated for every entry."""
+
+import torch
+
+from paper_2511_19291_amd import circuits as C
+from paper_2511_19291_amd import frontend as F
+
+
+def test_schema_matches_library_kinds():
+    for name, (kind, nc, nt, npar) in F.GATE_SCHEMA.items():
+        assert kind in C.ALL_KINDS, name
+        assert C.N_TARGETS[kind] == nt and C.N_PARAMS[kind] == npar, name
+        assert 0 <= nc <= 3
+
+
+def test_forms_generated_for_every_entry():
+    for name, (_, nc, nt, npar) in F.GATE_SCHEMA.items():
+        assert callable(getattr(F.functional, name))
+        cls = F.MODULES[name]
+        assert cls.__name__ == name.upper() and getattr(F, name.upper()) is cls
+        m = cls(wires=list(range(nc + nt)))
+        if npar:
+            assert isinstance(m.params, torch.nn.Parameter) and m.params.shape == (npar,)
+            assert 0 <= float(m.params.detach().min()) and float(m.params.detach().max()) < 2 * 3.1416
+        else:
+            assert m.params is None
+        frozen = cls(wires=list(range(nc + nt)), trainable=False, init_params=[0.5] * npar if npar else None)
+        assert not any(p.requires_grad for p in frozen.parameters())
+
+
+def test_listing_structure_builds_on_cpu():
+    nq = 5
+    enc = F.GeneralEncoder([{"func": "ry", "wires": [i], "input_idx": [i]} for i in range(nq)])
+    mods = [enc]
+    for _ in range(3):
+        mods += [F.CX(wires=[i, (i + 1) % nq]) for i in range(nq)] + [F.RY(wires=[i]) for i in range(nq)]
+    mod = F.InvertibleUnitary(mods)
+    assert sum(p.numel() for p in mod.parameters()) == 3 * nq
