@@ -344,15 +344,34 @@ sv_status sv_batch_plan_create(int n_circuits, const int* n_qubits, const sv_op*
  *     make one LDS sweep per gate. 15: never.
  *   wg_per_cu: persistent workgroups per compute unit, 1..16, at most the
  *     number that are resident at once; 0: as many as are resident.
- * Every configuration computes the same <Z_i> up to FP32 rounding order. */
+ *   phase_mode: the arithmetic of a register phase (the fusion of Sec. 4.1.1
+ *     applied to the phase's four qubits):
+ *     0: every gate on its own, in registers (FP32);
+ *     1: a phase of >= fuse_min_gates gates is fused into one 16 x 16
+ *        unitary (the gates multiplied in FP64 when the launch starts, rounded
+ *        to FP32 once) applied on FP32 matrix cores;
+ *     2: as 1, the product split into BF16 parts (hi*hi + hi*lo + lo*hi,
+ *        FP32 accumulation; relative error ~1e-5 per phase).
+ *     Fused phases need tiles of at least 2^9 amplitudes; smaller tiles and
+ *     shorter phases run gate by gate.
+ *   fuse_min_gates: 1..64, the fewest gates a phase needs to be fused.
+ *   run_bits: 3..6 and <= tile_bits - 5. Qubits 0..run_bits-1 belong to
+ *     every tile of a pass, so a tile moves between passes as contiguous runs
+ *     of 2^run_bits amplitudes (64 B .. 512 B); the other tile_bits -
+ *     run_bits tile qubits are chosen per pass. Fewer run bits leave more
+ *     room per pass, hence fewer passes.
+ * Modes 0 and 1 compute the same <Z_i> up to FP32 rounding order. */
 typedef struct sv_batch_config {
     int32_t tile_bits;
     int32_t threads;
     int32_t reg_min_bits;
     int32_t wg_per_cu;
+    int32_t phase_mode;
+    int32_t fuse_min_gates;
+    int32_t run_bits;
 } sv_batch_config;
 
-/* The configuration sv_batch_plan_create uses: {14, 1024, 12, 0}. */
+/* The configuration sv_batch_plan_create uses: {14, 512, 12, 0, 1, 3, 3}. */
 sv_status sv_batch_default_config(sv_batch_config* out);
 
 /* sv_batch_plan_create with an explicit launch shape (config NULL: the
@@ -398,8 +417,10 @@ typedef struct sv_batch_trial {
 
 /* Autotuner of the batched launch: times the batch (the same arguments as
  * sv_batch_plan_create) under a staged search over launch shapes -- tile
- * width x threads per workgroup, then where register phases start, then
- * workgroups per CU -- and returns the fastest configuration whose outputs
+ * width x threads per workgroup, then the run length (run_bits), then where
+ * register phases start, then workgroups per CU, then the phase arithmetic
+ * (phase_mode x fuse_min_gates in {2, 3, 4, 6}) -- and returns the fastest
+ * configuration whose outputs
  * agree with the default configuration's within 1e-4 (FP32 rounding order).
  *   dev_params: the device parameter block of sv_batch_param_layout (the
  *     layout does not depend on the configuration).

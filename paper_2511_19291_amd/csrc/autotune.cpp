@@ -1,6 +1,7 @@
 // autotune.cpp -- measured choice of the launch shapes: the batched launch's
 // tile (tile width, threads per workgroup, register phases, workgroups per
-// CU) and the fusion width k and arithmetic of a circuit's fused blocks.
+// CU, phase fusion and its arithmetic) and the fusion width k and arithmetic
+// of a circuit's fused blocks.
 // Every candidate is timed on the device with HIP events on the caller's
 // stream; candidates whose results disagree with the reference configuration
 // are never chosen.
@@ -90,7 +91,12 @@ struct DevBuf {
 bool same_effective(const sv_batch_config& a, const sv_batch_config& b)
 {
     auto reg = [](const sv_batch_config& c) { return c.reg_min_bits > c.tile_bits ? 99 : c.reg_min_bits; };
-    return a.tile_bits == b.tile_bits && a.threads == b.threads && reg(a) == reg(b) && a.wg_per_cu == b.wg_per_cu;
+    // without register phases, or with gate-by-gate phases, the fusion threshold is unused
+    auto fuse = [&](const sv_batch_config& c) {
+        return reg(c) == 99 || c.phase_mode == kPhaseGates ? 0 : c.phase_mode * 100 + c.fuse_min_gates;
+    };
+    return a.tile_bits == b.tile_bits && a.threads == b.threads && reg(a) == reg(b) && a.wg_per_cu == b.wg_per_cu &&
+           fuse(a) == fuse(b) && a.run_bits == b.run_bits;
 }
 
 }  // namespace
@@ -167,9 +173,17 @@ sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* co
                 sv_batch_config c = base;
                 c.tile_bits = tb;
                 c.threads = th;
+                c.run_bits = std::min(base.run_bits, tb - 5);
                 const sv_batch_trial t = run(c);
                 if (better(t, &cur)) cur = t;
             }
+        // stage 1b: length of the contiguous runs a tile is made of
+        for (int rb = 3; rb <= std::min(6, cur.config.tile_bits - 5); ++rb) {
+            sv_batch_config c = cur.config;
+            c.run_bits = rb;
+            const sv_batch_trial t = run(c);
+            if (better(t, &cur)) cur = t;
+        }
         // stage 2: where register phases start
         for (int rb : {8, 10, 12, 15}) {
             sv_batch_config c = cur.config;
@@ -185,6 +199,16 @@ sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* co
             const sv_batch_trial t = run(c);
             if (better(t, &cur)) cur = t;
         }
+        // stage 4: phase arithmetic (gate by gate, fused on FP32 or BF16x3
+        // matrix cores) and the fewest gates a fused phase needs
+        for (int pm : {kPhaseGates, kPhaseFp32, kPhaseBf16x3})
+            for (int fm : {2, 3, 4, 6}) {
+                sv_batch_config c = cur.config;
+                c.phase_mode = pm;
+                c.fuse_min_gates = fm;
+                const sv_batch_trial t = run(c);
+                if (better(t, &cur)) cur = t;
+            }
         need(usable(cur), SV_ERR_HIP, "no configuration reproduced the reference output");
         *best = cur.config;
         if (n_trials) *n_trials = (int)done.size();

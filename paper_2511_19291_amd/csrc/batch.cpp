@@ -25,6 +25,9 @@ struct sv_batch_plan_s {
     sv::BPhase* d_phases = nullptr;
     float2* d_arena = nullptr;
     float2* d_mats = nullptr;
+    float* d_frag = nullptr;
+    int* d_frag_phase = nullptr;
+    int n_frag = 0;
     double* d_zpart = nullptr;
     int* d_counter = nullptr;
     int* d_done = nullptr;
@@ -82,20 +85,21 @@ struct Pass {
     uint64_t tile;
 };
 
-// Qubits 0..low_bits-1 are in every tile, so a tile is made of contiguous
-// runs of 2^low_bits amplitudes; the rest of the tile (at least five qubits,
-// the most one gate touches) is free for the pass's gates.
-int low_bits_of(int tile_bits) { return std::min(6, tile_bits - 5); }
-
 // Cut a gate list into passes whose gates all act inside one tile of
 // tile_bits qubits that always contains the low qubits. Scanning in order, a
 // gate joins the pass when its qubits fit and it touches no qubit of a gate
 // already left for a later pass; so gates only move past gates on disjoint
 // qubits and the pass sequence equals the circuit.
-std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops, int tile_bits)
+//
+// Qubits 0..run_bits-1 are in every tile, so a tile is made of contiguous
+// runs of 2^run_bits amplitudes in the state (the unit of coalesced memory
+// access); the rest of the tile (at least five qubits, the most one gate
+// touches) is free for the pass's gates. Shorter runs leave more room, so
+// fewer passes (fewer round trips of the state through memory).
+std::vector<Pass> plan_passes(int n, const std::vector<sv_op>& ops, int tile_bits, int run_bits)
 {
-    const uint64_t low = (1ull << low_bits_of(tile_bits)) - 1;
-    const int room = tile_bits - low_bits_of(tile_bits);
+    const uint64_t low = (1ull << run_bits) - 1;
+    const int room = tile_bits - run_bits;
     std::vector<int> remaining(ops.size());
     std::iota(remaining.begin(), remaining.end(), 0);
     std::vector<Pass> passes;
@@ -203,6 +207,8 @@ void destroy(sv_batch_plan p)
     (void)hipFree(p->d_phases);
     (void)hipFree(p->d_arena);
     (void)hipFree(p->d_mats);
+    (void)hipFree(p->d_frag);
+    (void)hipFree(p->d_frag_phase);
     (void)hipFree(p->d_zpart);
     (void)hipFree(p->d_counter);
     (void)hipFree(p->d_done);
@@ -214,9 +220,12 @@ sv_batch_config default_config()
 {
     sv_batch_config c{};
     c.tile_bits = kMaxTileBits;
-    c.threads = 1024;
+    c.threads = 512;
     c.reg_min_bits = 12;
     c.wg_per_cu = 0;
+    c.phase_mode = kPhaseFp32;
+    c.fuse_min_gates = 3;
+    c.run_bits = 3;
     return c;
 }
 
@@ -229,6 +238,11 @@ void check_config(const sv_batch_config& c)
     need(c.reg_min_bits >= kRegBits && c.reg_min_bits <= kMaxTileBits + 1, SV_ERR_INVALID_ARGUMENT,
          "reg_min_bits must be 4..15");
     need(c.wg_per_cu >= 0 && c.wg_per_cu <= 16, SV_ERR_INVALID_ARGUMENT, "wg_per_cu must be 0..16");
+    need(c.phase_mode >= kPhaseGates && c.phase_mode <= kPhaseBf16x3, SV_ERR_INVALID_ARGUMENT,
+         "phase_mode must be 0 (gates), 1 (FP32 MFMA) or 2 (BF16x3 MFMA)");
+    need(c.fuse_min_gates >= 1 && c.fuse_min_gates <= 64, SV_ERR_INVALID_ARGUMENT, "fuse_min_gates must be 1..64");
+    need(c.run_bits >= 3 && c.run_bits <= 6 && c.run_bits <= c.tile_bits - 5, SV_ERR_INVALID_ARGUMENT,
+         "run_bits must be 3..6 and at most tile_bits - 5");
 }
 
 BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
@@ -244,6 +258,10 @@ BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
     a.n_pass = p->n_pass;
     a.arena = p->d_arena;
     a.mats = p->d_mats;
+    a.frag = p->d_frag;
+    a.frag_phase = p->d_frag_phase;
+    a.n_frag = p->n_frag;
+    a.phase_mode = p->cfg.phase_mode;
     a.zpart = p->d_zpart;
     a.params = params;
     a.out = out;
@@ -313,6 +331,7 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
         std::vector<BPass> pass;
         std::vector<BOp> bops;
         std::vector<BPhase> phase;
+        std::vector<int> frag_phase;
         int64_t arena = 0, zrows = 0;
         for (int c : order) {
             const int n = p->n[c];
@@ -338,7 +357,7 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                 one.tile = (1ull << n) - 1;
                 pl.push_back(std::move(one));
             } else {
-                pl = plan_passes(n, v, cfg.tile_bits);
+                pl = plan_passes(n, v, cfg.tile_bits, cfg.run_bits);
             }
             bc.pass_begin = (int)pass.size();
             for (const Pass& ps : pl) {
@@ -383,6 +402,7 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                     masks.push_back(mask);
                 }
                 bp.phase_begin = bp.phase_end = (int)phase.size();
+                bp.first_frag = -1;
                 if (bc.m >= cfg.reg_min_bits) {
                     std::vector<BPhase> ph;
                     const std::vector<int> order = plan_phases(masks, bc.m, ph);
@@ -402,9 +422,23 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                         }
                         x.op_begin += (int)bops.size();
                         x.op_end += (int)bops.size();
+                        // fused on the matrix cores: a phase of enough gates
+                        // in a tile of at least 32 units (one wave's product)
+                        x.frag = x.next_frag = -1;
+                        if (cfg.phase_mode != kPhaseGates && x.g[0] >= 0 && bc.m >= kRegBits + 5 &&
+                            x.op_end - x.op_begin >= cfg.fuse_min_gates) {
+                            x.frag = (int)frag_phase.size();
+                            frag_phase.push_back((int)phase.size());
+                        }
                         phase.push_back(x);
                     }
                     bp.phase_end = (int)phase.size();
+                    int next = -1;
+                    for (int hi = bp.phase_end - 1; hi >= bp.phase_begin; --hi) {
+                        phase[hi].next_frag = next;
+                        if (phase[hi].frag >= 0) next = phase[hi].frag;
+                    }
+                    bp.first_frag = next;
                     for (int oi : order) bops.push_back(pops[oi]);
                 } else {
                     bops.insert(bops.end(), pops.begin(), pops.end());
@@ -415,7 +449,8 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
             bc.pass_end = (int)pass.size();
             circ.push_back(bc);
         }
-        need(p->n_params_total < (1ll << 31) && bops.size() < (1u << 31), SV_ERR_UNSUPPORTED, "batch too large");
+        need(p->n_params_total < (1ll << 31) && bops.size() < (1u << 31) && frag_phase.size() < (1u << 26),
+             SV_ERR_UNSUPPORTED, "batch too large");
         // tasks: round r = pass r of every circuit that has one (largest first),
         // all its tiles; the single-task small circuits follow round 0's large ones
         std::vector<BTask> tasks;
@@ -439,6 +474,8 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
         p->d_ops = upload(bops);
         p->d_tasks = upload(tasks);
         p->d_phases = upload(phase);
+        p->n_frag = (int)frag_phase.size();
+        p->d_frag_phase = upload(frag_phase);
         auto dev_alloc = [&](void** ptr, size_t bytes, const char* what) {
             if (hipMalloc(ptr, std::max<size_t>(bytes, 16)) != hipSuccess) {
                 (void)hipGetLastError();
@@ -448,12 +485,13 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
         };
         if (arena > 0) dev_alloc((void**)&p->d_arena, (size_t)arena * sizeof(float2), "state arena");
         dev_alloc((void**)&p->d_mats, (size_t)p->n_ops * kMatStride * sizeof(float2), "matrix table");
+        dev_alloc((void**)&p->d_frag, (size_t)p->n_frag * 64 * kFragFloats * sizeof(float), "fragment table");
         dev_alloc((void**)&p->d_zpart, (size_t)zrows * (kBatchMaxQubits + 1) * sizeof(double), "partials");
         dev_alloc((void**)&p->d_done, (size_t)p->n_pass * sizeof(int), "pass counters");
         dev_alloc((void**)&p->d_counter, sizeof(int), "queue counter");
         // persistent grid: the requested workgroups per CU, at most as many
         // as are resident at once (LDS, registers), at most one per task
-        const int resident = batch_max_wg_per_cu(cfg.threads, cfg.tile_bits);
+        const int resident = batch_max_wg_per_cu(cfg.threads, cfg.tile_bits, cfg.phase_mode);
         const int per_cu = cfg.wg_per_cu == 0 ? resident : std::min(cfg.wg_per_cu, resident);
         p->cfg = cfg;
         p->cfg.wg_per_cu = per_cu;

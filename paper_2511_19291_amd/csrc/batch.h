@@ -29,13 +29,24 @@ struct BOp {
 };
 
 // A register phase: gates [op_begin, op_end) all act inside the four
-// tile-local qubits g[0..3]; each thread holds the 16 amplitudes that differ
-// only in those qubits and applies the gates in registers.
+// tile-local qubits g[0..3] (ascending); each thread holds the 16 amplitudes
+// that differ only in those qubits and applies the gates in registers. A
+// fused phase (frag >= 0) instead applies the product of its gates, one
+// 16 x 16 unitary, on the matrix cores; its operand fragments are entry
+// `frag` of the fragment table.
 struct BPhase {
     int op_begin;
     int op_end;
     int g[kRegBits];
+    int frag;                         // -1: gate by gate in registers
+    int next_frag;                    // fragment of the next fused phase of the pass, -1 = none
 };
+
+// Phase arithmetic (sv_batch_config.phase_mode).
+constexpr int kPhaseGates = 0;        // every gate applied on its own
+constexpr int kPhaseFp32 = 1;         // fused phases on FP32 MFMA
+constexpr int kPhaseBf16x3 = 2;       // fused phases as BF16 x3 products, FP32 accumulation
+constexpr int kFragFloats = 16;       // per lane and fused phase: 64 bytes (16 FP32 or 32 BF16)
 
 // A pass: gates [op_begin, op_end) all act inside the tile whose bit j is
 // qubit pos[j] (ascending). When phase_begin < phase_end the gates run as
@@ -45,6 +56,7 @@ struct BPass {
     int op_end;
     int phase_begin;
     int phase_end;
+    int first_frag;                   // fragment of the pass's first fused phase, -1 = none
     int pos[kMaxTileBits];
 };
 
@@ -80,6 +92,10 @@ struct BatchArgs {
     int n_pass;
     float2* arena;
     float2* mats;                     // n_ops * kMatStride complex64
+    float* frag;                      // n_frag * 64 lanes * kFragFloats: fused-phase operands
+    const int* frag_phase;            // phase of each fragment
+    int n_frag;
+    int phase_mode;
     double* zpart;                    // per-tile partials [row][kBatchMaxQubits + 1]
     const double* params;
     double* out;
@@ -91,7 +107,7 @@ struct BatchArgs {
 size_t batch_lds_bytes(int tile_bits);
 // resident workgroups per CU of the persistent kernel (also raises the
 // kernel's dynamic-LDS limit to that size)
-int batch_max_wg_per_cu(int threads, int tile_bits);
+int batch_max_wg_per_cu(int threads, int tile_bits, int phase_mode);
 void launch_batch(const BatchArgs& a, int grid, int threads, int tile_bits, hipStream_t st);
 
 }  // namespace sv

@@ -34,39 +34,42 @@ namespace {
 
 constexpr int kZ = kBatchMaxQubits + 1;
 
-__device__ __forceinline__ float2 f2(double re, double im) { return make_float2((float)re, (float)im); }
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Gate matrix (first target = most significant index bit), complex64. The
+__device__ __forceinline__ double2 d2(double re, double im) { return make_double2(re, im); }
+
+// Gate matrix (first target = most significant index bit), complex128: the
 // same definitions as the host gate math (rotations exp(-i t P / 2),
-// OpenQASM U3, phase gate), evaluated in FP64 and rounded once.
-__device__ void dev_gate_matrix(int kind, const double* prm, float2* m)
+// OpenQASM U3, phase gate).
+__device__ void dev_gate_matrix(int kind, const double* prm, double2* m)
 {
     const double h = 0.70710678118654752440;
-    const float2 z0 = f2(0, 0), o1 = f2(1, 0);
+    const double2 z0 = d2(0, 0), o1 = d2(1, 0);
     for (int i = 0; i < kMatStride; ++i) m[i] = z0;
-    auto set2 = [&](float2 a, float2 b, float2 c, float2 d) { m[0] = a; m[1] = b; m[2] = c; m[3] = d; };
+    auto set2 = [&](double2 a, double2 b, double2 c, double2 d) { m[0] = a; m[1] = b; m[2] = c; m[3] = d; };
     switch (kind) {
-    case SV_H: set2(f2(h, 0), f2(h, 0), f2(h, 0), f2(-h, 0)); break;
+    case SV_H: set2(d2(h, 0), d2(h, 0), d2(h, 0), d2(-h, 0)); break;
     case SV_X: set2(z0, o1, o1, z0); break;
-    case SV_Y: set2(z0, f2(0, -1), f2(0, 1), z0); break;
-    case SV_Z: set2(o1, z0, z0, f2(-1, 0)); break;
-    case SV_S: set2(o1, z0, z0, f2(0, 1)); break;
-    case SV_SDG: set2(o1, z0, z0, f2(0, -1)); break;
-    case SV_T: set2(o1, z0, z0, f2(h, h)); break;
-    case SV_TDG: set2(o1, z0, z0, f2(h, -h)); break;
-    case SV_SX: set2(f2(0.5, 0.5), f2(0.5, -0.5), f2(0.5, -0.5), f2(0.5, 0.5)); break;
+    case SV_Y: set2(z0, d2(0, -1), d2(0, 1), z0); break;
+    case SV_Z: set2(o1, z0, z0, d2(-1, 0)); break;
+    case SV_S: set2(o1, z0, z0, d2(0, 1)); break;
+    case SV_SDG: set2(o1, z0, z0, d2(0, -1)); break;
+    case SV_T: set2(o1, z0, z0, d2(h, h)); break;
+    case SV_TDG: set2(o1, z0, z0, d2(h, -h)); break;
+    case SV_SX: set2(d2(0.5, 0.5), d2(0.5, -0.5), d2(0.5, -0.5), d2(0.5, 0.5)); break;
     case SV_RX: case SV_RY: case SV_RZ: {
         double s, c;
         sincos(0.5 * prm[0], &s, &c);
-        if (kind == SV_RX) set2(f2(c, 0), f2(0, -s), f2(0, -s), f2(c, 0));
-        else if (kind == SV_RY) set2(f2(c, 0), f2(-s, 0), f2(s, 0), f2(c, 0));
-        else set2(f2(c, -s), z0, z0, f2(c, s));
+        if (kind == SV_RX) set2(d2(c, 0), d2(0, -s), d2(0, -s), d2(c, 0));
+        else if (kind == SV_RY) set2(d2(c, 0), d2(-s, 0), d2(s, 0), d2(c, 0));
+        else set2(d2(c, -s), z0, z0, d2(c, s));
         break;
     }
     case SV_P: {
         double s, c;
         sincos(prm[0], &s, &c);
-        set2(o1, z0, z0, f2(c, s));
+        set2(o1, z0, z0, d2(c, s));
         break;
     }
     case SV_U3: {
@@ -75,7 +78,7 @@ __device__ void dev_gate_matrix(int kind, const double* prm, float2* m)
         sincos(prm[1], &sf, &cf);
         sincos(prm[2], &sl, &cl);
         sincos(prm[1] + prm[2], &sfl, &cfl);
-        set2(f2(c, 0), f2(-s * cl, -s * sl), f2(s * cf, s * sf), f2(c * cfl, c * sfl));
+        set2(d2(c, 0), d2(-s * cl, -s * sl), d2(s * cf, s * sf), d2(c * cfl, c * sfl));
         break;
     }
     case SV_SWAP:
@@ -85,20 +88,144 @@ __device__ void dev_gate_matrix(int kind, const double* prm, float2* m)
     case SV_RXX: case SV_RYY: case SV_RZZ: {
         double s, c;
         sincos(0.5 * prm[0], &s, &c);
-        for (int i = 0; i < 4; ++i) m[i * 5] = f2(c, 0);
+        for (int i = 0; i < 4; ++i) m[i * 5] = d2(c, 0);
         if (kind == SV_RZZ) {
             // cos I - i sin Z(x)Z, Z(x)Z = diag(1, -1, -1, 1)
-            m[0] = f2(c, -s); m[5] = f2(c, s); m[10] = f2(c, s); m[15] = f2(c, -s);
+            m[0] = d2(c, -s); m[5] = d2(c, s); m[10] = d2(c, s); m[15] = d2(c, -s);
         } else if (kind == SV_RXX) {
             // X(x)X = antidiag(1, 1, 1, 1)
-            m[3] = m[6] = m[9] = m[12] = f2(0, -s);
+            m[3] = m[6] = m[9] = m[12] = d2(0, -s);
         } else {
             // Y(x)Y = antidiag(-1, 1, 1, -1)
-            m[3] = f2(0, s); m[6] = f2(0, -s); m[9] = f2(0, -s); m[12] = f2(0, s);
+            m[3] = d2(0, s); m[6] = d2(0, -s); m[9] = d2(0, -s); m[12] = d2(0, s);
         }
         break;
     }
     default: break;
+    }
+}
+
+__device__ __forceinline__ void op_params(const BatchArgs& a, const BOp& op, double (&prm)[3])
+{
+    for (int q = 0; q < 3; ++q) prm[q] = op.p[q] >= 0 ? a.params[op.p[q]] : 0.0;
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b)
+{
+    return d2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int P>
+__device__ __forceinline__ void dg1(double2 (&v)[16], const double2 (&m)[kMatStride], int cm)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & (1 << P)) continue;
+        if ((j & cm) != cm) continue;
+        const int j1 = j | (1 << P);
+        const double2 x0 = v[j], x1 = v[j1];
+        const double2 a0 = zmul(m[0], x0), b0 = zmul(m[1], x1), a1 = zmul(m[2], x0), b1 = zmul(m[3], x1);
+        v[j] = d2(a0.x + b0.x, a0.y + b0.y);
+        v[j1] = d2(a1.x + b1.x, a1.y + b1.y);
+    }
+}
+
+template <int P0, int P1>
+__device__ __forceinline__ void dg2(double2 (&v)[16], const double2 (&m)[kMatStride], int cm)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & ((1 << P0) | (1 << P1))) continue;
+        if ((j & cm) != cm) continue;
+        const int o[4] = {j, j | (1 << P1), j | (1 << P0), j | (1 << P0) | (1 << P1)};
+        double2 x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = v[o[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double2 acc = d2(0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double2 t = zmul(m[r * 4 + q], x[q]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            v[o[r]] = acc;
+        }
+    }
+}
+
+// One gate of a phase on a 16-amplitude vector in FP64 (the register-phase
+// convention: targets rt[], controls rcmask, bit i <-> the phase's qubit g[i]).
+__device__ void phase_gate_d(double2 (&v)[16], const BOp& op, const double2 (&m)[kMatStride])
+{
+    const int cm = op.rcmask;
+    if (op.nt == 1) {
+        switch (op.rt[0]) {
+        case 0: dg1<0>(v, m, cm); break;
+        case 1: dg1<1>(v, m, cm); break;
+        case 2: dg1<2>(v, m, cm); break;
+        default: dg1<3>(v, m, cm); break;
+        }
+        return;
+    }
+    switch (op.rt[0] * 4 + op.rt[1]) {
+    case 1: dg2<0, 1>(v, m, cm); break;
+    case 2: dg2<0, 2>(v, m, cm); break;
+    case 3: dg2<0, 3>(v, m, cm); break;
+    case 4: dg2<1, 0>(v, m, cm); break;
+    case 6: dg2<1, 2>(v, m, cm); break;
+    case 7: dg2<1, 3>(v, m, cm); break;
+    case 8: dg2<2, 0>(v, m, cm); break;
+    case 9: dg2<2, 1>(v, m, cm); break;
+    case 11: dg2<2, 3>(v, m, cm); break;
+    case 12: dg2<3, 0>(v, m, cm); break;
+    case 13: dg2<3, 1>(v, m, cm); break;
+    default: dg2<3, 2>(v, m, cm); break;
+    }
+}
+
+// Column c of a fused phase's unitary: the phase's gates applied in FP64 to
+// the basis vector e_c of its 16-amplitude space (bit i of the index <->
+// the phase's qubit g[i]), then scattered into the matrix-core operand
+// layout of the phase (see fused_phase below for the layout).
+__device__ void build_fragment_column(const BatchArgs& a, int f, int c)
+{
+    const BPhase ph = a.phases[a.frag_phase[f]];
+    double2 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = d2(j == c ? 1.0 : 0.0, 0.0);
+    for (int oi = ph.op_begin; oi < ph.op_end; ++oi) {
+        const BOp op = a.ops[oi];
+        double prm[3];
+        op_params(a, op, prm);
+        double2 m[kMatStride];
+        dev_gate_matrix(op.kind, prm, m);
+        phase_gate_d(v, op, m);
+    }
+    // v = U e_c. Real form: row i (0..31) of the 32 x 32 operand is output
+    // component (i & 1) of amplitude jo(i) = 8 ((i >> 2) & 1) + 2 (i >> 3) +
+    // ((i >> 1) & 1); the input column is (amplitude c, component ci).
+    const int lane_hi = 32 * (c >> 3);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const int jo = 8 * ((i >> 2) & 1) + 2 * (i >> 3) + ((i >> 1) & 1);
+        const double ur = v[jo].x, ui = v[jo].y;
+        for (int ci = 0; ci < 2; ++ci) {
+            // [[Ur, -Ui], [Ui, Ur]]
+            const double e = (i & 1) == 0 ? (ci == 0 ? ur : -ui) : (ci == 0 ? ui : ur);
+            float* fr = a.frag + ((size_t)f * 64 + lane_hi + i) * kFragFloats;
+            if (a.phase_mode == kPhaseFp32) {
+                fr[2 * (c & 7) + ci] = (float)e;
+            } else {
+                const float ef = (float)e;
+                const __bf16 hi = (__bf16)ef;
+                const __bf16 lo = (__bf16)(ef - (float)hi);
+                __bf16* fb = reinterpret_cast<__bf16*>(fr);
+                fb[(ci * 2 + 0) * 8 + (c & 7)] = hi;
+                fb[(ci * 2 + 1) * 8 + (c & 7)] = lo;
+            }
+        }
     }
 }
 
@@ -108,13 +235,30 @@ __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a)
     if (i < a.n_ops) {
         const BOp op = a.ops[i];
         double prm[3];
-        for (int q = 0; q < 3; ++q) prm[q] = op.p[q] >= 0 ? a.params[op.p[q]] : 0.0;
-        float2 m[kMatStride];
+        op_params(a, op, prm);
+        double2 m[kMatStride];
         dev_gate_matrix(op.kind, prm, m);
-        for (int q = 0; q < kMatStride; ++q) a.mats[(size_t)i * kMatStride + q] = m[q];
+        for (int q = 0; q < kMatStride; ++q)
+            a.mats[(size_t)i * kMatStride + q] = make_float2((float)m[q].x, (float)m[q].y);
     }
+    if (i < a.n_frag * 16) build_fragment_column(a, i >> 4, i & 15);
     if (i < a.n_pass) a.done[i] = 0;
     if (i == 0) *a.counter = 0;
+}
+
+// Load of a launch table entry at a uniform address through the scalar
+// cache: the task, circuit, pass and phase tables are read-only while the
+// persistent kernel runs, so they may be read as constant memory.
+template <class T>
+__device__ __forceinline__ T ld_const(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    typedef const __attribute__((address_space(4))) uint32_t cword;
+    const cword* q = (const cword*)p;
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+    return __builtin_bit_cast(T, w);
 }
 
 __device__ __forceinline__ uint32_t ins0(uint32_t g, const int* pos, int np)
@@ -126,6 +270,14 @@ __device__ __forceinline__ uint32_t ins0(uint32_t g, const int* pos, int np)
     return g;
 }
 
+// LDS layout of a tile: amplitude i sits at word swz(i). XOR-ing tile bits
+// 5..9 into bits 0..4 spreads the strided accesses of phases whose qubits
+// include low tile bits over all banks (a unit-per-lane access then differs
+// in some of bits 5..9 across lanes). swz is linear over XOR, so
+// swz(a | b) = swz(a) ^ swz(b) for disjoint bit sets, and it only permutes
+// within aligned blocks of 32, so indices stay below 2^m.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+
 // One gate on the tile in LDS.
 template <int NT>
 __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, const float2* __restrict__ mat)
@@ -136,9 +288,10 @@ __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, c
         const uint32_t tb = op.off[1];
         for (uint32_t g = threadIdx.x; g < groups; g += NT) {
             const uint32_t i0 = ins0(g, op.pos, op.np) | op.cmask, i1 = i0 | tb;
-            const float2 x0 = s[i0], x1 = s[i1];
-            s[i0] = cfma(m1, x1, cmul(m0, x0));
-            s[i1] = cfma(m3, x1, cmul(m2, x0));
+            const uint32_t w0 = swz(i0), w1 = swz(i1);
+            const float2 x0 = s[w0], x1 = s[w1];
+            s[w0] = cfma(m1, x1, cmul(m0, x0));
+            s[w1] = cfma(m3, x1, cmul(m2, x0));
         }
     } else {
         float2 mm[16];
@@ -148,7 +301,7 @@ __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, c
             const uint32_t base = ins0(g, op.pos, op.np) | op.cmask;
             float2 x[4], y[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) x[r] = s[base | op.off[r]];
+            for (int r = 0; r < 4; ++r) x[r] = s[swz(base | op.off[r])];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float2 acc = cmul(mm[r * 4], x[0]);
@@ -157,7 +310,7 @@ __device__ __forceinline__ void lds_gate(float2* s, int m_bits, const BOp& op, c
                 y[r] = acc;
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) s[base | op.off[r]] = y[r];
+            for (int r = 0; r < 4; ++r) s[swz(base | op.off[r])] = y[r];
         }
     }
 }
@@ -237,15 +390,189 @@ __device__ __forceinline__ void reg_gate(float2 (&v)[16], const BOp& op, const f
     }
 }
 
+// Operand fragments of one fused phase for this lane: 64 bytes (FP32: 16
+// floats; BF16 x3: the hi and lo parts of two 8-element operands).
+struct Frag {
+    float4 w[4];
+};
+
+// The fused-phase operands of one phase are 64 lanes x 64 bytes = 1024
+// floats, identical for every wave: they are staged in LDS (two buffers, the
+// next fused phase's copied in while the current one runs), and each lane
+// reads its 64 bytes from there.
+constexpr int kFragBlock = 64 * kFragFloats;
+
+template <int NT>
+struct FragCopy {
+    static constexpr int W = kFragBlock / NT;    // floats per thread: 1, 2 or 4
+    float v[W];
+};
+
+template <int NT>
+__device__ __forceinline__ FragCopy<NT> frag_fetch(const BatchArgs& a, int f)
+{
+    FragCopy<NT> r;
+    const float* p = a.frag + (size_t)f * kFragBlock + threadIdx.x * FragCopy<NT>::W;
+#pragma unroll
+    for (int q = 0; q < FragCopy<NT>::W; ++q) r.v[q] = p[q];
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ void frag_put(float* buf, const FragCopy<NT>& r)
+{
+#pragma unroll
+    for (int q = 0; q < FragCopy<NT>::W; ++q) buf[threadIdx.x * FragCopy<NT>::W + q] = r.v[q];
+}
+
+__device__ __forceinline__ Frag frag_lds(const float* buf, int lane)
+{
+    const float4* p = reinterpret_cast<const float4*>(buf + lane * kFragFloats);
+    Frag r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.w[q] = p[q];
+    return r;
+}
+
+__device__ __forceinline__ float frag_f(const Frag& fr, int s)
+{
+    const float4 v = fr.w[s >> 2];
+    return (s & 3) == 0 ? v.x : (s & 3) == 1 ? v.y : (s & 3) == 2 ? v.z : v.w;
+}
+
+__device__ __forceinline__ bf16x8 frag_b(const Frag& fr, int idx)
+{
+    // idx = ci * 2 + (0 hi, 1 lo): 16 bytes
+    const float4 v = fr.w[idx];
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// The products of one fused phase for two groups of 32 units (operand
+// layouts as described for fused_phase).
+template <int PM>
+__device__ __forceinline__ void product2(const Frag& fr, const float2 (&xa)[8], const float2 (&xb)[8], f32x16& acca,
+                                         f32x16& accb)
+{
+    if constexpr (PM == kPhaseFp32) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float f = frag_f(fr, s);
+            acca = __builtin_amdgcn_mfma_f32_32x32x2f32(f, (s & 1) ? xa[s >> 1].y : xa[s >> 1].x, acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x2f32(f, (s & 1) ? xb[s >> 1].y : xb[s >> 1].x, accb, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci) {
+            bf16x8 ha, la, hb, lb;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float va = ci ? xa[q].y : xa[q].x, vb = ci ? xb[q].y : xb[q].x;
+                ha[q] = (__bf16)va;
+                la[q] = (__bf16)(va - (float)ha[q]);
+                hb[q] = (__bf16)vb;
+                lb[q] = (__bf16)(vb - (float)hb[q]);
+            }
+            const bf16x8 fh = frag_b(fr, ci * 2), fl = frag_b(fr, ci * 2 + 1);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, ha, acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, hb, accb, 0, 0, 0);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh, la, acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh, lb, accb, 0, 0, 0);
+            acca = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh, ha, acca, 0, 0, 0);
+            accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh, hb, accb, 0, 0, 0);
+        }
+    }
+}
+
+// A fused phase: every unit's 16 amplitudes y = U x with U the product of
+// the phase's gates, on the matrix cores. As a real product Y = M X with
+// M = [[Ur, -Ui], [Ui, Ur]] (32 x 32) and X one 32-real column per unit, a
+// wave takes 32 units at a time (the 32 columns of one 32 x 32 x K product).
+// Lane (h, u) (h = lane / 32, unit u = lane % 32 of the group) reads and
+// writes amplitudes 8h .. 8h+7 of its unit: input step s of the FP32 form
+// (v_mfma_f32_32x32x2_f32, K = 2 per step) is component s & 1 of amplitude
+// 8h + (s >> 1); step s of the BF16 x3 form (v_mfma_f32_32x32x16_bf16,
+// K = 16 per step) is component s of amplitudes 8h .. 8h+7. The output
+// register r is component r & 1 of amplitude 8h + (r >> 1), so each lane
+// writes back exactly what it read. The fragment builder orders the rows and
+// columns of M to match.
+template <int NT, int PM>
+__device__ __forceinline__ void fused_phase(float2* tile, int m, const BPhase& ph, const Frag& fr)
+{
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const uint32_t groups = 1u << (m - kRegBits - 5);
+    const int g0 = ph.g[0], g1 = ph.g[1], g2 = ph.g[2], g3 = ph.g[3];
+    uint32_t offa[8];     // swizzled offsets of the lane's amplitudes within a unit
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        offa[q] = swz(((uint32_t)h << g3) | ((uint32_t)(q & 1) << g0) | ((uint32_t)((q >> 1) & 1) << g1) |
+                      ((uint32_t)((q >> 2) & 1) << g2));
+    // unit index -> (swizzled) tile index with zeros at the phase's qubits
+    auto unit_base = [&](uint32_t grp) {
+        uint32_t u = grp * 32 + (lane & 31);
+        u = ((u >> g0) << (g0 + 1)) | (u & ((1u << g0) - 1u));
+        u = ((u >> g1) << (g1 + 1)) | (u & ((1u << g1) - 1u));
+        u = ((u >> g2) << (g2 + 1)) | (u & ((1u << g2) - 1u));
+        return swz(((u >> g3) << (g3 + 1)) | (u & ((1u << g3) - 1u)));
+    };
+    // two groups per iteration (two independent accumulation chains)
+    uint32_t grp = wave;
+    for (; grp + NW < groups; grp += 2 * NW) {
+        const uint32_t ua = unit_base(grp), ub = unit_base(grp + NW);
+        float2 xa[8], xb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xa[q] = tile[ua ^ offa[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xb[q] = tile[ub ^ offa[q]];
+        f32x16 acca = {0}, accb = {0};
+        product2<PM>(fr, xa, xb, acca, accb);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tile[ua ^ offa[q]] = make_float2(acca[2 * q], acca[2 * q + 1]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tile[ub ^ offa[q]] = make_float2(accb[2 * q], accb[2 * q + 1]);
+    }
+    if (grp < groups) {
+        const uint32_t ua = unit_base(grp);
+        float2 xa[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xa[q] = tile[ua ^ offa[q]];
+        f32x16 acca = {0}, accb = {0};
+        product2<PM>(fr, xa, xa, acca, accb);     // the second chain is discarded
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tile[ua ^ offa[q]] = make_float2(acca[2 * q], acca[2 * q + 1]);
+    }
+}
+
+// The scalar fields of a pass.
+struct PassHead {
+    int op_begin, op_end, phase_begin, phase_end, first_frag;
+};
+
 // One pass on the tile in LDS as register phases. A unit u < 2^(m-4) is the
 // set of 16 amplitudes that share the complement bits u; the units of a phase
-// are disjoint, so the threads take them in any order.
-template <int NT>
-__device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs& a)
+// are disjoint, so the threads take them in any order. The operands of the
+// next fused phase are fetched while a fused phase runs (the pass's first
+// ones while the tile is filled), so their latency overlaps that work.
+template <int NT, int PM>
+__device__ void run_phases(float2* tile, int m, const PassHead& ps, const BatchArgs& a, float* fragbuf)
 {
     const uint32_t units = 1u << (m - kRegBits);
+    int cur = 0;     // buffer holding the next fused phase's operands
     for (int hi = ps.phase_begin; hi < ps.phase_end; ++hi) {
-        const BPhase ph = a.phases[hi];
+        const BPhase ph = ld_const(a.phases + hi);
+        if constexpr (PM != kPhaseGates) {
+            if (ph.frag >= 0) {
+                FragCopy<NT> nx{};
+                if (ph.next_frag >= 0) nx = frag_fetch<NT>(a, ph.next_frag);
+                const Frag fr = frag_lds(fragbuf + cur * kFragBlock, threadIdx.x & 63);
+                fused_phase<NT, PM>(tile, m, ph, fr);
+                if (ph.next_frag >= 0) frag_put<NT>(fragbuf + (cur ^ 1) * kFragBlock, nx);
+                cur ^= 1;
+                __syncthreads();
+                continue;
+            }
+        }
         if (ph.g[0] < 0) {
             // a gate on more than four qubits: one LDS sweep
             for (int oi = ph.op_begin; oi < ph.op_end; ++oi) {
@@ -254,21 +581,16 @@ __device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs
             }
             continue;
         }
-        uint32_t goff[kRegBits];
-        uint32_t gmask = 0;
+        uint32_t goff[kRegBits];      // swizzled offsets of the phase's qubits
 #pragma unroll
-        for (int i = 0; i < kRegBits; ++i) {
-            goff[i] = 1u << ph.g[i];
-            gmask |= goff[i];
-        }
+        for (int i = 0; i < kRegBits; ++i) goff[i] = swz(1u << ph.g[i]);
         for (uint32_t u = threadIdx.x; u < units; u += NT) {
-            // deposit the unit index on the complement positions
-            uint32_t base = 0;
-            for (int b = 0, k = 0; b < m; ++b) {
-                if ((gmask >> b) & 1) continue;
-                if ((u >> k) & 1) base |= 1u << b;
-                ++k;
-            }
+            // the unit index with zeros inserted at the phase's qubits (ascending)
+            uint32_t base = u;
+#pragma unroll
+            for (int i = 0; i < kRegBits; ++i)
+                base = ((base >> ph.g[i]) << (ph.g[i] + 1)) | (base & ((1u << ph.g[i]) - 1u));
+            base = swz(base);
             float2 v[16];
             uint32_t off[16];
 #pragma unroll
@@ -276,7 +598,7 @@ __device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs
                 uint32_t o = base;
 #pragma unroll
                 for (int i = 0; i < kRegBits; ++i)
-                    if ((j >> i) & 1) o |= goff[i];
+                    if ((j >> i) & 1) o ^= goff[i];
                 off[j] = o;
             }
 #pragma unroll
@@ -290,35 +612,55 @@ __device__ void run_phases(float2* tile, int m, const BPass& ps, const BatchArgs
     }
 }
 
-// Offset inside the state of tile-local index l = threadIdx.x + NT j: the
-// thread's own bits (off_t) plus the bits of j on tile positions LB.. (LB =
-// log2 NT).
-template <int LB>
-__device__ __forceinline__ uint64_t tile_off(const int* pos, int m, uint64_t off_t, uint32_t j)
-{
-    uint64_t off = off_t;
-    for (int b = LB; b < m; ++b)
-        if ((j >> (b - LB)) & 1) off |= 1ull << pos[b];
-    return off;
-}
-
-template <int NT>
-__device__ __forceinline__ void wg_sum(double (&zs)[kZ], double (*red)[kZ])
+// Sum of each of K per-thread values over the workgroup: red[w][i] holds
+// wave w's sum of value i after the call.
+template <int NT, int K>
+__device__ __forceinline__ void wg_sum(double (&zs)[K], double (*red)[kZ])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int i = 0; i < kZ; ++i) zs[i] += __shfl_xor(zs[i], off, 64);
+        for (int i = 0; i < K; ++i) zs[i] += __shfl_xor(zs[i], off, 64);
     if (lane == 0)
 #pragma unroll
-        for (int i = 0; i < kZ; ++i) red[wave][i] = zs[i];
+        for (int i = 0; i < K; ++i) red[wave][i] = zs[i];
     __syncthreads();
 }
 
 constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
 
-template <int NT>
+// State offsets of a thread's tile elements (see the fill in k_batch).
+template <int LB>
+struct ElemOffsets {
+    static constexpr int kHb = kMaxTileBits - 8;    // element bits: tile bits LB.. (LB >= 8)
+    uint32_t off_t;                                  // this thread's own tile bits
+    uint32_t hb[kHb];
+    uint32_t hq[8];                                  // element bits 0..2 of a chunk
+
+    __device__ __forceinline__ ElemOffsets(const int* pos, int m)
+    {
+        const int hb_n = m > LB ? m - LB : 0;
+        off_t = 0;
+        for (int b = 0; b < m && b < LB; ++b)
+            if ((threadIdx.x >> b) & 1) off_t |= 1u << pos[b];
+#pragma unroll
+        for (int i = 0; i < kHb; ++i) hb[i] = i < hb_n ? 1u << pos[LB + i] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hq[q] = ((q & 1) ? hb[0] : 0u) | ((q & 2) ? hb[1] : 0u) | ((q & 4) ? hb[2] : 0u);
+    }
+    // offset of chunk e0's element bits 3..
+    __device__ __forceinline__ uint32_t chunk(int e0) const
+    {
+        uint32_t h0 = 0;
+#pragma unroll
+        for (int i = 3; i < kHb; ++i)
+            if ((e0 >> i) & 1) h0 |= hb[i];
+        return h0;
+    }
+};
+
+template <int NT, int PM>
 __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
 {
     constexpr int LB = log2i(NT);
@@ -327,15 +669,18 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
     __shared__ double red[NW][kZ];
     __shared__ int s_pos[kMaxTileBits];      // the pass's tile qubits (LDS: indexed at run time)
     __shared__ int s_task, s_final, s_late;
+    __shared__ __align__(16) float fragbuf[PM != kPhaseGates ? 2 * kFragBlock : 4];
     for (;;) {
         if (threadIdx.x == 0) s_task = atomicAdd(a.counter, 1);
         __syncthreads();
-        const int ti = s_task;
+        const int ti = __builtin_amdgcn_readfirstlane(s_task);   // uniform: table reads go through the scalar cache
         __syncthreads();
         if (ti >= a.n_tasks) break;
-        const BTask tk = a.tasks[ti];
-        const BCirc c = a.circ[tk.circ];
-        const BPass& ps = a.pass[tk.pass];
+        const BTask tk = ld_const(a.tasks + ti);
+        const BCirc c = ld_const(a.circ + tk.circ);
+        const BPass& ps = a.pass[tk.pass];     // per-thread reads of pos[] below
+        const PassHead hd = {ld_const(&ps.op_begin), ld_const(&ps.op_end), ld_const(&ps.phase_begin),
+                             ld_const(&ps.phase_end), ld_const(&ps.first_frag)};
         const int m = c.m;
         if (threadIdx.x < kMaxTileBits) s_pos[threadIdx.x] = ps.pos[threadIdx.x];
         const uint32_t tsize = 1u << m;
@@ -357,63 +702,113 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
         }
         __syncthreads();
         const uint64_t base = insert_zeros((uint64_t)tk.tile, s_pos, m);
-        uint64_t off_t = 0;
-        for (int b = 0; b < m && b < LB; ++b)
-            if ((threadIdx.x >> b) & 1) off_t |= 1ull << s_pos[b];
-        // fill the tile
-        for (uint32_t j = 0; (j << LB) < tsize; ++j) {
-            const uint32_t l = threadIdx.x + (j << LB);
-            if (l >= tsize) break;
-            if (first) tile[l] = make_float2(base == 0 && l == 0 ? 1.f : 0.f, 0.f);
-            else tile[l] = ld2<false>(a.arena + c.arena_off + base + tile_off<LB>(s_pos, m, off_t, j));
+        // Element e of this thread is tile index l = threadIdx.x + (e << LB);
+        // its state offset is base + off_t + hoff(e), hoff(e) = the OR of
+        // 1 << pos[LB + i] over the set bits i of e. Elements move in chunks
+        // of 8 so that a thread has 8 memory accesses in flight. The offsets
+        // are rebuilt from s_pos where they are used (fill, then store) so
+        // that they hold no registers while the phases run.
+        const int hb_n = m > LB ? m - LB : 0;
+        const int per = 1 << hb_n;                  // elements per thread
+        const bool active = threadIdx.x < tsize;    // m < LB: fewer amplitudes than threads
+        // fill the tile (and stage the pass's first fused-phase operands)
+        if constexpr (PM != kPhaseGates)
+            if (hd.first_frag >= 0) frag_put<NT>(fragbuf, frag_fetch<NT>(a, hd.first_frag));
+        if (active) {
+            if (first) {
+                for (int e = 0; e < per; ++e) {
+                    const uint32_t l = threadIdx.x + ((uint32_t)e << LB);
+                    tile[swz(l)] = make_float2(base == 0 && l == 0 ? 1.f : 0.f, 0.f);
+                }
+            } else {
+                const ElemOffsets<LB> eo(s_pos, m);
+                const float2* st_t = a.arena + c.arena_off + base + eo.off_t;
+                for (int e0 = 0; e0 < per; e0 += 8) {
+                    const uint32_t h0 = eo.chunk(e0);
+                    float2 v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q < per) v[q] = ld2<false>(st_t + (h0 | eo.hq[q]));
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q < per) tile[swz(threadIdx.x + ((uint32_t)(e0 + q) << LB))] = v[q];
+                }
+            }
         }
         __syncthreads();
-        if (ps.phase_end > ps.phase_begin) {
-            run_phases<NT>(tile, m, ps, a);
+        if (hd.phase_end > hd.phase_begin) {
+            run_phases<NT, PM>(tile, m, hd, a, fragbuf);
         } else {
-            for (int oi = ps.op_begin; oi < ps.op_end; ++oi) {
+            for (int oi = hd.op_begin; oi < hd.op_end; ++oi) {
                 lds_gate<NT>(tile, m, a.ops[oi], a.mats + (size_t)oi * kMatStride);
                 __syncthreads();
             }
         }
         if (last) {
-            double zs[kZ];
+            // probability sums per tile bit: S[b] = sum of p over the tile's
+            // amplitudes with tile bit b set, S[kMaxTileBits] = sum of p. For
+            // b < LB bit b is this thread's own, so only the element bits
+            // (b >= LB) need per-amplitude work.
+            constexpr int kS = kMaxTileBits + 1;
+            constexpr int kHb = ElemOffsets<LB>::kHb;
+            double tot = 0.0, hs[kHb];
 #pragma unroll
-            for (int i = 0; i < kZ; ++i) zs[i] = 0.0;
-            for (uint32_t j = 0; (j << LB) < tsize; ++j) {
-                const uint32_t l = threadIdx.x + (j << LB);
-                if (l >= tsize) break;
-                const uint64_t gb = base + tile_off<LB>(s_pos, m, off_t, j);
-                const float2 v = tile[l];
-                const double p = (double)v.x * v.x + (double)v.y * v.y;
-                zs[kBatchMaxQubits] += p;
+            for (int i = 0; i < kHb; ++i) hs[i] = 0.0;
+            if (active)
+                for (int e0 = 0; e0 < per; e0 += 8) {
 #pragma unroll
-                for (int i = 0; i < kBatchMaxQubits; ++i)
-                    if ((gb >> i) & 1) zs[i] += p;
-            }
-            wg_sum<NT>(zs, red);
-            if (c.ntiles == 1) {
-                if (threadIdx.x < SV_BATCH_OUT_STRIDE) {
-                    const int i = threadIdx.x;
-                    double t = 0.0, s = 0.0;
-                    if (i < c.n)
-                        for (int w = 0; w < NW; ++w) {
-                            t += red[w][kBatchMaxQubits];
-                            s += red[w][i];
-                        }
-                    a.out[(size_t)c.out_idx * SV_BATCH_OUT_STRIDE + i] =
-                        s_late ? __builtin_nan("") : (i < c.n ? t - 2.0 * s : 0.0);
+                    for (int q = 0; q < 8; ++q) {
+                        if (q >= per) continue;
+                        const float2 v = tile[swz(threadIdx.x + ((uint32_t)(e0 + q) << LB))];
+                        const double p = (double)v.x * v.x + (double)v.y * v.y;
+                        tot += p;
+#pragma unroll
+                        for (int i = 0; i < kHb; ++i)
+                            if (((e0 + q) >> i) & 1) hs[i] += p;
+                    }
                 }
-            } else if (threadIdx.x < kZ) {
-                double s = 0.0;
-                for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
-                a.zpart[(size_t)(c.zpart_off + tk.tile) * kZ + threadIdx.x] = s_late ? __builtin_nan("") : s;
+            double zs[kS];
+#pragma unroll
+            for (int b = 0; b < kMaxTileBits; ++b) {
+                if (b < LB) zs[b] = ((threadIdx.x >> b) & 1) ? tot : 0.0;
+                else zs[b] = hs[b - LB];
             }
-        } else {
-            for (uint32_t j = 0; (j << LB) < tsize; ++j) {
-                const uint32_t l = threadIdx.x + (j << LB);
-                if (l >= tsize) break;
-                st2<false>(a.arena + c.arena_off + base + tile_off<LB>(s_pos, m, off_t, j), tile[l]);
+            zs[kMaxTileBits] = tot;
+            wg_sum<NT, kS>(zs, red);
+            // per qubit of the circuit: a tile qubit's sum, else the whole
+            // tile's sum when the qubit's (fixed) bit in this tile is 1
+            double zq = 0.0, tt = 0.0;
+            const int i = threadIdx.x;
+            if (i < kZ) {
+                int bt = -1;
+                for (int b = 0; b < m; ++b)
+                    if (s_pos[b] == i) bt = b;
+                for (int w = 0; w < NW; ++w) {
+                    tt += red[w][kMaxTileBits];
+                    if (bt >= 0) zq += red[w][bt];
+                }
+                if (i == kBatchMaxQubits) zq = tt;
+                else if (bt < 0) zq = ((base >> i) & 1) ? tt : 0.0;
+            }
+            if (c.ntiles == 1) {
+                if (i < SV_BATCH_OUT_STRIDE)
+                    a.out[(size_t)c.out_idx * SV_BATCH_OUT_STRIDE + i] =
+                        s_late ? __builtin_nan("") : (i < c.n ? tt - 2.0 * zq : 0.0);
+            } else if (i < kZ) {
+                a.zpart[(size_t)(c.zpart_off + tk.tile) * kZ + i] = s_late ? __builtin_nan("") : zq;
+            }
+        } else if (active) {
+            const ElemOffsets<LB> eo(s_pos, m);
+            float2* st_t = a.arena + c.arena_off + base + eo.off_t;
+            for (int e0 = 0; e0 < per; e0 += 8) {
+                const uint32_t h0 = eo.chunk(e0);
+                float2 v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q < per) v[q] = tile[swz(threadIdx.x + ((uint32_t)(e0 + q) << LB))];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q < per) st2<false>(st_t + (h0 | eo.hq[q]), v[q]);
             }
         }
         __syncthreads();   // all results written before the pass counter moves
@@ -446,9 +841,20 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
 }
 
 template <int NT>
-void* batch_kernel()
+void* batch_kernel(int phase_mode)
 {
-    return reinterpret_cast<void*>(&k_batch<NT>);
+    switch (phase_mode) {
+    case kPhaseFp32: return reinterpret_cast<void*>(&k_batch<NT, kPhaseFp32>);
+    case kPhaseBf16x3: return reinterpret_cast<void*>(&k_batch<NT, kPhaseBf16x3>);
+    default: return reinterpret_cast<void*>(&k_batch<NT, kPhaseGates>);
+    }
+}
+
+void* batch_kernel_for(int threads, int phase_mode)
+{
+    return threads == 256 ? batch_kernel<256>(phase_mode)
+           : threads == 512 ? batch_kernel<512>(phase_mode)
+                            : batch_kernel<1024>(phase_mode);
 }
 
 }  // namespace
@@ -458,11 +864,11 @@ size_t batch_lds_bytes(int tile_bits)
     return (sizeof(float2) << tile_bits);
 }
 
-int batch_max_wg_per_cu(int threads, int tile_bits)
+int batch_max_wg_per_cu(int threads, int tile_bits, int phase_mode)
 {
     int nb = 0;
     const size_t lds = batch_lds_bytes(tile_bits);
-    void* f = threads == 256 ? batch_kernel<256>() : threads == 512 ? batch_kernel<512>() : batch_kernel<1024>();
+    void* f = batch_kernel_for(threads, phase_mode);
     SV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, threads, lds));
     return std::max(nb, 1);
@@ -470,16 +876,13 @@ int batch_max_wg_per_cu(int threads, int tile_bits)
 
 void launch_batch(const BatchArgs& a, int grid, int threads, int tile_bits, hipStream_t st)
 {
-    const int items = std::max(std::max(a.n_ops, a.n_pass), 1);
+    const int items = std::max(std::max(a.n_ops, a.n_pass), std::max(a.n_frag * 16, 1));
     hipLaunchKernelGGL(k_batch_prep, dim3((items + 255) / 256), dim3(256), 0, st, a);
     SV_HIP(hipGetLastError());
     const size_t lds = batch_lds_bytes(tile_bits);
-    switch (threads) {
-    case 256: hipLaunchKernelGGL(k_batch<256>, dim3(grid), dim3(256), lds, st, a); break;
-    case 512: hipLaunchKernelGGL(k_batch<512>, dim3(grid), dim3(512), lds, st, a); break;
-    default: hipLaunchKernelGGL(k_batch<1024>, dim3(grid), dim3(1024), lds, st, a); break;
-    }
-    SV_HIP(hipGetLastError());
+    void* f = batch_kernel_for(threads, a.phase_mode);
+    void* args[] = {const_cast<BatchArgs*>(&a)};
+    SV_HIP(hipLaunchKernel(f, dim3(grid), dim3(threads), args, lds, st));
 }
 
 }  // namespace sv

@@ -49,14 +49,17 @@ class SvPauliTerm(C.Structure):
 
 class SvBatchConfig(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("threads", C.c_int32), ("reg_min_bits", C.c_int32),
-                ("wg_per_cu", C.c_int32)]
+                ("wg_per_cu", C.c_int32), ("phase_mode", C.c_int32), ("fuse_min_gates", C.c_int32),
+                ("run_bits", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
     @classmethod
     def of(cls, d: dict) -> "SvBatchConfig":
-        return cls(*[int(d[f]) for f, _ in cls._fields_])
+        """Fields missing from d take the library's default."""
+        base = default_batch_config() if any(f not in d for f, _ in cls._fields_) else {}
+        return cls(*[int(d[f] if f in d else base[f]) for f, _ in cls._fields_])
 
 
 class SvBatchTrial(C.Structure):

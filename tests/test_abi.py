@@ -115,12 +115,16 @@ def test_gate_validation_host_only(svmod, n, targets, controls, code):
 def test_batch_config_default_and_validation_host_only(svmod):
     """The default launch shape, and out-of-range shapes rejected before any
     device work (no GPU needed)."""
-    assert svmod.default_batch_config() == {"tile_bits": 14, "threads": 1024, "reg_min_bits": 12, "wg_per_cu": 0}
+    assert svmod.default_batch_config() == {"tile_bits": 14, "threads": 512, "reg_min_bits": 12, "wg_per_cu": 0,
+                                            "phase_mode": 1, "fuse_min_gates": 3, "run_bits": 3}
     circ = Cc.ghz(3)
     table = svmod.OpTable(circ.ops)
     ops_arr = (C.POINTER(svmod.SvOp) * 1)(C.cast(table.arr, C.POINTER(svmod.SvOp)))
-    bad = [(9, 1024, 12, 0), (15, 1024, 12, 0), (12, 128, 12, 0), (12, 256, 3, 0), (12, 256, 16, 0),
-           (12, 256, 12, -1), (12, 256, 12, 17)]
+    bad = [(9, 1024, 12, 0, 1, 3, 4), (15, 1024, 12, 0, 1, 3, 4), (12, 128, 12, 0, 1, 3, 4),
+           (12, 256, 3, 0, 1, 3, 4), (12, 256, 16, 0, 1, 3, 4), (12, 256, 12, -1, 1, 3, 4),
+           (12, 256, 12, 17, 1, 3, 4), (12, 256, 12, 0, 3, 3, 4), (12, 256, 12, 0, -1, 3, 4),
+           (12, 256, 12, 0, 1, 0, 4), (12, 256, 12, 0, 2, 65, 4), (12, 256, 12, 0, 1, 3, 2),
+           (12, 256, 12, 0, 1, 3, 7), (10, 256, 10, 0, 1, 3, 6)]
     for cfg in bad:
         h = C.c_void_p()
         st = svmod.lib().sv_batch_plan_create_ex(1, svmod._iarr([3]), ops_arr, svmod._iarr([table.n]),

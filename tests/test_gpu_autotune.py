@@ -2,10 +2,11 @@
 autotuners themselves.
 
 * Batched launch: each tile width (10..14 qubits), thread count (256, 512,
-  1024), register-phase threshold and workgroups-per-CU setting gives the
-  oracle's <Z_i> for a batch whose circuits are narrower and wider than the
-  tile (so 10-qubit tiles cut 11..16-qubit circuits into passes over the
-  arena). Tolerance as the other batch tests: 2e-5.
+  1024), register-phase threshold, workgroups-per-CU setting, run length
+  and phase arithmetic (gate by gate, fused FP32, fused BF16x3) gives the oracle's
+  <Z_i> for a batch whose circuits are narrower and wider than the tile (so
+  10-qubit tiles cut 11..16-qubit circuits into passes over the arena).
+  Tolerance as the other batch tests: 2e-5 (1e-4 for BF16x3 phases).
 * The batch autotuner returns a configuration it ran, whose output agreed
   with the default's, and that is the fastest such trial.
 * The fusion autotuner's choice, applied, gives the oracle's state.
@@ -44,20 +45,31 @@ def _expected(circuits):
 
 WORK = _workload()
 
-CONFIGS = [(tb, th, 12, 0) for tb in (10, 11, 12, 13, 14) for th in (256, 512, 1024)]
-CONFIGS += [(14, 1024, 4, 0), (14, 256, 8, 0), (12, 512, 15, 0), (10, 256, 10, 2), (13, 512, 12, 1)]
+# (tile_bits, threads, reg_min_bits, wg_per_cu, phase_mode, fuse_min_gates, run_bits)
+CONFIGS = [(tb, th, 12, 0, pm, 3, 4) for tb in (10, 11, 12, 13, 14) for th in (256, 512, 1024) for pm in (0, 1)]
+CONFIGS += [(14, 1024, 4, 0, 1, 1, 4), (14, 256, 8, 0, 1, 1, 6), (12, 512, 15, 0, 1, 3, 5), (10, 256, 10, 2, 1, 2, 3),
+            (13, 512, 12, 1, 0, 3, 6), (14, 1024, 12, 0, 2, 1, 3), (11, 512, 9, 0, 2, 2, 5), (12, 256, 4, 0, 1, 64, 4),
+            (10, 1024, 12, 0, 1, 3, 5), (14, 512, 12, 0, 1, 3, 3)]
+# BF16x3 phases: per phase the operands carry ~2^-17 relative representation
+# error (hi + lo of an FP32 value, the lo*lo product dropped); summed over the
+# tens of phases of these circuits the <Z_i> error stays below 1e-4
+BF16_Z_TOL = 1e-4
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "tb{}_th{}_reg{}_wg{}".format(*c))
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "tb{}_th{}_reg{}_wg{}_pm{}_fm{}_rb{}".format(*c))
 def test_batch_config_parity(sv, cfg):
-    d = dict(zip(("tile_bits", "threads", "reg_min_bits", "wg_per_cu"), cfg))
+    d = dict(zip(("tile_bits", "threads", "reg_min_bits", "wg_per_cu", "phase_mode", "fuse_min_gates", "run_bits"),
+                 cfg))
     plan = svmod.BatchPlan(WORK, config=d)
     info = plan.info()
     assert info["config"]["tile_bits"] == cfg[0] and info["config"]["threads"] == cfg[1]
+    assert info["config"]["phase_mode"] == cfg[4] and info["config"]["fuse_min_gates"] == cfg[5]
+    assert info["config"]["run_bits"] == cfg[6]
     assert info["config"]["wg_per_cu"] >= 1 and info["grid"] >= 1
     out = plan.run()
+    tol = BF16_Z_TOL if cfg[4] == 2 else Z_TOL
     for i, (c, z) in enumerate(zip(WORK, _expected(WORK))):
-        np.testing.assert_allclose(out[i, : c.n], z, atol=Z_TOL, err_msg=f"circuit {i} n={c.n} cfg={cfg}")
+        np.testing.assert_allclose(out[i, : c.n], z, atol=tol, err_msg=f"circuit {i} n={c.n} cfg={cfg}")
         assert np.all(out[i, c.n:] == 0)
     plan.free()
 
@@ -66,7 +78,10 @@ def test_bad_batch_config_rejected(sv):
     for bad in ({"tile_bits": 9, "threads": 1024, "reg_min_bits": 12, "wg_per_cu": 0},
                 {"tile_bits": 12, "threads": 384, "reg_min_bits": 12, "wg_per_cu": 0},
                 {"tile_bits": 12, "threads": 256, "reg_min_bits": 3, "wg_per_cu": 0},
-                {"tile_bits": 12, "threads": 256, "reg_min_bits": 12, "wg_per_cu": 17}):
+                {"tile_bits": 12, "threads": 256, "reg_min_bits": 12, "wg_per_cu": 17},
+                {"tile_bits": 12, "threads": 256, "reg_min_bits": 12, "wg_per_cu": 0, "phase_mode": 3},
+                {"tile_bits": 12, "threads": 256, "reg_min_bits": 12, "wg_per_cu": 0, "fuse_min_gates": 0},
+                {"tile_bits": 10, "threads": 256, "reg_min_bits": 12, "wg_per_cu": 0, "run_bits": 6}):
         with pytest.raises(svmod.SvError):
             svmod.BatchPlan(WORK[:2], config=bad)
 

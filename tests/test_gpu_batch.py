@@ -3,7 +3,9 @@ hipGraph-captured kernel) against the oracle circuit by circuit, and against
 the per-gate form of the same batch.
 
 Tolerance: <Z_i> within 2e-5 (complex64 state error <= 1e-5 in norm at
-these depths, |d<Z>| <= 2 ||dpsi||)."""
+these depths, |d<Z>| <= 2 ||dpsi||). The default launch fuses register
+phases of >= 3 gates on FP32 matrix cores; gate-by-gate and BF16x3 phases
+are checked too."""
 
 import numpy as np
 import pytest
@@ -85,6 +87,28 @@ def test_batch_workload_sample(sv):
     plan = svmod.BatchPlan(circuits)
     out = plan.run()
     _check(out, circuits)
+
+
+@pytest.mark.parametrize("pm", [0, 1, 2], ids=["gates", "fused_fp32", "fused_bf16x3"])
+def test_phase_arithmetic_deep_circuits(sv, pm):
+    """Deep circuits of 15..20 qubits (the batching workload's 6-layer
+    ansatz; random circuits with two-qubit and controlled gates) with every
+    register phase fused (fuse_min_gates 1) in each phase arithmetic, vs the
+    oracle; BF16x3 phases within 1e-4 (operands with ~2^-17 relative error,
+    tens of phases)."""
+    rng = np.random.default_rng(31)
+    circuits = [C.encoded_ansatz(n, 6, rng) for n in (15, 18, 20)]
+    circuits += [C.random_circuit(17, 300, 12), C.random_circuit(20, 300, 13)]
+    plan = svmod.BatchPlan(circuits, config={"phase_mode": pm, "fuse_min_gates": 1})
+    out = plan.run()
+    tol = 1e-4 if pm == 2 else Z_TOL
+    errs = []
+    for i, c in enumerate(circuits):
+        z, _ = oracle.expval_z_all(oracle.run(c), c.n)
+        errs.append(float(np.max(np.abs(out[i, : c.n] - z))))
+    print(f"phase_mode {pm}: max |dZ| per circuit {['%.2e' % e for e in errs]}")
+    assert max(errs) <= tol
+    plan.free()
 
 
 def test_batch_rejects_bad_plans(sv):
