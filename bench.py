@@ -376,14 +376,18 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     t0 = time.perf_counter()
     best, trials = sv.batch_autotune(circs, reps=2)
     tune_s = time.perf_counter() - t0
-    timings = {}
-    for name, cfg in (("default", None), ("tuned", best)):
+    timings, outs, stats = {}, {}, {}
+    modes = (("default", None), ("tuned", best), ("gate_by_gate", {"phase_mode": 0}),
+             ("fused_fp32", {"phase_mode": 1}), ("fused_bf16x3", {"phase_mode": 2}))
+    for name, cfg in modes:
         plan = sv.BatchPlan(circs, config=cfg)
         dp = plan.pack()
         out = plan.out_buffer()
         plan.launch(dp, out)
         torch.cuda.synchronize()
         timings[name] = min(_timed_ms(lambda: plan.launch(dp, out), stream) for _ in range(3))
+        outs[name] = out.cpu().numpy().copy()
+        stats[name] = plan.stats()
         if name == "tuned":
             info = plan.info()
             t0 = time.perf_counter()
@@ -393,12 +397,31 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         plan.free()
     graph_ms = timings["tuned"]
     gates = sum(len(c.ops) for c in circs)
+
+    def mode_entry(name, flop_per_amp, peak):
+        st = stats[name]
+        e = {"ms": round(timings[name], 3), "gates_per_s": round(gates / (timings[name] / 1e3), 1),
+             "max_dev_vs_default": float(np.max(np.abs(outs[name] - outs["default"]))),
+             "fused_phases": st["n_fused_phases"], "phases": st["n_phases"], "passes": st["n_passes"]}
+        if flop_per_amp:
+            # matrix-core work of the fused phases over the whole launch
+            tf = st["fused_amp_phases"] * flop_per_amp / (timings[name] / 1e3) / 1e12
+            e["mfma_TFLOPs"] = round(tf, 1)
+            e["mfma_peak_TFLOPs"] = peak
+            e["mfma_frac"] = round(tf / peak, 3)
+        return e
+
     res["batched"] = {
         "workload": "256 circuits, n uniform in 10..20, encoded RY inputs + 6 x [RY, RZ, CNOT ladder], all <Z_i>",
         "gates": gates, "graph_launch_ms": round(graph_ms, 3), "per_gate_launches_ms": round(pergate_ms, 2),
         "gates_per_s": round(gates / (graph_ms / 1e3), 1),
         "speedup_vs_per_gate": round(pergate_ms / graph_ms, 2),
         "default_config_ms": round(timings["default"], 3),
+        # a fused phase amplitude costs one 32-wide real row of a 32x32
+        # product: 64 multiply-adds = 128 FLOP (BF16x3: three such products)
+        "phase_arithmetic": {"gate_by_gate": mode_entry("gate_by_gate", 0, None),
+                             "fused_fp32": mode_entry("fused_fp32", 128, 157.3),
+                             "fused_bf16x3": mode_entry("fused_bf16x3", 3 * 128, 2500.0)},
         "autotune": {"chosen": info["config"], "grid": info["grid"], "tasks": info["n_tasks"],
                      "passes": info["n_passes"], "configs_tried": len(trials), "tune_s": round(tune_s, 2)},
     }

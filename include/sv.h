@@ -387,6 +387,23 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
 sv_status sv_batch_plan_info(sv_batch_plan p, sv_batch_config* config, int* grid, int* n_tasks,
                              int* n_passes);
 
+/* Work of a batch plan (for rooflines).
+ *   fused_amp_phases: sum over fused phases of the amplitudes they update
+ *     (each update is one 16 x 16 complex product share: 64 real
+ *     multiply-adds per amplitude);
+ *   gate_amp_updates: sum over the gates applied one by one (register or
+ *     LDS sweeps) of the amplitudes each visits. */
+typedef struct sv_batch_stats {
+    int32_t n_tasks;
+    int32_t n_passes;
+    int32_t n_phases;
+    int32_t n_fused_phases;
+    int64_t fused_amp_phases;
+    int64_t gate_amp_updates;
+} sv_batch_stats;
+
+sv_status sv_batch_plan_stats(sv_batch_plan p, sv_batch_stats* out);
+
 /* Number of doubles in the parameter block the launch reads: circuit c's
  * parameter j is at offset param_offset[c] + j. */
 sv_status sv_batch_param_layout(sv_batch_plan p, int64_t* param_offsets, int64_t* total);

@@ -34,6 +34,7 @@ struct sv_batch_plan_s {
     int n_tasks = 0;
     int n_ops = 0;
     int n_pass = 0;
+    sv_batch_stats stats{};
     int grid = 1;
     sv_batch_config cfg{};                     // effective configuration
     hipGraph_t graph = nullptr;
@@ -430,6 +431,14 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                             x.frag = (int)frag_phase.size();
                             frag_phase.push_back((int)phase.size());
                         }
+                        const int64_t amps = 1ll << n;     // every tile of the pass runs the phase
+                        p->stats.n_phases += 1;
+                        if (x.frag >= 0) {
+                            p->stats.n_fused_phases += 1;
+                            p->stats.fused_amp_phases += amps;
+                        } else {
+                            p->stats.gate_amp_updates += amps * (x.op_end - x.op_begin);
+                        }
                         phase.push_back(x);
                     }
                     bp.phase_end = (int)phase.size();
@@ -442,6 +451,7 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                     for (int oi : order) bops.push_back(pops[oi]);
                 } else {
                     bops.insert(bops.end(), pops.begin(), pops.end());
+                    p->stats.gate_amp_updates += (1ll << n) * (int64_t)pops.size();
                 }
                 bp.op_end = (int)bops.size();
                 pass.push_back(bp);
@@ -516,6 +526,16 @@ sv_status sv_batch_plan_info(sv_batch_plan p, sv_batch_config* config, int* grid
         if (grid) *grid = p->grid;
         if (n_tasks) *n_tasks = p->n_tasks;
         if (n_passes) *n_passes = p->n_pass;
+    });
+}
+
+sv_status sv_batch_plan_stats(sv_batch_plan p, sv_batch_stats* out)
+{
+    return guarded([&] {
+        need(p != nullptr && out != nullptr, SV_ERR_INVALID_ARGUMENT, "null plan or output");
+        *out = p->stats;
+        out->n_tasks = p->n_tasks;
+        out->n_passes = p->n_pass;
     });
 }
 

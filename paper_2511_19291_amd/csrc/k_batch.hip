@@ -630,13 +630,15 @@ __device__ __forceinline__ void wg_sum(double (&zs)[K], double (*red)[kZ])
 
 constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
 
-// State offsets of a thread's tile elements (see the fill in k_batch).
-template <int LB>
+// State offsets of a thread's tile elements (see the fill in k_batch);
+// elements move in chunks of 2^CB.
+template <int LB, int CB>
 struct ElemOffsets {
     static constexpr int kHb = kMaxTileBits - 8;    // element bits: tile bits LB.. (LB >= 8)
+    static constexpr int kChunk = 1 << CB;
     uint32_t off_t;                                  // this thread's own tile bits
     uint32_t hb[kHb];
-    uint32_t hq[8];                                  // element bits 0..2 of a chunk
+    uint32_t hq[kChunk];                             // element bits 0..CB-1 of a chunk
 
     __device__ __forceinline__ ElemOffsets(const int* pos, int m)
     {
@@ -647,14 +649,20 @@ struct ElemOffsets {
 #pragma unroll
         for (int i = 0; i < kHb; ++i) hb[i] = i < hb_n ? 1u << pos[LB + i] : 0u;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) hq[q] = ((q & 1) ? hb[0] : 0u) | ((q & 2) ? hb[1] : 0u) | ((q & 4) ? hb[2] : 0u);
+        for (int q = 0; q < kChunk; ++q) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int i = 0; i < CB; ++i)
+                if ((q >> i) & 1) o |= hb[i];
+            hq[q] = o;
+        }
     }
-    // offset of chunk e0's element bits 3..
+    // offset of chunk e0's element bits CB..
     __device__ __forceinline__ uint32_t chunk(int e0) const
     {
         uint32_t h0 = 0;
 #pragma unroll
-        for (int i = 3; i < kHb; ++i)
+        for (int i = CB; i < kHb; ++i)
             if ((e0 >> i) & 1) h0 |= hb[i];
         return h0;
     }
@@ -665,6 +673,9 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
 {
     constexpr int LB = log2i(NT);
     constexpr int NW = NT / 64;
+    constexpr int CB = NT >= 1024 ? 3 : 4;      // 2^CB elements per thread in flight (registers allow 16 below 1024)
+    constexpr int kChunk = 1 << CB;
+    using Offsets = ElemOffsets<LB, CB>;
     extern __shared__ float2 tile[];         // 2^m complex64, m <= the plan's tile width
     __shared__ double red[NW][kZ];
     __shared__ int s_pos[kMaxTileBits];      // the pass's tile qubits (LDS: indexed at run time)
@@ -705,7 +716,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
         // Element e of this thread is tile index l = threadIdx.x + (e << LB);
         // its state offset is base + off_t + hoff(e), hoff(e) = the OR of
         // 1 << pos[LB + i] over the set bits i of e. Elements move in chunks
-        // of 8 so that a thread has 8 memory accesses in flight. The offsets
+        // of 2^CB so that a thread has that many memory accesses in flight. The offsets
         // are rebuilt from s_pos where they are used (fill, then store) so
         // that they hold no registers while the phases run.
         const int hb_n = m > LB ? m - LB : 0;
@@ -721,16 +732,16 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
                     tile[swz(l)] = make_float2(base == 0 && l == 0 ? 1.f : 0.f, 0.f);
                 }
             } else {
-                const ElemOffsets<LB> eo(s_pos, m);
+                const Offsets eo(s_pos, m);
                 const float2* st_t = a.arena + c.arena_off + base + eo.off_t;
-                for (int e0 = 0; e0 < per; e0 += 8) {
+                for (int e0 = 0; e0 < per; e0 += kChunk) {
                     const uint32_t h0 = eo.chunk(e0);
-                    float2 v[8];
+                    float2 v[kChunk];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
+                    for (int q = 0; q < kChunk; ++q)
                         if (q < per) v[q] = ld2<false>(st_t + (h0 | eo.hq[q]));
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
+                    for (int q = 0; q < kChunk; ++q)
                         if (q < per) tile[swz(threadIdx.x + ((uint32_t)(e0 + q) << LB))] = v[q];
                 }
             }
@@ -750,14 +761,14 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
             // b < LB bit b is this thread's own, so only the element bits
             // (b >= LB) need per-amplitude work.
             constexpr int kS = kMaxTileBits + 1;
-            constexpr int kHb = ElemOffsets<LB>::kHb;
+            constexpr int kHb = Offsets::kHb;
             double tot = 0.0, hs[kHb];
 #pragma unroll
             for (int i = 0; i < kHb; ++i) hs[i] = 0.0;
             if (active)
-                for (int e0 = 0; e0 < per; e0 += 8) {
+                for (int e0 = 0; e0 < per; e0 += kChunk) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
+                    for (int q = 0; q < kChunk; ++q) {
                         if (q >= per) continue;
                         const float2 v = tile[swz(threadIdx.x + ((uint32_t)(e0 + q) << LB))];
                         const double p = (double)v.x * v.x + (double)v.y * v.y;
@@ -798,16 +809,16 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
                 a.zpart[(size_t)(c.zpart_off + tk.tile) * kZ + i] = s_late ? __builtin_nan("") : zq;
             }
         } else if (active) {
-            const ElemOffsets<LB> eo(s_pos, m);
+            const Offsets eo(s_pos, m);
             float2* st_t = a.arena + c.arena_off + base + eo.off_t;
-            for (int e0 = 0; e0 < per; e0 += 8) {
+            for (int e0 = 0; e0 < per; e0 += kChunk) {
                 const uint32_t h0 = eo.chunk(e0);
-                float2 v[8];
+                float2 v[kChunk];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
+                for (int q = 0; q < kChunk; ++q)
                     if (q < per) v[q] = tile[swz(threadIdx.x + ((uint32_t)(e0 + q) << LB))];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
+                for (int q = 0; q < kChunk; ++q)
                     if (q < per) st2<false>(st_t + (h0 | eo.hq[q]), v[q]);
             }
         }

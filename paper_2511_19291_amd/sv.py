@@ -62,6 +62,11 @@ class SvBatchConfig(C.Structure):
         return cls(*[int(d[f] if f in d else base[f]) for f, _ in cls._fields_])
 
 
+class SvBatchStats(C.Structure):
+    _fields_ = [("n_tasks", C.c_int32), ("n_passes", C.c_int32), ("n_phases", C.c_int32),
+                ("n_fused_phases", C.c_int32), ("fused_amp_phases", C.c_int64), ("gate_amp_updates", C.c_int64)]
+
+
 class SvBatchTrial(C.Structure):
     _fields_ = [("config", SvBatchConfig), ("ms", C.c_double), ("max_dev", C.c_double)]
 
@@ -115,6 +120,7 @@ def lib() -> C.CDLL:
         "sv_batch_plan_create_ex": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, C.POINTER(SvBatchConfig), vp,
                                     C.POINTER(vp)],
         "sv_batch_plan_info": [vp, C.POINTER(SvBatchConfig), ip, ip, ip],
+        "sv_batch_plan_stats": [vp, C.POINTER(SvBatchStats)],
         "sv_batch_autotune": [C.c_int, ip, C.POINTER(C.POINTER(SvOp)), ip, ip, vp, C.c_int, vp,
                               C.POINTER(SvBatchConfig), C.POINTER(SvBatchTrial), C.c_int, ip],
         "sv_fused_autotune": [vp, C.POINTER(SvOp), C.c_int, dp, C.c_int, C.c_uint32, C.c_int,
@@ -426,6 +432,12 @@ class BatchPlan:
         grid, tasks, passes = C.c_int(), C.c_int(), C.c_int()
         check(lib().sv_batch_plan_info(self.h, C.byref(cfg), C.byref(grid), C.byref(tasks), C.byref(passes)))
         return {"config": cfg.as_dict(), "grid": grid.value, "n_tasks": tasks.value, "n_passes": passes.value}
+
+    def stats(self) -> dict:
+        """Work counts of the plan (sv_batch_plan_stats)."""
+        st = SvBatchStats()
+        check(lib().sv_batch_plan_stats(self.h, C.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in st._fields_}
 
     def pack(self, params_list=None):
         """Device FP64 parameter block in the plan's layout."""
