@@ -314,13 +314,17 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         blocked[f"block{lb}"] = {"backward_ms": round(ms_b, 2), "backward_over_forward": round(ms_b / fwd_ms, 3),
                                  "max_grad_diff_vs_per_gate": float(np.max(np.abs(grad_b[0] - grad[0]))),
                                  "drift": float(drift_b[0])}
+    # the autograd layers' forward: row-shared gates fused into 5-qubit
+    # matrix-core blocks (host planning included in the time)
+    fwd_fused_ms = min(_timed_ms(lambda: (st.reset(), st.run_fused(circ)), stream) for _ in range(2))
     n_par = circ.n_params
     shift_ms = 2 * n_par * fwd_ms
     # the autograd layers' default backward is the 4-qubit blocked one
     default_ms = blocked["block4"]["backward_ms"]
     res["adjoint"] = {
         "workload": "rxry_ring28: 28 qubits, 10 x [RX all, RY all, CNOT ring], loss <sum Z_i>",
-        "params": n_par, "forward_ms": round(fwd_ms, 2),
+        "params": n_par, "forward_ms": round(fwd_ms, 2), "forward_fused_ms": round(fwd_fused_ms, 2),
+        "train_step_ms": round(fwd_fused_ms + blocked["block4"]["backward_ms"], 2),
         "backward_ms": round(default_ms, 2), "backward_kind": "blocked, 4-qubit blocks (the default)",
         "backward_over_forward": round(default_ms / fwd_ms, 3),
         "backward_per_gate_ms": round(bwd_ms, 2), "per_gate_over_forward": round(bwd_ms / fwd_ms, 3),

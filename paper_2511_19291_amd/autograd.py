@@ -2,7 +2,10 @@
 execution, Sec. 4.4 and the `invertible=True` device of Appendix A).
 
 Forward: reset the state to |0..0>, run the circuit with the given
-parameters, return L = sum_t coeff_t <P_t> per batch row. Backward: the
+parameters, return L = sum_t coeff_t <P_t> per batch row. From 14 qubits on
+(``fuse``), gates whose angles are equal on every row are fused into
+5-qubit blocks on the matrix cores (Sec. 4.1.1); per-row gates (an input
+encoding) stay per-gate sweeps. Backward: the
 library un-applies the gates from the forward output (x = U^* y) and
 accumulates dL/dtheta in FP64; nothing is stored between the passes except
 the final state itself. By default the backward groups the gates into
@@ -19,6 +22,23 @@ import numpy as np
 import torch
 
 from . import sv
+
+
+# The forward fuses row-shared gates into matrix-core blocks from this width
+# on (below it a per-gate sweep is cheaper than planning the blocks).
+FUSED_FORWARD_MIN_QUBITS = 14
+
+
+def default_fuse(circuit) -> bool:
+    return circuit.n >= FUSED_FORWARD_MIN_QUBITS
+
+
+def _forward(state, circuit, p, fuse: bool) -> None:
+    state.reset()
+    if fuse:
+        state.run_fused(circuit, params=p)
+    else:
+        state.run(circuit, params=p)
 
 
 def default_block_qubits(circuit) -> int:
@@ -38,11 +58,10 @@ def default_block_qubits(circuit) -> int:
 class AdjointExpval(torch.autograd.Function):
     @staticmethod
     def forward(ctx, params: torch.Tensor, circuit, terms: Sequence[Tuple[float, int, int]], state: "sv.State",
-                block_qubits: int = 0):
+                block_qubits: int = 0, fuse: bool = False):
         ctx.block_qubits = block_qubits
         p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy())
-        state.reset()
-        state.run(circuit, params=p)
+        _forward(state, circuit, p, fuse)
         vals = state.expval(terms)                 # [batch, n_terms]
         loss = vals.sum(axis=1)
         ctx.circuit = circuit
@@ -59,7 +78,7 @@ class AdjointExpval(torch.autograd.Function):
         go = grad_out.detach().to("cpu", torch.float64).reshape(-1, 1).numpy()
         g = grad * go                              # [batch, n_params]
         g = torch.from_numpy(g.reshape(ctx.shape)).to(device=grad_out.device, dtype=grad_out.dtype)
-        return g, None, None, None, None
+        return g, None, None, None, None, None
 
 
 class QuantumExpval(torch.nn.Module):
@@ -67,15 +86,16 @@ class QuantumExpval(torch.nn.Module):
     differentiable through the adjoint backward."""
 
     def __init__(self, circuit, terms: Sequence[Tuple[float, int, int]], batch: int = 1, device=None,
-                 block_qubits=None):
+                 block_qubits=None, fuse=None):
         super().__init__()
         self.circuit = circuit
         self.terms = list(terms)
         self.state = sv.State(circuit.n, batch, device=device)
         self.block_qubits = default_block_qubits(circuit) if block_qubits is None else block_qubits
+        self.fuse = default_fuse(circuit) if fuse is None else bool(fuse)
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
-        return AdjointExpval.apply(params, self.circuit, self.terms, self.state, self.block_qubits)
+        return AdjointExpval.apply(params, self.circuit, self.terms, self.state, self.block_qubits, self.fuse)
 
 
 class ExpvalZ(torch.autograd.Function):
@@ -85,11 +105,10 @@ class ExpvalZ(torch.autograd.Function):
     observable sum_i g[r, i] Z_i of row r (``sv_adjoint_grad_weighted``)."""
 
     @staticmethod
-    def forward(ctx, params: torch.Tensor, circuit, state: "sv.State", block_qubits: int = 0):
+    def forward(ctx, params: torch.Tensor, circuit, state: "sv.State", block_qubits: int = 0, fuse: bool = False):
         ctx.block_qubits = block_qubits
         p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, circuit.n_params))
-        state.reset()
-        state.run(circuit, params=p if state.batch > 1 else p[0])
+        _forward(state, circuit, p if state.batch > 1 else p[0], fuse)
         z = state.expval_z_all()[:, : circuit.n]
         ctx.circuit = circuit
         ctx.state = state
@@ -105,7 +124,7 @@ class ExpvalZ(torch.autograd.Function):
         p = ctx.p if ctx.state.batch > 1 else ctx.p[0]
         _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, terms, params=p, coeff_rows=g, block_qubits=ctx.block_qubits)
         out = torch.from_numpy(grad.reshape(ctx.shape)).to(device=grad_z.device, dtype=grad_z.dtype)
-        return out, None, None, None
+        return out, None, None, None, None
 
 
 class MeasureAllZ(torch.nn.Module):
@@ -114,11 +133,12 @@ class MeasureAllZ(torch.nn.Module):
     adjoint backward (the appendix example's measure_allZ on an invertible
     device)."""
 
-    def __init__(self, circuit, batch: int = 1, device=None, block_qubits=None):
+    def __init__(self, circuit, batch: int = 1, device=None, block_qubits=None, fuse=None):
         super().__init__()
         self.circuit = circuit
         self.state = sv.State(circuit.n, batch, device=device)
         self.block_qubits = default_block_qubits(circuit) if block_qubits is None else block_qubits
+        self.fuse = default_fuse(circuit) if fuse is None else bool(fuse)
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
-        return ExpvalZ.apply(params, self.circuit, self.state, self.block_qubits)
+        return ExpvalZ.apply(params, self.circuit, self.state, self.block_qubits, self.fuse)

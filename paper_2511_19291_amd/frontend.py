@@ -36,7 +36,7 @@ import torch
 
 from . import circuits as C
 from . import sv
-from .autograd import ExpvalZ, default_block_qubits
+from .autograd import ExpvalZ, default_block_qubits, default_fuse
 
 # name -> (kind, number of controls, number of targets, number of angles)
 GATE_SCHEMA: Dict[str, Tuple[str, int, int, int]] = {
@@ -215,7 +215,7 @@ def measure_allZ(qdev: QuantumDevice, shots: int = 0, training: bool = True) -> 
     circ, mat = qdev._program()
     mat = mat.to(torch.float64)
     if shots == 0:
-        z = ExpvalZ.apply(mat, circ, qdev.state, default_block_qubits(circ))
+        z = ExpvalZ.apply(mat, circ, qdev.state, default_block_qubits(circ), default_fuse(circ))
         return z.to(qdev.device) if qdev.device.type == "cuda" else z
     if training:
         raise NotImplementedError("differentiable shot-noise estimates are not provided by this front end")

@@ -276,6 +276,35 @@ class State:
         check(lib().sv_run(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar))
         return self
 
+    def run_fused(self, circuit, params=None, max_k: int = 5, mode: int = None) -> "State":
+        """Apply the circuit with the gates whose angles are equal on every
+        row fused into blocks of <= max_k qubits (``fuse_plan``, then
+        ``apply_fused`` in ``mode``, FP32 MFMA by default); gates whose
+        angles differ between rows (an input encoding) run as per-gate
+        sweeps with per-row parameters. The gate order is kept: the circuit
+        is cut into maximal runs of row-shared and per-row gates."""
+        from .circuits import Circuit
+
+        if mode is None:
+            mode = FUSED_FP32_MFMA
+        p = np.asarray(circuit.params if params is None else params, dtype=np.float64)
+        rows = p.reshape(1, -1) if p.ndim == 1 else p
+        same = np.all(rows == rows[:1], axis=0) if rows.shape[1] else np.zeros(0, dtype=bool)
+        segs = []
+        for op in circuit.ops:
+            shared = all(bool(same[j]) for j in op.params)
+            if segs and segs[-1][0] == shared:
+                segs[-1][1].append(op)
+            else:
+                segs.append((shared, [op]))
+        for shared, ops in segs:
+            sub = Circuit(circuit.n, ops, rows[0])
+            if shared:
+                self.apply_fused(fuse_plan(sub, min(max_k, circuit.n), rows[0]), mode)
+            else:
+                self.run(sub, params=p)
+        return self
+
     def run_ops(self, table: "OpTable", start: int, count: int, params: np.ndarray) -> None:
         """Apply ``count`` ops of a prepared table from index ``start``
         (shared parameters)."""

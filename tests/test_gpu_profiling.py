@@ -56,12 +56,14 @@ def test_weighted_adjoint_vs_parameter_shift(sv, shared):
     assert np.all(drift < 1e-4)
 
 
-@pytest.mark.parametrize("block_qubits", [None, 0, 3, 5])
-def test_expvalz_forward_and_backward(sv, block_qubits):
-    """None: the default (blocked, 4 qubits); 0: the per-gate backward."""
-    n, B = 8, 3
+@pytest.mark.parametrize("block_qubits,n,fuse", [(None, 8, False), (0, 8, False), (3, 8, False), (5, 8, False),
+                                                 (None, 14, True)])
+def test_expvalz_forward_and_backward(sv, block_qubits, n, fuse):
+    """None: the default (blocked, 4 qubits); 0: the per-gate backward;
+    fuse: the fused forward (row-shared gates as matrix-core blocks)."""
+    B = 3
     circ, rows = C.profiling_ladder(n, 3, B, seed=4)
-    layer = MeasureAllZ(circ, B, block_qubits=block_qubits)
+    layer = MeasureAllZ(circ, B, block_qubits=block_qubits, fuse=fuse)
     x = torch.tensor(rows, dtype=torch.float64, requires_grad=True)
     z = layer(x)
     for r in range(B):
@@ -79,6 +81,31 @@ def test_expvalz_forward_and_backward(sv, block_qubits):
             fp = oracle.expval_terms(oracle.run(circ, params=pp), n, _zterms(n, w[r].numpy()))
             fm = oracle.expval_terms(oracle.run(circ, params=pm), n, _zterms(n, w[r].numpy()))
             assert abs(g[r, j] - (fp - fm) / (2 * h)) < 1e-4 * max(1.0, abs(g[r, j]))
+
+
+@pytest.mark.parametrize("shared", [True, False], ids=["shared_ansatz", "all_per_row"])
+def test_run_fused_forward(sv, shared):
+    """The fused forward of the autograd layers: gates whose angles are equal
+    on every row as 5-qubit matrix-core blocks, per-row gates (the input
+    encoding) as per-gate sweeps, in circuit order. Equal to the per-gate
+    forward (2e-6) and to the oracle (1e-5) row by row."""
+    n, B = 14, 3
+    circ, rows = C.profiling_ladder(n, 3, B, seed=11)
+    if not shared:
+        rows = rows + np.random.default_rng(12).uniform(-0.2, 0.2, size=rows.shape)
+    a = sv.State(n, B).reset().run(circ, params=rows).to_numpy()
+    b = sv.State(n, B).reset().run_fused(circ, params=rows).to_numpy()
+    assert np.max(np.abs(a - b)) < 2e-6
+    for r in range(B):
+        assert np.max(np.abs(b[r] - oracle.run(circ, params=rows[r]))) < 1e-5
+
+
+def test_run_fused_general_circuit(sv):
+    """run_fused on a circuit with two-qubit and controlled gates and shared
+    parameters (one fused sweep per block) vs the oracle."""
+    circ = C.random_circuit(13, 160, 21)
+    b = sv.State(13).reset().run_fused(circ).to_numpy()[0]
+    assert np.max(np.abs(b - oracle.run(circ))) < 1e-5
 
 
 def _cpu_adam_loop(circ, rows, steps, lr):
