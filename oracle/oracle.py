@@ -68,6 +68,10 @@ def bind(lib: C.CDLL) -> C.CDLL:
     lib.orc_sample_exact.restype = None
     lib.orc_sample_gaussian.argtypes = [dp, C.c_int, dp, C.c_double, dp]
     lib.orc_sample_gaussian.restype = None
+    lib.orc_gaussian_z.argtypes = [dp, C.c_int, dp, C.c_double, dp, dp]
+    lib.orc_gaussian_z.restype = None
+    lib.orc_gaussian_z_weights.argtypes = [dp, C.c_int, dp, C.c_double, dp, dp]
+    lib.orc_gaussian_z_weights.restype = None
     return lib
 
 
@@ -339,3 +343,28 @@ def sample_gaussian(psi: np.ndarray, n: int, normals: np.ndarray, shots: float) 
     y = np.empty(1 << n, dtype=np.float64)
     load().orc_sample_gaussian(_dptr(psi.view(np.float64)), n, _dptr(z), float(shots), _dptr(y))
     return y
+
+
+def gaussian_z(psi: np.ndarray, n: int, normals: np.ndarray, shots: float) -> np.ndarray:
+    """Gaussian shot estimate of every <Z_i> (Sec. 4.3.2): E_i = (1/shots)
+    sum_b y_b s_i(b), y the histogram of ``sample_gaussian``."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    z = np.ascontiguousarray(normals, dtype=np.float64)
+    assert len(z) == 1 << n
+    est = np.empty(n, dtype=np.float64)
+    work = np.empty(1 << n, dtype=np.float64)
+    load().orc_gaussian_z(_dptr(psi.view(np.float64)), n, _dptr(z), float(shots), _dptr(est), _dptr(work))
+    return est
+
+
+def gaussian_z_weights(psi: np.ndarray, n: int, normals: np.ndarray, shots: float, upstream) -> np.ndarray:
+    """dF/d|psi_b|^2 for F = sum_i upstream_i E_i (E from ``gaussian_z``,
+    the normals held fixed): the diagonal observable whose adjoint gives
+    dF/dtheta."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    z = np.ascontiguousarray(normals, dtype=np.float64)
+    g = np.ascontiguousarray(upstream, dtype=np.float64)
+    assert len(z) == 1 << n and len(g) == n
+    w = np.empty(1 << n, dtype=np.float64)
+    load().orc_gaussian_z_weights(_dptr(psi.view(np.float64)), n, _dptr(z), float(shots), _dptr(g), _dptr(w))
+    return w

@@ -401,3 +401,75 @@ void orc_sample_gaussian(const cplx* psi, int n, const double* z, double shots, 
         y[b] = shots * p + sqrt(shots) * u * (zb - 2.0 * v * vdotz);
     }
 }
+
+/* Gaussian estimate of every <Z_i> (Sec. 4.3.2): the histogram y of
+ * orc_sample_gaussian turned into E_i = (1/shots) sum_b y_b s_i(b) with
+ * s_i(b) = 1 - 2 (bit i of b), i.e. the Z_i eigenvalue of b. */
+void orc_gaussian_z(const cplx* psi, int n, const double* z, double shots, double* est, double* y_work)
+{
+    const int64_t N = (int64_t)1 << n;
+    orc_sample_gaussian(psi, n, z, shots, y_work);
+    for (int i = 0; i < n; ++i) {
+        neum a = {0, 0};
+        for (int64_t b = 0; b < N; ++b) neum_add(&a, ((b >> i) & 1) ? -y_work[b] : y_work[b]);
+        est[i] = neum_val(&a) / shots;
+    }
+}
+
+/* Derivative of F = sum_i g_i E_i with respect to the unnormalised
+ * probabilities q_b = |psi_b|^2, for fixed normals z (the reparameterised
+ * estimate of Sec. 4.3.2 is a smooth function of q). With T = sum q,
+ * p = q / T, u = sqrt p, d = e - u (e the last basis vector), R = ||d||^2,
+ * K = d . z, c_b = sum_i g_i s_i(b), Q = sum_b c_b u_b d_b:
+ *   F = sum_b c_b p_b + (1/sqrt shots) sum_b c_b u_b (S z)_b,
+ *   (S z)_b = z_b - 2 d_b K / R,
+ *   dF/dp_b = c_b + c_b K / (R sqrt shots)
+ *             + (c_b (S z)_b + 2 z_b Q / R - 4 d_b K Q / R^2) / (2 u_b sqrt shots)
+ *   (the last term taken as 0 where u_b = 0: the square root has no
+ *   derivative at 0), and dF/dq_b = (dF/dp_b - sum_b' p_b' dF/dp_b') / T. */
+void orc_gaussian_z_weights(const cplx* psi, int n, const double* z, double shots, const double* g, double* w)
+{
+    const int64_t N = (int64_t)1 << n;
+    neum tn = {0, 0};
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        neum_add(&tn, re * re + im * im);
+    }
+    const double T = neum_val(&tn);
+    const double sq = sqrt(shots);
+    neum rn = {0, 0}, kn = {0, 0}, qn = {0, 0};
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        const double u = sqrt((re * re + im * im) / T);
+        const double d = (b == N - 1 ? 1.0 : 0.0) - u;
+        const double zb = b < N - 1 ? z[b] : 0.0;
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += ((b >> i) & 1) ? -g[i] : g[i];
+        neum_add(&rn, d * d);
+        neum_add(&kn, d * zb);
+        neum_add(&qn, c * u * d);
+    }
+    const double R = neum_val(&rn), K = neum_val(&kn), Q = neum_val(&qn);
+    neum mn = {0, 0};
+    for (int64_t b = 0; b < N; ++b) {
+        const double re = creal(psi[b]), im = cimag(psi[b]);
+        const double p = (re * re + im * im) / T;
+        const double u = sqrt(p);
+        const double d = (b == N - 1 ? 1.0 : 0.0) - u;
+        const double zb = b < N - 1 ? z[b] : 0.0;
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += ((b >> i) & 1) ? -g[i] : g[i];
+        double wp = c;
+        if (R > 0.0) {
+            const double sz = zb - 2.0 * d * K / R;
+            wp += c * K / (R * sq);
+            if (u > 0.0) wp += (c * sz + 2.0 * zb * Q / R - 4.0 * d * K * Q / (R * R)) / (2.0 * u * sq);
+        } else if (u > 0.0) {
+            wp += c * zb / (2.0 * u * sq);   /* S = I when u = e */
+        }
+        w[b] = wp;
+        neum_add(&mn, p * wp);
+    }
+    const double M = neum_val(&mn);
+    for (int64_t b = 0; b < N; ++b) w[b] = (w[b] - M) / T;
+}

@@ -39,6 +39,11 @@ MUTANTS = {
     "reflection target": ("const double v = r > 0 ? ((b == N - 1 ? 1.0 : 0.0) - u) / r : 0.0;",
                           "const double v = r > 0 ? ((b == 0 ? 1.0 : 0.0) - u) / r : 0.0;"),
     "last normal kept": ("const double zb = b < N - 1 ? z[b] : 0.0;", "const double zb = z[b];"),
+    "weights reflection sign": ("- 4.0 * d * K * Q / (R * R)) / (2.0 * u * sq);",
+                                "+ 4.0 * d * K * Q / (R * R)) / (2.0 * u * sq);"),
+    "weights normalisation dropped": ("for (int64_t b = 0; b < N; ++b) w[b] = (w[b] - M) / T;",
+                                      "for (int64_t b = 0; b < N; ++b) w[b] = w[b] / T;"),
+    "weights sqrt derivative": ("Q / (R * R)) / (2.0 * u * sq);", "Q / (R * R)) / (u * sq);"),
 }
 
 
@@ -97,6 +102,17 @@ def _pins_pass() -> bool:
         want = 100.0 * pp + 10.0 * uu * ((np.eye(1 << n) - 2 * np.outer(vv, vv)) @ zz)
         if np.max(np.abs(oracle.sample_gaussian(psz, n, zs, 100.0) - want)) > 1e-9:
             return False
+        # the Gaussian estimate's weights vs central differences of the estimate
+        gz = rng.normal(size=n)
+        wz = oracle.gaussian_z_weights(psi, n, zs, 50.0, gz)
+        for b in range(1 << n):
+            q = abs(psi[b]) ** 2
+            pp, pm = psi.copy(), psi.copy()
+            pp[b] *= np.sqrt((q + 1e-7) / q)
+            pm[b] *= np.sqrt((q - 1e-7) / q)
+            fd = (np.dot(gz, oracle.gaussian_z(pp, n, zs, 50.0)) - np.dot(gz, oracle.gaussian_z(pm, n, zs, 50.0))) / 2e-7
+            if abs(fd - wz[b]) > 1e-5 * max(1.0, abs(wz[b])):
+                return False
         circ = C.rxry_ring(4, 2, 8)
         terms = C.z_sum_terms(4)
         g_fd = oracle.grad_finite_diff(circ, terms, h=1e-4)

@@ -151,3 +151,70 @@ def test_gaussian_moments_match_multinomial():
     sd = np.sqrt(np.diag(want_cov))
     assert np.all(np.abs(mean - shots * p) < 5 * sd / np.sqrt(40000) + 1e-9)
     assert np.max(np.abs(cov - want_cov)) < 0.05 * shots * p.max()
+
+
+# ---- the differentiable Gaussian estimate of every <Z_i> (Sec. 4.3.2 with
+# the normals held fixed: a smooth function of the probabilities)
+
+def test_gaussian_z_without_noise_is_the_exact_expectation():
+    """z = 0: y = shots p, so E_i is <Z_i> itself (the plain definition)."""
+    rng = np.random.default_rng(4)
+    n = 6
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    est = oracle.gaussian_z(psi, n, np.zeros(1 << n), 500.0)
+    want = [np.sum(np.abs(psi) ** 2 * (1 - 2 * ((np.arange(1 << n) >> i) & 1))) for i in range(n)]
+    np.testing.assert_allclose(est, want, atol=1e-14)
+
+
+def test_gaussian_z_is_the_histogram_read_out():
+    """E_i = (1/shots) sum_b y_b s_i(b) over the sampler's histogram."""
+    rng = np.random.default_rng(5)
+    n = 5
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    z = rng.normal(size=1 << n)
+    y = oracle.sample_gaussian(psi, n, z, 800.0)
+    sign = 1 - 2 * ((np.arange(1 << n)[:, None] >> np.arange(n)) & 1)
+    np.testing.assert_allclose(oracle.gaussian_z(psi, n, z, 800.0), y @ sign / 800.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,seed,shots", [(4, 1, 100.0), (5, 2, 1000.0), (6, 3, 1e5)])
+def test_gaussian_z_weights_are_the_derivative(n, seed, shots):
+    """The weights w_b = dF/d|psi_b|^2 (F = sum_i g_i E_i) against central
+    differences of the oracle's own estimate: |psi_b|^2 moved by +-h with the
+    phase kept (the step error is O(h^2); h = 1e-7)."""
+    rng = np.random.default_rng(seed)
+    N = 1 << n
+    psi = rng.normal(size=N) + 1j * rng.normal(size=N)
+    psi /= np.linalg.norm(psi)
+    z = rng.normal(size=N)
+    g = rng.normal(size=n)
+    w = oracle.gaussian_z_weights(psi, n, z, shots, g)
+
+    def F(ps):
+        return float(np.dot(g, oracle.gaussian_z(ps, n, z, shots)))
+
+    h = 1e-7
+    for b in range(N):
+        q = abs(psi[b]) ** 2
+        pp, pm = psi.copy(), psi.copy()
+        pp[b] *= np.sqrt((q + h) / q)
+        pm[b] *= np.sqrt((q - h) / q)
+        fd = (F(pp) - F(pm)) / (2 * h)
+        assert abs(fd - w[b]) < 1e-6 * max(1.0, abs(w[b])), (b, fd, w[b])
+
+
+def test_gaussian_z_weights_without_noise():
+    """z = 0: F = sum_b c_b p_b with p = q / T, so w_b = (c_b - F) / T with
+    c_b = sum_i g_i s_i(b) (T = 1 here)."""
+    rng = np.random.default_rng(6)
+    n = 5
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    g = rng.normal(size=n)
+    sign = 1 - 2 * ((np.arange(1 << n)[:, None] >> np.arange(n)) & 1)
+    c = sign @ g
+    F = float(np.sum(np.abs(psi) ** 2 * c))
+    w = oracle.gaussian_z_weights(psi, n, np.zeros(1 << n), 300.0, g)
+    np.testing.assert_allclose(w, c - F, atol=1e-12)
