@@ -315,6 +315,37 @@ sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64
 sv_status sv_sample_gaussian(sv_state s, int row, const double* dev_normals, double shots,
                              double* dev_y);
 
+/* Gaussian shot estimate of every <Z_i> of row `row` (Sec. 4.3.2): with y
+ * the histogram sv_sample_gaussian draws from the same normals,
+ * est_out[i] = (1/shots) sum_b y_b (1 - 2 bit_i(b)) (host, n doubles). y is
+ * not stored. Synchronous. Errors as sv_sample_gaussian. */
+sv_status sv_gaussian_expval_z(sv_state s, int row, const double* dev_normals, double shots, double* est_out);
+
+/* Backward of sv_gaussian_expval_z with the normals held fixed (the
+ * reparameterisation that makes the estimate differentiable): for
+ * F = sum_i upstream[i] E_i, dev_weights[b] = dF/d|psi_b|^2 (device, 2^n
+ * doubles), the diagonal observable for sv_adjoint_grad_diag. Where
+ * |psi_b| = 0 the term of dF/dp_b that divides by sqrt(p_b) is taken as 0
+ * (the square root has no derivative there). Asynchronous on the state's
+ * stream. upstream: host, n doubles. Errors as sv_sample_gaussian. */
+sv_status sv_gaussian_expval_z_backward(sv_state s, int row, const double* dev_normals, double shots,
+                                        const double* upstream, double* dev_weights);
+
+/* Adjoint gradient for a diagonal observable W = diag(w) given per
+ * amplitude (the backward of any function of the probabilities: with
+ * w_b = dF/d|psi_b|^2, dF/dtheta = 2 Re <W psi | dpsi/dtheta>, the adjoint
+ * recursion of Sec. 4.4 started from lambda = W psi). Used for the
+ * reparameterised shot-noise estimates of Sec. 4.3.2.
+ *   dev_weights: device doubles [batch][2^n], 8-byte aligned.
+ *   block_qubits: 0 = gate by gate (as sv_adjoint_grad), 3..5 = blocked (as
+ *     sv_adjoint_grad_blocked, with its restrictions on ops).
+ *   loss_out[r] = sum_b w_b |psi_b|^2. Other arguments, outputs and errors
+ *   as sv_adjoint_grad. */
+sv_status sv_adjoint_grad_diag(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                               int64_t params_batch_stride, int n_params, const double* dev_weights,
+                               int block_qubits, void* lambda_buffer, double* grad_out, double* loss_out,
+                               double* drift_out);
+
 /* -------------------------------------------------------------- batching */
 
 typedef struct sv_batch_plan_s* sv_batch_plan;

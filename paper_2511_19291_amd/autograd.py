@@ -142,3 +142,34 @@ class MeasureAllZ(torch.nn.Module):
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
         return ExpvalZ.apply(params, self.circuit, self.state, self.block_qubits, self.fuse)
+
+
+class GaussianExpvalZ(torch.autograd.Function):
+    """Shot-noise estimates of every <Z_i> (Sec. 4.3.2's Gaussian limit of the
+    multinomial), differentiable by reparameterisation: for fixed normals z
+    the estimate is a smooth function of the probabilities, so its backward
+    is the adjoint (Sec. 4.4) started from the diagonal observable
+    w_b = dF/d|psi_b|^2 that the library derives from the upstream gradient.
+    ``normals``: device float64 [batch, 2^n] (drawn by the caller)."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, circuit, state: "sv.State", normals: torch.Tensor, shots: float,
+                block_qubits: int = 0, fuse: bool = False):
+        p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, circuit.n_params))
+        _forward(state, circuit, p if state.batch > 1 else p[0], fuse)
+        est = np.stack([state.gaussian_expval_z(normals[r], shots, row=r) for r in range(state.batch)])
+        ctx.circuit, ctx.state, ctx.p, ctx.shape = circuit, state, p, params.shape
+        ctx.normals, ctx.shots, ctx.block_qubits = normals, shots, block_qubits
+        return torch.from_numpy(est).to(device=params.device, dtype=params.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_e: torch.Tensor):
+        st = ctx.state
+        g = np.ascontiguousarray(grad_e.detach().to("cpu", torch.float64).numpy().reshape(st.batch, ctx.circuit.n))
+        w = torch.empty((st.batch, 1 << st.n), dtype=torch.float64, device=st.tensor.device)
+        for r in range(st.batch):
+            st.gaussian_expval_z_backward(ctx.normals[r], ctx.shots, g[r], row=r, out=w[r])
+        p = ctx.p if st.batch > 1 else ctx.p[0]
+        _, grad, _ = st.adjoint_grad_diag(ctx.circuit, w, params=p, block_qubits=ctx.block_qubits)
+        out = torch.from_numpy(grad.reshape(ctx.shape)).to(device=grad_e.device, dtype=grad_e.dtype)
+        return out, None, None, None, None, None, None

@@ -268,6 +268,29 @@ void launch_adj_step(const AdjLaunch& g, double* part, hipStream_t st)
     SV_HIP(hipGetLastError());
 }
 
+// lambda = W psi for a diagonal observable W = diag(w) given per amplitude
+// (w: [rows][N] doubles), the product taken in FP64 and rounded once.
+__global__ __launch_bounds__(kBlock) void k_diag_lambda(Rows rp, Rows rl, uint64_t N, const double* __restrict__ w)
+{
+    const int row = blockIdx.y;
+    const float2* psi = mrow(rp, row);
+    float2* lam = mrow(rl, row);
+    const double* wr = w + (uint64_t)row * N;
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (uint64_t)gridDim.x * kBlock) {
+        const float2 v = psi[c];
+        const double f = wr[c];
+        lam[c] = make_float2((float)(f * v.x), (float)(f * v.y));
+    }
+}
+
+void launch_diag_lambda(const Rows& psi, const Rows& lam, int n, const double* w, hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    const uint64_t blocks = std::min<uint64_t>((N + kBlock - 1) / kBlock, (uint64_t)device_info().cu_count * 16);
+    hipLaunchKernelGGL(k_diag_lambda, dim3((unsigned)blocks, psi.nrows), dim3(kBlock), 0, st, psi, lam, N, w);
+    SV_HIP(hipGetLastError());
+}
+
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
                             const double* coeff_rows, hipStream_t st)
 {

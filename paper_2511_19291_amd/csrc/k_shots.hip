@@ -324,6 +324,180 @@ __global__ __launch_bounds__(kST) void k_gauss_y(const float2* __restrict__ psi,
     reinterpret_cast<double2*>(y)[i] = make_double2(out[0], out[1]);
 }
 
+// ---- Gaussian estimate of every <Z_i> and its backward (normals fixed).
+// With p = q / T (q_b = |psi_b|^2), u = sqrt p, d = e - u, R = ||d||^2,
+// K = d . z and y_b = shots p_b + sqrt(shots) u_b (z_b - 2 d_b K / R):
+//   E_i = (1/shots) sum_b y_b s_i(b),   s_i(b) = 1 - 2 (bit i of b);
+// for F = sum_i g_i E_i, c_b = sum_i g_i s_i(b), Q = sum_b c_b u_b d_b:
+//   dF/dp_b = c_b + c_b K / (R sqrt shots)
+//             + (c_b (S z)_b + 2 z_b Q / R - 4 d_b K Q / R^2) / (2 u_b sqrt shots)
+//   (that last term 0 where u_b = 0), and
+//   w_b = dF/dq_b = (dF/dp_b - sum_b' p_b' dF/dp_b') / T.
+// y is the sampler's (same formula, same rounding); every sum is FP64 in a
+// fixed order.
+
+struct GzArgs {
+    const float2* psi;
+    const double* z;
+    uint64_t N;
+    int n;
+    double shots;
+    double g[SV_MAX_QUBITS];
+    double G;                 // sum of g
+    const double* sc;         // [0] T, [1] r = sqrt R, [2] v . z (v = d / r), [3] Q, [4] M
+    double* part;
+    double* w;
+};
+
+// y_b of the sampler
+__device__ __forceinline__ double gz_y(double q, bool lastb, double zb, const double* sc, double shots, double sq)
+{
+    const double T = sc[0], r = sc[1], vz = sc[2];
+    const double p = q / T;
+    const double u = sqrt(p);
+    const double vb = r > 0.0 ? ((lastb ? 1.0 : 0.0) - u) / r : 0.0;
+    return shots * p + sq * u * (zb - 2.0 * vb * vz);
+}
+
+// c_b = G - 2 sum_{i: bit i of b} g_i from per-byte tables in LDS
+__device__ __forceinline__ double gz_c(const double (*tab)[256], int nt, double G, uint64_t b)
+{
+    double s = 0.0;
+    for (int j = 0; j < nt; ++j) s += tab[j][(b >> (8 * j)) & 255];
+    return G - 2.0 * s;
+}
+
+__device__ void gz_tables(const GzArgs& a, double (*tab)[256], int nt)
+{
+    for (int j = 0; j < nt; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 8 && 8 * j + k < a.n; ++k)
+            if ((threadIdx.x >> k) & 1) s += a.g[8 * j + k];
+        tab[j][threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// E partials: per workgroup sum_b y_b and sum_{bit i of b} y_b for every i
+__global__ __launch_bounds__(kST) void k_gz_est(GzArgs a)
+{
+    __shared__ double sh[kST / 64];
+    const double sq = sqrt(a.shots);
+    double tot = 0.0, acc[SV_MAX_QUBITS];
+#pragma unroll
+    for (int i = 0; i < SV_MAX_QUBITS; ++i) acc[i] = 0.0;
+    for (uint64_t j = (uint64_t)blockIdx.x * kST + threadIdx.x; j < a.N / 2; j += (uint64_t)gridDim.x * kST) {
+        const float4 v = reinterpret_cast<const float4*>(a.psi)[j];
+        const double2 zz = reinterpret_cast<const double2*>(a.z)[j];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint64_t b = 2 * j + h;
+            const bool lastb = b == a.N - 1;
+            const double y = gz_y(prob(h ? make_float2(v.z, v.w) : make_float2(v.x, v.y)), lastb,
+                                  lastb ? 0.0 : (h ? zz.y : zz.x), a.sc, a.shots, sq);
+            tot += y;
+#pragma unroll
+            for (int i = 0; i < SV_MAX_QUBITS; ++i)
+                if (i < a.n && ((b >> i) & 1)) acc[i] += y;
+        }
+    }
+    const int stride = a.n + 1;
+    const double st = wg_sum256(tot, sh);
+    if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * stride + a.n] = st;
+#pragma unroll
+    for (int i = 0; i < SV_MAX_QUBITS; ++i) {
+        if (i < a.n) {     // uniform: every thread takes the same branches around the barriers
+            const double si = wg_sum256(acc[i], sh);
+            if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * stride + i] = si;
+        }
+    }
+}
+
+// E_i = (tot - 2 acc_i) / shots from the partials, in workgroup order
+__global__ __launch_bounds__(kST) void k_gz_est_final(const double* __restrict__ part, int g, int n, double shots,
+                                                      double* __restrict__ est)
+{
+    __shared__ double sh[kST / 64];
+    const int stride = n + 1;
+    double tv = 0.0;
+    for (int k = threadIdx.x; k < g; k += kST) tv += part[(size_t)k * stride + n];
+    const double tot = wg_sum256(tv, sh);
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < g; k += kST) v += part[(size_t)k * stride + i];
+        const double si = wg_sum256(v, sh);
+        if (threadIdx.x == 0) est[i] = (tot - 2.0 * si) / shots;
+    }
+}
+
+// Q partials: sum_b c_b u_b d_b
+__global__ __launch_bounds__(kST) void k_gz_q(GzArgs a)
+{
+    __shared__ double sh[kST / 64];
+    __shared__ double tab[(SV_MAX_QUBITS + 7) / 8][256];
+    const int nt = (a.n + 7) / 8;
+    gz_tables(a, tab, nt);
+    const double T = a.sc[0];
+    double acc = 0.0;
+    for (uint64_t b = (uint64_t)blockIdx.x * kST + threadIdx.x; b < a.N; b += (uint64_t)gridDim.x * kST) {
+        const double u = sqrt(prob(a.psi[b]) / T);
+        const double d = (b == a.N - 1 ? 1.0 : 0.0) - u;
+        acc += gz_c(tab, nt, a.G, b) * u * d;
+    }
+    const double s = wg_sum256(acc, sh);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+// w'_b = dF/dp_b (written to w) and partials of M = sum_b p_b w'_b
+__global__ __launch_bounds__(kST) void k_gz_w(GzArgs a)
+{
+    __shared__ double sh[kST / 64];
+    __shared__ double tab[(SV_MAX_QUBITS + 7) / 8][256];
+    const int nt = (a.n + 7) / 8;
+    gz_tables(a, tab, nt);
+    const double T = a.sc[0], r = a.sc[1], Q = a.sc[3];
+    const double R = r * r, K = r * a.sc[2];
+    const double sq = sqrt(a.shots);
+    double acc = 0.0;
+    for (uint64_t b = (uint64_t)blockIdx.x * kST + threadIdx.x; b < a.N; b += (uint64_t)gridDim.x * kST) {
+        const bool lastb = b == a.N - 1;
+        const double p = prob(a.psi[b]) / T;
+        const double u = sqrt(p);
+        const double d = (lastb ? 1.0 : 0.0) - u;
+        const double zb = lastb ? 0.0 : a.z[b];
+        const double c = gz_c(tab, nt, a.G, b);
+        double wp = c;
+        if (R > 0.0) {
+            const double sz = zb - 2.0 * d * K / R;
+            wp += c * K / (R * sq);
+            if (u > 0.0) wp += (c * sz + 2.0 * zb * Q / R - 4.0 * d * K * Q / (R * R)) / (2.0 * u * sq);
+        } else if (u > 0.0) {
+            wp += c * zb / (2.0 * u * sq);
+        }
+        a.w[b] = wp;
+        acc += p * wp;
+    }
+    const double s = wg_sum256(acc, sh);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+// a scalar from g partials, in workgroup order
+__global__ __launch_bounds__(kST) void k_gz_scalar(const double* __restrict__ part, int g, double* __restrict__ out)
+{
+    __shared__ double sh[kST / 64];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < g; k += kST) v += part[k];
+    const double s = wg_sum256(v, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(kST) void k_gz_fix(double* __restrict__ w, uint64_t N, const double* __restrict__ sc)
+{
+    const double T = sc[0], M = sc[4];
+    for (uint64_t b = (uint64_t)blockIdx.x * kST + threadIdx.x; b < N; b += (uint64_t)gridDim.x * kST)
+        w[b] = (w[b] - M) / T;
+}
+
 template <class T>
 void scan_inclusive(T* x, uint64_t n, T* tmp, hipStream_t st)
 {
@@ -422,6 +596,87 @@ void launch_sample_gaussian(const GaussLaunch& a, hipStream_t st)
     SV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gauss_y, dim3((unsigned)((N / 2 + kST - 1) / kST)), dim3(kST), 0, st, a.psi, a.z, N, a.shots,
                        sc, a.y);
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace sv
+
+namespace sv {
+
+namespace {
+
+int gz_grid(uint64_t N)
+{
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((N / 2 + kST - 1) / kST, (uint64_t)device_info().cu_count * 8));
+}
+
+// scratch: [0, 2g) T and A partials; [2g, 2g + 8) scalars; then the
+// estimate partials (g (n + 1)) or the Q / M partials (g)
+GzArgs gz_args(const GaussZLaunch& a, int g)
+{
+    GzArgs x{};
+    x.psi = a.psi;
+    x.z = a.z;
+    x.N = 1ull << a.n;
+    x.n = a.n;
+    x.shots = a.shots;
+    x.G = 0.0;
+    for (int i = 0; i < a.n; ++i) {
+        x.g[i] = a.g[i];
+        x.G += a.g[i];
+    }
+    x.sc = a.scratch + 2 * g;
+    x.part = a.scratch + 2 * g + 8;
+    x.w = a.w;
+    return x;
+}
+
+void gz_scalars(const GaussZLaunch& a, int g, hipStream_t st)
+{
+    const uint64_t N = 1ull << a.n;
+    double* part = a.scratch;
+    double* sc = a.scratch + 2 * g;
+    hipLaunchKernelGGL(k_gauss_partial, dim3(g), dim3(kST), 0, st, a.psi, a.z, N, part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gauss_final, dim3(1), dim3(kST), 0, st, a.psi, N, part, g, sc);
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+uint64_t gauss_z_scratch_doubles(int n)
+{
+    const uint64_t g = (uint64_t)device_info().cu_count * 8;
+    return 2 * g + 8 + g * (uint64_t)(n + 1) + 8;
+}
+
+void launch_gauss_z(const GaussZLaunch& a, hipStream_t st)
+{
+    const int g = gz_grid(1ull << a.n);
+    gz_scalars(a, g, st);
+    const GzArgs x = gz_args(a, g);
+    hipLaunchKernelGGL(k_gz_est, dim3(g), dim3(kST), 0, st, x);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gz_est_final, dim3(1), dim3(kST), 0, st, x.part, g, a.n, a.shots, a.est);
+    SV_HIP(hipGetLastError());
+}
+
+void launch_gauss_z_backward(const GaussZLaunch& a, hipStream_t st)
+{
+    const uint64_t N = 1ull << a.n;
+    const int g = gz_grid(N);
+    gz_scalars(a, g, st);
+    const GzArgs x = gz_args(a, g);
+    double* sc = a.scratch + 2 * g;
+    hipLaunchKernelGGL(k_gz_q, dim3(g), dim3(kST), 0, st, x);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gz_scalar, dim3(1), dim3(kST), 0, st, x.part, g, sc + 3);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gz_w, dim3(g), dim3(kST), 0, st, x);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gz_scalar, dim3(1), dim3(kST), 0, st, x.part, g, sc + 4);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gz_fix, dim3(g), dim3(kST), 0, st, a.w, N, x.sc);
     SV_HIP(hipGetLastError());
 }
 

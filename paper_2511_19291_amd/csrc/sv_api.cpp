@@ -580,7 +580,8 @@ namespace {
 
 sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* params, int64_t params_batch_stride,
                        int n_params, const sv_pauli_term* obs, int n_obs, const double* coeff_rows,
-                       void* lambda_buffer, double* grad_out, double* loss_out, double* drift_out)
+                       void* lambda_buffer, double* grad_out, double* loss_out, double* drift_out,
+                       const double* diag_w = nullptr)
 {
     return guarded([&] {
         check_state(s);
@@ -588,7 +589,7 @@ sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* pa
         need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
         need(n_params == 0 || grad_out != nullptr, SV_ERR_INVALID_ARGUMENT, "grad_out is NULL");
         need(params_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative params stride");
-        check_terms(s->n, obs, n_obs);
+        if (!diag_w) check_terms(s->n, obs, n_obs);
         std::vector<OpInfo> info(n_ops);
         for (int i = 0; i < n_ops; ++i) info[i] = check_op(s->n, ops[i], n_params);
         check_not_capturing(s->stream);
@@ -599,7 +600,7 @@ sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* pa
         ensure_lambda(s, lambda_buffer, &lam);
         PauliTermDev* dterms = nullptr;
         const double* dcoeff = nullptr;
-        upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
+        if (!diag_w) upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
 
         // slots: one per (parameterised op, row, derivative)
         struct Slot { int row; int param; };
@@ -620,7 +621,8 @@ sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* pa
 
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
-        launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        if (diag_w) launch_diag_lambda(prow, lrow, s->n, diag_w, s->stream);
+        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
         const Rows both{s->psi, lam, B, 2 * B, s->N};
@@ -702,7 +704,7 @@ sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* pa
 sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const double* params,
                                int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
                                const double* coeff_rows, int lb, void* lambda_buffer, double* grad_out,
-                               double* loss_out, double* drift_out)
+                               double* loss_out, double* drift_out, const double* diag_w = nullptr)
 {
     return guarded([&] {
         check_state(s);
@@ -712,7 +714,7 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
         need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
         need(n_params == 0 || grad_out != nullptr, SV_ERR_INVALID_ARGUMENT, "grad_out is NULL");
         need(params_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative params stride");
-        check_terms(s->n, obs, n_obs);
+        if (!diag_w) check_terms(s->n, obs, n_obs);
         std::vector<OpInfo> info(n_ops);
         std::vector<uint64_t> masks(n_ops);
         for (int i = 0; i < n_ops; ++i) {
@@ -735,7 +737,7 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
         ensure_lambda(s, lambda_buffer, &lam);
         PauliTermDev* dterms = nullptr;
         const double* dcoeff = nullptr;
-        upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
+        if (!diag_w) upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
 
         // ---- plan on the host: launches (block, row set, gate range) and their gate tables
         struct Launch {
@@ -863,7 +865,8 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
 
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
-        launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        if (diag_w) launch_diag_lambda(prow, lrow, s->n, diag_w, s->stream);
+        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
         struct Slot { int row; int param; };
@@ -937,6 +940,22 @@ sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, cons
                         grad_out, loss_out, drift_out);
 }
 
+sv_status sv_adjoint_grad_diag(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                               int64_t params_batch_stride, int n_params, const double* dev_weights,
+                               int block_qubits, void* lambda_buffer, double* grad_out, double* loss_out,
+                               double* drift_out)
+{
+    if (dev_weights == nullptr) {
+        set_last_error("dev_weights is NULL");
+        return SV_ERR_INVALID_ARGUMENT;
+    }
+    if (block_qubits == 0)
+        return adjoint_impl(s, ops, n_ops, params, params_batch_stride, n_params, nullptr, 0, nullptr, lambda_buffer,
+                            grad_out, loss_out, drift_out, dev_weights);
+    return adjoint_blocked_impl(s, ops, n_ops, params, params_batch_stride, n_params, nullptr, 0, nullptr,
+                                block_qubits, lambda_buffer, grad_out, loss_out, drift_out, dev_weights);
+}
+
 sv_status sv_adjoint_grad_blocked(sv_state s, const sv_op* ops, int n_ops, const double* params,
                                   int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
                                   const double* coeff_rows, int block_qubits, void* lambda_buffer, double* grad_out,
@@ -985,6 +1004,58 @@ sv_status sv_sample_gaussian(sv_state s, int row, const double* dev_normals, dou
         a.y = dev_y;
         a.scratch = s->scratch;
         launch_sample_gaussian(a, s->stream);
+    });
+}
+
+namespace {
+
+GaussZLaunch gauss_z_launch(sv_state s, int row, const double* dev_normals, double shots)
+{
+    check_state(s);
+    need(row >= 0 && row < s->batch, SV_ERR_INVALID_ARGUMENT, "row out of range");
+    need(shots > 0 && std::isfinite(shots), SV_ERR_INVALID_ARGUMENT, "shots must be positive");
+    need(dev_normals != nullptr, SV_ERR_INVALID_ARGUMENT, "NULL device pointer");
+    need(((uintptr_t)dev_normals & 15) == 0, SV_ERR_INVALID_ARGUMENT, "device arrays must be 16-byte aligned");
+    ensure_scratch(s, gauss_z_scratch_doubles(s->n));
+    GaussZLaunch a{};
+    a.psi = s->psi + (uint64_t)row * s->N;
+    a.n = s->n;
+    a.z = dev_normals;
+    a.shots = shots;
+    a.scratch = s->scratch;
+    return a;
+}
+
+}  // namespace
+
+sv_status sv_gaussian_expval_z(sv_state s, int row, const double* dev_normals, double shots, double* est_out)
+{
+    return guarded([&] {
+        need(est_out != nullptr, SV_ERR_INVALID_ARGUMENT, "est_out is NULL");
+        GaussZLaunch a = gauss_z_launch(s, row, dev_normals, shots);
+        check_not_capturing(s->stream);
+        ensure_dout(s, (uint64_t)s->n);
+        a.est = s->dout;
+        launch_gauss_z(a, s->stream);
+        SV_HIP(hipMemcpyAsync(s->hout, s->dout, (size_t)s->n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        SV_HIP(hipStreamSynchronize(s->stream));
+        for (int i = 0; i < s->n; ++i) est_out[i] = s->hout[i];
+    });
+}
+
+sv_status sv_gaussian_expval_z_backward(sv_state s, int row, const double* dev_normals, double shots,
+                                        const double* upstream, double* dev_weights)
+{
+    return guarded([&] {
+        need(upstream != nullptr, SV_ERR_INVALID_ARGUMENT, "upstream is NULL");
+        need(dev_weights != nullptr, SV_ERR_INVALID_ARGUMENT, "dev_weights is NULL");
+        GaussZLaunch a = gauss_z_launch(s, row, dev_normals, shots);
+        for (int i = 0; i < s->n; ++i) {
+            need(std::isfinite(upstream[i]), SV_ERR_INVALID_ARGUMENT, "upstream values must be finite");
+            a.g[i] = upstream[i];
+        }
+        a.w = dev_weights;
+        launch_gauss_z_backward(a, s->stream);
     });
 }
 

@@ -116,6 +116,7 @@ struct PauliTermDev {
 // lam <- O psi, O = sum of terms (device array of nt terms). coeff_rows:
 // NULL, or device [rows][nt] coefficients (caller's term order) replacing
 // each term's coeff row by row.
+void launch_diag_lambda(const Rows& psi, const Rows& lam, int n, const double* w, hipStream_t st);
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
                             const double* coeff_rows, hipStream_t st);
 
@@ -141,6 +142,22 @@ struct GaussLaunch {
 };
 uint64_t gauss_scratch_doubles(int n);
 void launch_sample_gaussian(const GaussLaunch& a, hipStream_t st);
+
+// Gaussian estimate of every <Z_i> (E_i = (1/shots) sum_b y_b s_i(b)) and
+// its backward: w_b = dF/d|psi_b|^2 for F = sum_i g_i E_i, normals fixed.
+struct GaussZLaunch {
+    const float2* psi;        // one row
+    int n;
+    const double* z;          // device normals [2^n]
+    double shots;
+    double g[SV_MAX_QUBITS];  // upstream dF/dE_i (backward)
+    double* est;              // device [n] (forward)
+    double* w;                // device [2^n] (backward)
+    double* scratch;          // gauss_z_scratch_doubles(n) doubles
+};
+uint64_t gauss_z_scratch_doubles(int n);
+void launch_gauss_z(const GaussZLaunch& a, hipStream_t st);
+void launch_gauss_z_backward(const GaussZLaunch& a, hipStream_t st);
 
 // ------------------------------------------------------------ blocked adjoint
 // Block planning on qubit masks only (the fusion planners): per block its

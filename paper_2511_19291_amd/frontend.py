@@ -11,7 +11,8 @@ Sec. 3):
 
 plus ``GeneralEncoder`` (input features as rotation angles, one column per
 gate), ``InvertibleUnitary`` (a list of modules whose backward un-applies the
-gates, Sec. 4.4) and ``measure_allZ``.
+gates, Sec. 4.4) and ``measure_allZ`` (exact, or with shots: exact draws, or
+the differentiable Gaussian estimate in training).
 
 Execution model: a ``QuantumDevice`` records the gates applied to it since
 its last ``reset_states()`` together with their angle tensors (a scalar
@@ -36,7 +37,7 @@ import torch
 
 from . import circuits as C
 from . import sv
-from .autograd import ExpvalZ, default_block_qubits, default_fuse
+from .autograd import ExpvalZ, GaussianExpvalZ, default_block_qubits, default_fuse
 
 # name -> (kind, number of controls, number of targets, number of angles)
 GATE_SCHEMA: Dict[str, Tuple[str, int, int, int]] = {
@@ -203,22 +204,26 @@ class InvertibleUnitary(torch.nn.Module):
                 m(qdev)
 
 
-def measure_allZ(qdev: QuantumDevice, shots: int = 0, training: bool = True) -> torch.Tensor:
+def measure_allZ(qdev: QuantumDevice, shots: int = 0, training: bool = True, generator=None) -> torch.Tensor:
     """<Z_i> of every wire for every row, [bsz, n_wires].
 
     shots = 0: exact expectations (Sec. 2.2.1), differentiable through the
-    adjoint backward. shots > 0 and not training: estimates from exact shot
-    sampling (Sec. 4.3.1: inverse-CDF draws on the GPU), not differentiable.
-    The differentiable shot-noise estimate (the Gaussian reparameterisation of
-    Sec. 4.3.2 in training) is not provided by this front end; the library
-    draws it with sv_sample_gaussian."""
+    adjoint backward. shots > 0 and training: the Gaussian shot-noise
+    estimate (Sec. 4.3.2), differentiable by reparameterisation (normals
+    drawn here, with ``generator`` if given, and held fixed for the
+    backward). shots > 0 and not training: estimates from exact shot sampling
+    (Sec. 4.3.1: inverse-CDF draws on the GPU), not differentiable."""
     circ, mat = qdev._program()
     mat = mat.to(torch.float64)
     if shots == 0:
         z = ExpvalZ.apply(mat, circ, qdev.state, default_block_qubits(circ), default_fuse(circ))
         return z.to(qdev.device) if qdev.device.type == "cuda" else z
     if training:
-        raise NotImplementedError("differentiable shot-noise estimates are not provided by this front end")
+        normals = torch.randn((qdev.bsz, 1 << qdev.n_wires), dtype=torch.float64, device=qdev.device,
+                              generator=generator)
+        z = GaussianExpvalZ.apply(mat, circ, qdev.state, normals, float(shots), default_block_qubits(circ),
+                                  default_fuse(circ))
+        return z.to(qdev.device)
     with torch.no_grad():
         p = mat.detach().numpy()
         qdev.state.reset()

@@ -132,6 +132,9 @@ def lib() -> C.CDLL:
         "sv_stream_copy": [vp, vp, u64, vp],
         "sv_sample_exact": [vp, C.c_int, vp, i64, vp],
         "sv_sample_gaussian": [vp, C.c_int, vp, C.c_double, vp],
+        "sv_gaussian_expval_z": [vp, C.c_int, vp, C.c_double, dp],
+        "sv_gaussian_expval_z_backward": [vp, C.c_int, vp, C.c_double, dp, vp],
+        "sv_adjoint_grad_diag": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, vp, C.c_int, vp, dp, dp, dp],
         "sv_check_gate": [C.c_int, ip, C.c_int, ip, C.c_int],
     }
     for name, args in sig.items():
@@ -362,6 +365,50 @@ class State:
         check(lib().sv_sample_gaussian(self.h, row, C.c_void_p(z.data_ptr()), float(shots), C.c_void_p(y.data_ptr())))
         self._keep = z
         return y
+
+    def gaussian_expval_z(self, normals, shots: float, row: int = 0) -> np.ndarray:
+        """Gaussian shot estimate of every <Z_i> of one row (Sec. 4.3.2),
+        from device float64 normals of length 2^n: [n] on the host."""
+        import torch
+
+        z = torch.as_tensor(normals, dtype=torch.float64, device=self.tensor.device).contiguous()
+        assert z.numel() == 1 << self.n
+        est = np.empty(self.n, dtype=np.float64)
+        check(lib().sv_gaussian_expval_z(self.h, row, C.c_void_p(z.data_ptr()), float(shots), _dptr(est)))
+        return est
+
+    def gaussian_expval_z_backward(self, normals, shots: float, upstream, row: int = 0, out=None):
+        """dF/d|psi_b|^2 for F = sum_i upstream[i] E_i (the estimate of
+        ``gaussian_expval_z`` with the normals fixed): a device float64
+        tensor of length 2^n (written into ``out`` when given)."""
+        import torch
+
+        z = torch.as_tensor(normals, dtype=torch.float64, device=self.tensor.device).contiguous()
+        assert z.numel() == 1 << self.n
+        g = np.ascontiguousarray(np.asarray(upstream, dtype=np.float64).reshape(self.n))
+        w = out if out is not None else torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device)
+        assert w.dtype == torch.float64 and w.is_contiguous() and w.numel() == 1 << self.n
+        check(lib().sv_gaussian_expval_z_backward(self.h, row, C.c_void_p(z.data_ptr()), float(shots), _dptr(g),
+                                                  C.c_void_p(w.data_ptr())))
+        self._keep = z
+        return w
+
+    def adjoint_grad_diag(self, circuit, weights, params=None, block_qubits: int = 0,
+                          lambda_tensor=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """Adjoint gradient for the diagonal observable diag(weights), a
+        device float64 tensor [batch, 2^n]; returns (loss, grad, drift) as
+        ``adjoint_grad``."""
+        table = OpTable(circuit.ops)
+        p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
+        assert weights.is_contiguous() and weights.numel() == self.batch << self.n
+        grad = np.zeros((self.batch, max(npar, 1)), dtype=np.float64)
+        loss = np.zeros(self.batch, dtype=np.float64)
+        drift = np.zeros(self.batch, dtype=np.float64)
+        lam = C.c_void_p(lambda_tensor.data_ptr()) if lambda_tensor is not None else None
+        check(lib().sv_adjoint_grad_diag(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar,
+                                         C.c_void_p(weights.data_ptr()), block_qubits, lam, _dptr(grad), _dptr(loss),
+                                         _dptr(drift)))
+        return loss, grad[:, :npar], drift
 
     def adjoint_grad(self, circuit, terms: Sequence[Tuple[float, int, int]], params=None,
                      lambda_tensor=None, coeff_rows=None, block_qubits: int = 0) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:

@@ -123,7 +123,16 @@ def test_shot_estimates_and_refusals(sv):
     np.testing.assert_allclose(exact, np.cos(x.numpy()), atol=1e-6)
     est = F.measure_allZ(qdev, shots=200_000, training=False).cpu().numpy()
     assert np.max(np.abs(est - exact)) < 5 * 1 / np.sqrt(200_000) + 1e-9
-    with pytest.raises(NotImplementedError):
-        F.measure_allZ(qdev, shots=100, training=True)
+    # training: the Gaussian estimate, differentiable in the inputs
+    xg = x.clone().requires_grad_(True)
+    qdev.reset_states()
+    enc(qdev, xg)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    noisy = F.measure_allZ(qdev, shots=200_000, training=True, generator=gen)
+    assert np.max(np.abs(noisy.detach().cpu().numpy() - exact)) < 5 * 1 / np.sqrt(200_000) + 1e-9
+    noisy.sum().backward()
+    assert xg.grad is not None and np.all(np.isfinite(xg.grad.numpy()))
+    # d<Z_i>/dx_i = -sin(x_i) for the noise-free part; the noise adds O(1/sqrt(shots))
+    np.testing.assert_allclose(xg.grad.numpy(), -np.sin(x.numpy()), atol=0.05)
     with pytest.raises(ValueError):
         F.QuantumDevice(nq, world_sz=2)
