@@ -304,14 +304,14 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     bwd_ms = min(bwd_ms, (time.perf_counter() - t0) * 1e3)
     # blocked backward: one sweep per block of gates on 3, 4 or 5 qubits
     blocked = {}
-    for lb in (3, 4, 5):
+    for lb in (3, 4, 5, sv.ADJOINT_MFMA):
         st.reset()
         st.run_ops(table, 0, len(circ.ops), p)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         loss_b, grad_b, drift_b = st.adjoint_grad(circ, terms, block_qubits=lb)
         ms_b = (time.perf_counter() - t0) * 1e3
-        blocked[f"block{lb}"] = {"backward_ms": round(ms_b, 2), "backward_over_forward": round(ms_b / fwd_ms, 3),
+        blocked["mfma4" if lb == sv.ADJOINT_MFMA else f"block{lb}"] = {"backward_ms": round(ms_b, 2), "backward_over_forward": round(ms_b / fwd_ms, 3),
                                  "max_grad_diff_vs_per_gate": float(np.max(np.abs(grad_b[0] - grad[0]))),
                                  "drift": float(drift_b[0])}
     # the autograd layers' forward: row-shared gates fused into 5-qubit

@@ -331,6 +331,27 @@ sv_status sv_gaussian_expval_z(sv_state s, int row, const double* dev_normals, d
 sv_status sv_gaussian_expval_z_backward(sv_state s, int row, const double* dev_normals, double shots,
                                         const double* upstream, double* dev_weights);
 
+/* The blocked backward on the matrix cores (Sec. 4.4's recursion regrouped
+ * per block of gates on at most four qubits, taken from the last block).
+ * With psi and lambda after a block and, over every column c of the 16
+ * amplitudes that differ only in the block's qubits, the correlation
+ * S = sum_c psi_c lambda_c^*, gate k's derivative is 2 Re Tr(X_k S) with
+ * X_k = W_k (dG_k G_k^*) W_k^* (W_k the block's gates after k), and the
+ * vectors before the block are U_B^* psi, U_B^* lambda. One sweep per block
+ * computes S on FP64 matrix cores (the FP32 data's products exact, FP64
+ * sums) and the un-apply on FP32 matrix cores; X_k and the traces are FP64
+ * on the host. Any gate kind on at most four qubits (targets and controls).
+ * Needs n >= 9 (SV_ERR_UNSUPPORTED otherwise). Arguments, outputs and errors
+ * otherwise as sv_adjoint_grad_weighted (coeff_rows may be NULL). */
+sv_status sv_adjoint_grad_mfma(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                               int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                               const double* coeff_rows, void* lambda_buffer, double* grad_out, double* loss_out,
+                               double* drift_out);
+
+/* block_qubits value of sv_adjoint_grad_diag that selects the matrix-core
+ * backward of sv_adjoint_grad_mfma. */
+#define SV_ADJOINT_MFMA (-1)
+
 /* Adjoint gradient for a diagonal observable W = diag(w) given per
  * amplitude (the backward of any function of the probabilities: with
  * w_b = dF/d|psi_b|^2, dF/dtheta = 2 Re <W psi | dpsi/dtheta>, the adjoint
@@ -338,7 +359,8 @@ sv_status sv_gaussian_expval_z_backward(sv_state s, int row, const double* dev_n
  * reparameterised shot-noise estimates of Sec. 4.3.2.
  *   dev_weights: device doubles [batch][2^n], 8-byte aligned.
  *   block_qubits: 0 = gate by gate (as sv_adjoint_grad), 3..5 = blocked (as
- *     sv_adjoint_grad_blocked, with its restrictions on ops).
+ *     sv_adjoint_grad_blocked, with its restrictions on ops), SV_ADJOINT_MFMA
+ *     = the matrix-core backward (as sv_adjoint_grad_mfma).
  *   loss_out[r] = sum_b w_b |psi_b|^2. Other arguments, outputs and errors
  *   as sv_adjoint_grad. */
 sv_status sv_adjoint_grad_diag(sv_state s, const sv_op* ops, int n_ops, const double* params,

@@ -1,0 +1,211 @@
+// k_adj_mfma.hip -- the blocked adjoint backward on the matrix cores.
+//
+// For a block of gates acting inside four qubits (local bit i = qubit q[i],
+// ascending), the adjoint recursion of Sec. 4.4 regroups per block: with
+// psi, lambda the vectors after the block and, for every column c (the 16
+// amplitudes that differ only in the block's qubits), the block's
+// correlation
+//     S = sum_c psi_c lambda_c^*            (S[b][a] = sum_c psi_c[b] conj(lambda_c[a])),
+// the derivative of gate k in the block is 2 Re Tr(X_k S) with
+// X_k = W_k (dG_k G_k^*) W_k^* and W_k the block's gates after k (formed on
+// the host in FP64); the vectors before the block are U_B^* psi and
+// U_B^* lambda. One sweep per block therefore does two contractions:
+//   * S as a real 32 x 32 product X_psi X_lambda^T over all columns (rows
+//     0..15 the real parts, 16..31 the imaginary parts of a column), on
+//     FP64 matrix cores (v_mfma_f64_16x16x4_f64): the FP32 data's products
+//     are exact and the sums are FP64;
+//   * the un-apply y = U_B^* x for both vectors, as the real 32 x 32 product
+//     of [[Re M, -Im M], [Im M, Re M]] (M = U_B^*) with 32 columns at a time
+//     on FP32 matrix cores (v_mfma_f32_32x32x2_f32).
+// A wave takes 32 columns at a time; lane (h, u) (h = lane / 32) reads and
+// writes amplitudes 8h .. 8h+7 of column u. For the correlation the columns
+// are transposed through a per-wave LDS tile (the FP64 product wants a row
+// per lane). Each wave keeps its S in registers and writes it once; a
+// second kernel sums the waves' S in a fixed order (deterministic).
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kAmThreads = 256;
+constexpr int kAmWaves = kAmThreads / 64;
+constexpr int kTp = 33;            // LDS tile pitch (floats): [32 rows][33]
+
+__device__ __forceinline__ float2* am_row(const Rows& r, int row)
+{
+    return row < r.nrow0 ? r.p0 + (uint64_t)row * r.N : r.p1 + (uint64_t)(row - r.nrow0) * r.N;
+}
+
+__global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
+{
+    // the psi and lambda tiles of every wave; at the end the same memory holds
+    // the waves' S parts (4 x 1024 doubles = 32 KiB <= 2 x 4 x 32 x 33 floats)
+    __shared__ float tiles[2][kAmWaves][32][kTp];
+    static_assert(sizeof(tiles) >= kAmWaves * 1024 * sizeof(double), "S parts fit the tiles");
+    float (*tp)[32][kTp] = tiles[0];
+    float (*tl)[32][kTp] = tiles[1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int h = lane >> 5, cu = lane & 31;
+    const int row = blockIdx.y;
+    float2* psi = am_row(a.psi, row);
+    float2* lam = am_row(a.lam, row);
+    float fr[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) fr[s] = a.frag[lane * 16 + s];
+    const int q0 = a.q[0], q1 = a.q[1], q2 = a.q[2], q3 = a.q[3];
+    uint64_t offa[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        offa[t] = ((uint64_t)(t & 1) << q0) | ((uint64_t)((t >> 1) & 1) << q1) | ((uint64_t)((t >> 2) & 1) << q2) |
+                  ((uint64_t)h << q3);
+    f64x4 s00 = {0, 0, 0, 0}, s01 = {0, 0, 0, 0}, s10 = {0, 0, 0, 0}, s11 = {0, 0, 0, 0};
+    const uint64_t groups = a.N >> 9;          // 32 columns of 16 amplitudes
+    // the loop is uniform over the workgroup (barriers inside); a wave whose
+    // group is past the end works on zeros and stores nothing
+    for (uint64_t gb = (uint64_t)blockIdx.x * kAmWaves; gb < groups; gb += (uint64_t)gridDim.x * kAmWaves) {
+        const uint64_t grp = gb + w;
+        const bool valid = grp < groups;
+        uint64_t u = grp * 32 + cu;
+        u = ((u >> q0) << (q0 + 1)) | (u & ((1ull << q0) - 1));
+        u = ((u >> q1) << (q1 + 1)) | (u & ((1ull << q1) - 1));
+        u = ((u >> q2) << (q2 + 1)) | (u & ((1ull << q2) - 1));
+        u = ((u >> q3) << (q3 + 1)) | (u & ((1ull << q3) - 1));
+        float2 x[8], l[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            x[t] = valid ? psi[u | offa[t]] : make_float2(0.f, 0.f);
+            l[t] = valid ? lam[u | offa[t]] : make_float2(0.f, 0.f);
+        }
+        // transpose: tile row = real index (amplitude 8h + t: row 8h + t real,
+        // row 16 + 8h + t imaginary), tile column = column of the group
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            tp[w][8 * h + t][cu] = x[t].x;
+            tp[w][16 + 8 * h + t][cu] = x[t].y;
+            tl[w][8 * h + t][cu] = l[t].x;
+            tl[w][16 + 8 * h + t][cu] = l[t].y;
+        }
+        __syncthreads();
+        // S_real[16I + i][16J + j] += sum_k tp[16I + i][k] tl[16J + j][k]
+        // (A lane holds row lane % 16 of step column lane / 16)
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int kk = 4 * st + (lane >> 4), ii = lane & 15;
+            const double a0 = tp[w][ii][kk], a1 = tp[w][16 + ii][kk];
+            const double b0 = tl[w][ii][kk], b1 = tl[w][16 + ii][kk];
+            s00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, s00, 0, 0, 0);
+            s01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, s01, 0, 0, 0);
+            s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, s10, 0, 0, 0);
+            s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
+        }
+        __syncthreads();
+        // un-apply: y = M x for both vectors (step s: component s & 1 of
+        // amplitude 8h + (s >> 1); output register r: component r & 1 of
+        // amplitude 8h + (r >> 1))
+        f32x16 yp = {0}, yl = {0};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            yp = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? x[s >> 1].y : x[s >> 1].x, yp, 0, 0, 0);
+            yl = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? l[s >> 1].y : l[s >> 1].x, yl, 0, 0, 0);
+        }
+        if (valid) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                psi[u | offa[t]] = make_float2(yp[2 * t], yp[2 * t + 1]);
+                lam[u | offa[t]] = make_float2(yl[2 * t], yl[2 * t + 1]);
+            }
+        }
+    }
+    // the workgroup's S_real (32 x 32, row-major): the waves' parts summed in
+    // wave order through LDS (the tiles are free now); the FP64 product's
+    // output register r of lane l is row 4r + l / 16, column l % 16 of a
+    // 16 x 16 part
+    double* red = reinterpret_cast<double*>(&tiles[0][0][0][0]);    // [kAmWaves][1024]
+    const int col = lane & 15;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ri = 4 * r + (lane >> 4);
+        double* rw = red + w * 1024;
+        rw[ri * 32 + col] = s00[r];
+        rw[ri * 32 + 16 + col] = s01[r];
+        rw[(16 + ri) * 32 + col] = s10[r];
+        rw[(16 + ri) * 32 + 16 + col] = s11[r];
+    }
+    __syncthreads();
+    double* sp = a.spart + ((size_t)row * gridDim.x + blockIdx.x) * 1024;
+    for (int e = threadIdx.x; e < 1024; e += kAmThreads) {
+        double acc = red[e];
+#pragma unroll
+        for (int v = 1; v < kAmWaves; ++v) acc += red[v * 1024 + e];
+        sp[e] = acc;
+    }
+}
+
+// Two-level fixed-order sum of the workgroups' S_real: level 1, chunk c of
+// the workgroups (in order) per row; level 2, the chunks in order.
+constexpr int kAmChunks = 16;
+
+__global__ __launch_bounds__(kAmThreads) void k_adj_mfma_reduce1(const double* __restrict__ spart, int parts,
+                                                                 double* __restrict__ mid)
+{
+    const int c = blockIdx.x, row = blockIdx.y;
+    const int per = (parts + kAmChunks - 1) / kAmChunks;
+    const int p0 = c * per, p1 = min(parts, p0 + per);
+    const double* p = spart + (size_t)row * parts * 1024;
+    for (int e = threadIdx.x; e < 1024; e += kAmThreads) {
+        double acc = 0.0;
+        for (int v = p0; v < p1; ++v) acc += p[(size_t)v * 1024 + e];
+        mid[((size_t)row * kAmChunks + c) * 1024 + e] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kAmThreads) void k_adj_mfma_reduce2(const double* __restrict__ mid,
+                                                                 double* __restrict__ out)
+{
+    const int row = blockIdx.x;
+    for (int e = threadIdx.x; e < 1024; e += kAmThreads) {
+        double acc = 0.0;
+        for (int c = 0; c < kAmChunks; ++c) acc += mid[((size_t)row * kAmChunks + c) * 1024 + e];
+        out[(size_t)row * 1024 + e] = acc;
+    }
+}
+
+}  // namespace
+
+int adj_mfma_grid(int n)
+{
+    static int resident = 0;
+    if (resident == 0) {
+        int nb = 0;
+        SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_adj_mfma),
+                                                             kAmThreads, 0));
+        resident = std::max(nb, 1);
+    }
+    const uint64_t groups = (1ull << n) >> 9;
+    const uint64_t wgs = (groups + kAmWaves - 1) / kAmWaves;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(wgs, (uint64_t)device_info().cu_count * resident));
+}
+
+// doubles of the S parts for `rows` rows at `grid` workgroups per row
+uint64_t adj_mfma_part_doubles(int grid, int rows)
+{
+    return (uint64_t)rows * ((uint64_t)grid + kAmChunks) * 1024;
+}
+
+void launch_adj_mfma(const AdjMfmaLaunch& a, int rows, double* s_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_mfma, dim3(a.grid, rows), dim3(kAmThreads), 0, st, a);
+    SV_HIP(hipGetLastError());
+    double* mid = a.spart + (uint64_t)rows * a.grid * 1024;
+    hipLaunchKernelGGL(k_adj_mfma_reduce1, dim3(kAmChunks, rows), dim3(kAmThreads), 0, st, a.spart, a.grid, mid);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_adj_mfma_reduce2, dim3(rows), dim3(kAmThreads), 0, st, mid, s_out);
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace sv

@@ -917,6 +917,327 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
 
 }  // namespace
 
+namespace {
+
+// 16 x 16 embedding of a gate on a block's local bits: targets tl[0..k-1]
+// (tl[0] the most significant bit of m's index), controls cm; columns whose
+// control bits are not all 1 get the identity (id) or zero.
+void embed16(const cd* m, int k, const int* tl, int cm, bool id, cd* E)
+{
+    std::fill(E, E + 256, cd(0.0));
+    const int D = 1 << k;
+    for (int c = 0; c < 16; ++c) {
+        if ((c & cm) != cm) {
+            if (id) E[c * 16 + c] = 1.0;
+            continue;
+        }
+        int sin = 0, clr = c;
+        for (int t = 0; t < k; ++t) {
+            sin |= ((c >> tl[t]) & 1) << (k - 1 - t);
+            clr &= ~(1 << tl[t]);
+        }
+        for (int so = 0; so < D; ++so) {
+            int r = clr;
+            for (int t = 0; t < k; ++t)
+                if ((so >> (k - 1 - t)) & 1) r |= 1 << tl[t];
+            E[r * 16 + c] += m[so * D + sin];
+        }
+    }
+}
+
+// C = A B (16 x 16, row-major); complex products written out in real
+// arithmetic (the library's complex operator* keeps the C99 special-value
+// rules and is many times slower)
+void mm16(const cd* A, const cd* B, cd* C)
+{
+    for (int r = 0; r < 16; ++r)
+        for (int c = 0; c < 16; ++c) {
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < 16; ++j) {
+                const double ar = A[r * 16 + j].real(), ai = A[r * 16 + j].imag();
+                const double br = B[j * 16 + c].real(), bi = B[j * 16 + c].imag();
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+            }
+            C[r * 16 + c] = cd(re, im);
+        }
+}
+
+// C = A B^*
+void mm16_adj(const cd* A, const cd* B, cd* C)
+{
+    for (int r = 0; r < 16; ++r)
+        for (int c = 0; c < 16; ++c) {
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < 16; ++j) {
+                const double ar = A[r * 16 + j].real(), ai = A[r * 16 + j].imag();
+                const double br = B[c * 16 + j].real(), bi = -B[c * 16 + j].imag();
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+            }
+            C[r * 16 + c] = cd(re, im);
+        }
+}
+
+// Operand fragments of the real form [[Re M, -Im M], [Im M, Re M]] for the
+// FP32 product of k_adj_mfma: lane i + 32 (c >> 3), entry 2 (c & 7) + ci
+// holds row i (output component i & 1 of amplitude 8 ((i >> 2) & 1) +
+// 2 (i >> 3) + ((i >> 1) & 1)) against input column (amplitude c,
+// component ci).
+void mfma_fragments(const cd* M, float* frag)
+{
+    for (int c = 0; c < 16; ++c)
+        for (int i = 0; i < 32; ++i) {
+            const int jo = 8 * ((i >> 2) & 1) + 2 * (i >> 3) + ((i >> 1) & 1);
+            const cd e = M[jo * 16 + c];
+            for (int ci = 0; ci < 2; ++ci) {
+                const double v = (i & 1) == 0 ? (ci == 0 ? e.real() : -e.imag()) : (ci == 0 ? e.imag() : e.real());
+                frag[(i + 32 * (c >> 3)) * 16 + 2 * (c & 7) + ci] = (float)v;
+            }
+        }
+}
+
+// The blocked backward on the matrix cores (k_adj_mfma): blocks of gates on
+// at most four qubits; per block one sweep for the correlation S and the
+// un-apply, then each derivative as 2 Re Tr(X_k S) on the host.
+sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                            int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                            const double* coeff_rows, void* lambda_buffer, double* grad_out, double* loss_out,
+                            double* drift_out, const double* diag_w)
+{
+    return guarded([&] {
+        constexpr int lb = 4;
+        check_state(s);
+        need(s->n >= 9, SV_ERR_UNSUPPORTED, "the matrix-core adjoint needs at least 9 qubits");
+        need(n_ops >= 0 && (n_ops == 0 || ops != nullptr), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
+        need(n_params >= 0 && (n_params == 0 || params != nullptr), SV_ERR_INVALID_ARGUMENT, "params is NULL");
+        need(n_params == 0 || grad_out != nullptr, SV_ERR_INVALID_ARGUMENT, "grad_out is NULL");
+        need(params_batch_stride >= 0, SV_ERR_INVALID_ARGUMENT, "negative params stride");
+        if (!diag_w) check_terms(s->n, obs, n_obs);
+        std::vector<OpInfo> info(n_ops);
+        std::vector<uint64_t> masks(n_ops);
+        for (int i = 0; i < n_ops; ++i) {
+            const sv_op& op = ops[i];
+            info[i] = check_op(s->n, op, n_params);
+            for (int j = 0; j < info[i].k; ++j) masks[i] |= 1ull << op.targets[j];
+            for (int j = 0; j < op.n_controls; ++j) masks[i] |= 1ull << op.controls[j];
+            need(__builtin_popcountll(masks[i]) <= lb, SV_ERR_UNSUPPORTED,
+                 "op " + std::to_string(i) + " acts on more than four qubits");
+        }
+        check_not_capturing(s->stream);
+
+        const int B = s->batch;
+        const bool per_row = params_batch_stride != 0 && B > 1;
+        float2* lam = nullptr;
+        ensure_lambda(s, lambda_buffer, &lam);
+        PauliTermDev* dterms = nullptr;
+        const double* dcoeff = nullptr;
+        if (!diag_w) upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
+
+        // ---- plan on the host: one launch per block (per row where a gate's
+        // parameters differ between rows) and its fragments; the X_k are
+        // formed after the launches are queued, while the GPU sweeps
+        struct Deriv { int param; size_t x; };      // X_k at xs[x * 256]
+        struct Launch {
+            int row;
+            int q[4];
+            const GateBlock* gb;
+            std::vector<int> tl, cm;                 // local targets (2 per gate), control masks
+            size_t e_at;                             // E matrices of its gates at es[e_at]
+            std::vector<Deriv> d;
+        };
+        std::vector<Launch> launches;
+        std::vector<float> frags;
+        std::vector<cd> es, xs;
+        const std::vector<GateBlock> blocks = plan_gate_blocks(masks, lb);
+        std::vector<cd> U(256), T1(256), T2(256), W(256), G(256);
+        for (int bi = (int)blocks.size() - 1; bi >= 0; --bi) {
+            const GateBlock& gb = blocks[bi];
+            uint64_t used = 0;
+            for (int q : gb.qs) used |= 1ull << q;
+            for (int q = 0; q < s->n && __builtin_popcountll(used) < lb; ++q) used |= 1ull << q;
+            int lq[4], nq = 0;
+            for (int q = 0; q < s->n; ++q)
+                if ((used >> q) & 1) lq[nq++] = q;
+            auto local = [&](int q) {
+                for (int i = 0; i < lb; ++i)
+                    if (lq[i] == q) return i;
+                return -1;
+            };
+            bool rows_differ = false;
+            if (per_row)
+                for (int gi : gb.gates)
+                    if (info[gi].np > 0 && !same_params_all_rows(ops[gi], info[gi], params, params_batch_stride, B))
+                        rows_differ = true;
+            const int nrl = rows_differ ? B : 1;
+            const int ng = (int)gb.gates.size();
+            for (int rl = 0; rl < nrl; ++rl) {
+                const double* prow = params + (rows_differ ? rl * params_batch_stride : 0);
+                Launch L{};
+                L.row = rows_differ ? rl : -1;
+                for (int i = 0; i < 4; ++i) L.q[i] = lq[i];
+                L.gb = &gb;
+                L.tl.assign(ng * 2, 0);
+                L.cm.assign(ng, 0);
+                L.e_at = es.size();
+                es.resize(es.size() + (size_t)ng * 256);
+                for (int t = 0; t < ng; ++t) {
+                    const sv_op& op = ops[gb.gates[t]];
+                    const OpInfo& oi = info[gb.gates[t]];
+                    L.tl[2 * t] = local(op.targets[0]);
+                    L.tl[2 * t + 1] = oi.k == 2 ? local(op.targets[1]) : 0;
+                    for (int j = 0; j < op.n_controls; ++j) L.cm[t] |= 1 << local(op.controls[j]);
+                    cd m[16];
+                    op_matrix(op, oi, prow, m);
+                    embed16(m, oi.k, &L.tl[2 * t], L.cm[t], true, &es[L.e_at + (size_t)t * 256]);
+                }
+                // U_B = E_last ... E_first; the kernel applies M = U_B^*
+                for (int q = 0; q < 256; ++q) U[q] = (q % 17 == 0) ? 1.0 : 0.0;
+                for (int t = 0; t < ng; ++t) {
+                    mm16(&es[L.e_at + (size_t)t * 256], U.data(), T1.data());
+                    U.swap(T1);
+                }
+                for (int r = 0; r < 16; ++r)
+                    for (int c = 0; c < 16; ++c) T1[r * 16 + c] = std::conj(U[c * 16 + r]);
+                const size_t fo = frags.size();
+                frags.resize(fo + 1024);
+                mfma_fragments(T1.data(), &frags[fo]);
+                launches.push_back(std::move(L));
+            }
+        }
+        // X_k = W_k (dG_k G_k^*) W_k^*, W_k the gates after k (host, FP64)
+        auto form_derivatives = [&] {
+            for (Launch& L : launches) {
+                const GateBlock& gb = *L.gb;
+                const int ng = (int)gb.gates.size();
+                const double* prow = params + (L.row >= 0 ? L.row * params_batch_stride : 0);
+                for (int q = 0; q < 256; ++q) W[q] = (q % 17 == 0) ? 1.0 : 0.0;
+                for (int t = ng - 1; t >= 0; --t) {
+                    const int gi = gb.gates[t];
+                    const sv_op& op = ops[gi];
+                    const OpInfo& oi = info[gi];
+                    if (oi.np > 0) {
+                        const int D = 1 << oi.k;
+                        double prm[3];
+                        op_params(op, oi, prow, prm);
+                        cd m[16], md[16];
+                        op_matrix(op, oi, prow, m);
+                        dagger(oi.k, m, md);
+                        for (int d = 0; d < oi.np; ++d) {
+                            cd dm[16], g[16];
+                            kind_dmatrix(op.kind, prm, d, dm);
+                            for (int r = 0; r < D; ++r)
+                                for (int c = 0; c < D; ++c) {
+                                    double re = 0.0, im = 0.0;
+                                    for (int j = 0; j < D; ++j) {
+                                        const cd x = dm[r * D + j], y = md[j * D + c];
+                                        re += x.real() * y.real() - x.imag() * y.imag();
+                                        im += x.real() * y.imag() + x.imag() * y.real();
+                                    }
+                                    g[r * D + c] = cd(re, im);
+                                }
+                            embed16(g, oi.k, &L.tl[2 * t], L.cm[t], false, G.data());
+                            mm16(W.data(), G.data(), T1.data());
+                            mm16_adj(T1.data(), W.data(), T2.data());
+                            L.d.push_back(Deriv{op.param[d], xs.size() / 256});
+                            xs.insert(xs.end(), T2.begin(), T2.end());
+                        }
+                    }
+                    mm16(W.data(), &es[L.e_at + (size_t)t * 256], T1.data());
+                    W.swap(T1);
+                }
+            }
+        };
+
+        // ---- device buffers: fragments, the waves' S parts, S per launch and row
+        const int grid_full = adj_mfma_grid(s->n);
+        uint64_t spart_max = 1, s_total = 0;
+        for (const Launch& L : launches) {
+            const int rows_here = L.row < 0 ? B : 1;
+            const int grid = std::max(1, std::min(grid_full, (grid_full + rows_here - 1) / rows_here));
+            spart_max = std::max<uint64_t>(spart_max, adj_mfma_part_doubles(grid, rows_here));
+            s_total += (uint64_t)rows_here * 1024;
+        }
+        const uint64_t red = std::max<uint64_t>(inner_parts(s->n, B), drift_parts(s->n, B));
+        const uint64_t frag_doubles = (frags.size() + 1) / 2 + 2;
+        const uint64_t frag_at = (spart_max + red + 1) & ~1ull;
+        ensure_scratch(s, frag_at + frag_doubles);
+        double* spart = s->scratch;
+        double* rscratch = s->scratch + spart_max;
+        float* dfrag = reinterpret_cast<float*>(s->scratch + frag_at);
+        if (!frags.empty())
+            SV_HIP(hipMemcpyAsync(dfrag, frags.data(), frags.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
+        const uint64_t nout = std::max<uint64_t>(s_total, 1) + 3ull * B;
+        ensure_dout(s, nout + 2ull * B);
+        double* d_s = s->dout;
+        double* d_loss = s->dout + std::max<uint64_t>(s_total, 1);
+        double* d_drift = d_loss + 2ull * B;
+
+        const Rows prow{s->psi, s->psi, B, B, s->N};
+        const Rows lrow{lam, lam, B, B, s->N};
+        if (diag_w) launch_diag_lambda(prow, lrow, s->n, diag_w, s->stream);
+        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
+
+        uint64_t cur = 0;
+        for (size_t li = 0; li < launches.size(); ++li) {
+            const Launch& L = launches[li];
+            const int rows_here = L.row < 0 ? B : 1;
+            AdjMfmaLaunch a{};
+            if (L.row >= 0) {
+                a.psi = one_row(s, s->psi, L.row);
+                a.lam = one_row(s, lam, L.row);
+            } else {
+                a.psi = prow;
+                a.lam = lrow;
+            }
+            a.N = s->N;
+            for (int i = 0; i < 4; ++i) a.q[i] = L.q[i];
+            a.frag = dfrag + li * 1024;
+            a.spart = spart;
+            a.grid = std::max(1, std::min(grid_full, (grid_full + rows_here - 1) / rows_here));
+            launch_adj_mfma(a, rows_here, d_s + cur, s->stream);
+            cur += (uint64_t)rows_here * 1024;
+        }
+        launch_drift(prow, s->n, rscratch, d_drift, s->stream);
+        SV_HIP(hipMemcpyAsync(s->hout, s->dout, nout * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        form_derivatives();        // while the sweeps run
+        SV_HIP(hipStreamSynchronize(s->stream));
+        const double* h_s = s->hout;
+        const double* h_loss = s->hout + std::max<uint64_t>(s_total, 1);
+        const double* h_drift = h_loss + 2ull * B;
+        if (n_params > 0) std::fill(grad_out, grad_out + (size_t)B * n_params, 0.0);
+        // derivatives in launch (reverse block) order, then gate order
+        cur = 0;
+        std::vector<cd> S(256);
+        for (const Launch& L : launches) {
+            const int rows_here = L.row < 0 ? B : 1;
+            for (int r = 0; r < rows_here; ++r) {
+                const double* sr = h_s + cur + (uint64_t)r * 1024;     // S_real[32][32]
+                for (int b = 0; b < 16; ++b)
+                    for (int a2 = 0; a2 < 16; ++a2)
+                        S[b * 16 + a2] = cd(sr[b * 32 + a2] + sr[(16 + b) * 32 + 16 + a2],
+                                            sr[(16 + b) * 32 + a2] - sr[b * 32 + 16 + a2]);
+                const int row = L.row >= 0 ? L.row : r;
+                for (const Deriv& dv : L.d) {
+                    const cd* X = &xs[dv.x * 256];
+                    double tr = 0.0;       // Re Tr(X S)
+                    for (int a2 = 0; a2 < 16; ++a2)
+                        for (int b = 0; b < 16; ++b) tr += (X[a2 * 16 + b] * S[b * 16 + a2]).real();
+                    grad_out[(size_t)row * n_params + dv.param] += 2.0 * tr;
+                }
+            }
+            cur += (uint64_t)rows_here * 1024;
+        }
+        for (int r = 0; r < B; ++r) {
+            if (loss_out) loss_out[r] = h_loss[2 * r];
+            if (drift_out) drift_out[r] = std::sqrt(std::max(0.0, h_drift[r]));
+        }
+    });
+}
+
+}  // namespace
+
 extern "C" {
 
 sv_status sv_adjoint_grad(sv_state s, const sv_op* ops, int n_ops, const double* params,
@@ -940,6 +1261,15 @@ sv_status sv_adjoint_grad_weighted(sv_state s, const sv_op* ops, int n_ops, cons
                         grad_out, loss_out, drift_out);
 }
 
+sv_status sv_adjoint_grad_mfma(sv_state s, const sv_op* ops, int n_ops, const double* params,
+                               int64_t params_batch_stride, int n_params, const sv_pauli_term* obs, int n_obs,
+                               const double* coeff_rows, void* lambda_buffer, double* grad_out, double* loss_out,
+                               double* drift_out)
+{
+    return adjoint_mfma_impl(s, ops, n_ops, params, params_batch_stride, n_params, obs, n_obs, coeff_rows,
+                             lambda_buffer, grad_out, loss_out, drift_out, nullptr);
+}
+
 sv_status sv_adjoint_grad_diag(sv_state s, const sv_op* ops, int n_ops, const double* params,
                                int64_t params_batch_stride, int n_params, const double* dev_weights,
                                int block_qubits, void* lambda_buffer, double* grad_out, double* loss_out,
@@ -949,6 +1279,9 @@ sv_status sv_adjoint_grad_diag(sv_state s, const sv_op* ops, int n_ops, const do
         set_last_error("dev_weights is NULL");
         return SV_ERR_INVALID_ARGUMENT;
     }
+    if (block_qubits == SV_ADJOINT_MFMA)
+        return adjoint_mfma_impl(s, ops, n_ops, params, params_batch_stride, n_params, nullptr, 0, nullptr,
+                                 lambda_buffer, grad_out, loss_out, drift_out, dev_weights);
     if (block_qubits == 0)
         return adjoint_impl(s, ops, n_ops, params, params_batch_stride, n_params, nullptr, 0, nullptr, lambda_buffer,
                             grad_out, loss_out, drift_out, dev_weights);

@@ -159,6 +159,23 @@ uint64_t gauss_z_scratch_doubles(int n);
 void launch_gauss_z(const GaussZLaunch& a, hipStream_t st);
 void launch_gauss_z_backward(const GaussZLaunch& a, hipStream_t st);
 
+// ------------------------------------------------------ matrix-core adjoint
+// One sweep per block of gates on four qubits: the block's correlation
+// S = sum_c psi_c lambda_c^* (as S_real, 32 x 32 FP64 per row) and the
+// un-apply of the block's product from psi and lambda.
+struct AdjMfmaLaunch {
+    Rows psi;
+    Rows lam;
+    uint64_t N;
+    int q[4];                 // block qubits, ascending
+    const float* frag;        // 64 lanes x 16 floats: operands of [[Re M, -Im M], [Im M, Re M]], M = U_B^*
+    double* spart;            // adj_mfma_part_doubles(grid, rows): [rows][grid][1024], then the chunk sums
+    int grid;                 // workgroups per row
+};
+int adj_mfma_grid(int n);
+uint64_t adj_mfma_part_doubles(int grid, int rows);
+void launch_adj_mfma(const AdjMfmaLaunch& a, int rows, double* s_out, hipStream_t st);
+
 // ------------------------------------------------------------ blocked adjoint
 // Block planning on qubit masks only (the fusion planners): per block its
 // qubits and its gates (indices into the mask list, circuit order).

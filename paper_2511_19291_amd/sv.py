@@ -29,6 +29,7 @@ FLAG_CHECK_UNITARY = 2
 FUSED_FP32_MFMA = 0
 FUSED_BF16X3 = 1
 FUSED_VALU = 2
+ADJOINT_MFMA = -1          # block_qubits value: the matrix-core blocked backward
 BATCH_OUT_STRIDE = 32
 MAX_CONTROLS = 3
 
@@ -135,6 +136,8 @@ def lib() -> C.CDLL:
         "sv_gaussian_expval_z": [vp, C.c_int, vp, C.c_double, dp],
         "sv_gaussian_expval_z_backward": [vp, C.c_int, vp, C.c_double, dp, vp],
         "sv_adjoint_grad_diag": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, vp, C.c_int, vp, dp, dp, dp],
+        "sv_adjoint_grad_mfma": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm), C.c_int, dp,
+                                 vp, dp, dp, dp],
         "sv_check_gate": [C.c_int, ip, C.c_int, ip, C.c_int],
     }
     for name, args in sig.items():
@@ -415,8 +418,9 @@ class State:
         """The state must hold the forward output of ``circuit``. Returns
         (loss [batch], grad [batch, n_params], drift [batch]) and leaves the
         recomputed start state in the state. ``coeff_rows`` ([batch, n_terms])
-        replaces the terms' coefficients row by row. ``block_qubits`` 4 or 5
-        runs the blocked backward (one sweep per block of gates), 0 the
+        replaces the terms' coefficients row by row. ``block_qubits`` 3, 4 or
+        5 runs the blocked backward (one sweep per block of gates),
+        ``ADJOINT_MFMA`` the blocked backward on the matrix cores, 0 the
         per-gate one."""
         table = OpTable(circuit.ops)
         p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
@@ -425,7 +429,14 @@ class State:
         drift = np.zeros(self.batch, dtype=np.float64)
         lam = C.c_void_p(lambda_tensor.data_ptr()) if lambda_tensor is not None else None
         pp = _dptr(p) if npar else None
-        if block_qubits:
+        if block_qubits == ADJOINT_MFMA:
+            cr = None
+            if coeff_rows is not None:
+                cr = np.ascontiguousarray(np.asarray(coeff_rows, dtype=np.float64).reshape(self.batch, len(terms)))
+            check(lib().sv_adjoint_grad_mfma(self.h, table.ptr, table.n, pp, stride, npar, pauli_terms(terms),
+                                             len(terms), _dptr(cr) if cr is not None else None, lam, _dptr(grad),
+                                             _dptr(loss), _dptr(drift)))
+        elif block_qubits:
             cr = None
             if coeff_rows is not None:
                 cr = np.ascontiguousarray(np.asarray(coeff_rows, dtype=np.float64).reshape(self.batch, len(terms)))
