@@ -9,8 +9,9 @@ encoding) stay per-gate sweeps. Backward: the
 library un-applies the gates from the forward output (x = U^* y) and
 accumulates dL/dtheta in FP64; nothing is stored between the passes except
 the final state itself. By default the backward groups the gates into
-4-qubit blocks (one sweep per block, ``sv_adjoint_grad_blocked``) when every
-gate fits; ``block_qubits=0`` selects the per-gate backward. The state object therefore holds one pending
+4-qubit blocks (one sweep per block: ``sv_adjoint_grad_blocked`` from 14
+qubits, the matrix-core ``sv_adjoint_grad_mfma`` from 22) when every gate
+fits; ``block_qubits=0`` selects the per-gate backward. The state object therefore holds one pending
 forward at a time: run backward before the next forward on the same state.
 """
 
@@ -41,15 +42,25 @@ def _forward(state, circuit, p, fuse: bool) -> None:
         state.run(circuit, params=p)
 
 
+# Backward form by width (measured on one MI355X): below 14 qubits the
+# per-gate backward (launch-bound sizes), from 14 the 4-qubit VALU blocks,
+# from 22 the matrix-core blocks (their host planning and per-row launches
+# pay off only on large states).
+BLOCKED_MIN_QUBITS = 14
+MFMA_MIN_QUBITS = 22
+
+
 def default_block_qubits(circuit) -> int:
-    """Block width of the blocked adjoint backward for this circuit: 4 (the
-    fastest measured) when every gate fits in four qubits and n >= 4, else 0
-    (the per-gate backward)."""
-    if circuit.n < 4:
+    """Backward form for this circuit: ``sv.ADJOINT_MFMA`` (matrix-core
+    blocks) from 22 qubits when every gate fits in four qubits; 4 (VALU
+    blocks) from 14 qubits when every gate fits and the parameterised
+    two-target gates are Pauli rotations; else 0 (per gate)."""
+    fits = all(len(op.targets) + len(op.controls) <= 4 for op in circuit.ops)
+    if not fits or circuit.n < BLOCKED_MIN_QUBITS:
         return 0
+    if circuit.n >= MFMA_MIN_QUBITS:
+        return sv.ADJOINT_MFMA
     for op in circuit.ops:
-        if len(op.targets) + len(op.controls) > 4:
-            return 0
         if len(op.targets) == 2 and op.params and op.kind not in ("rxx", "ryy", "rzz"):
             return 0
     return 4

@@ -36,6 +36,17 @@ constexpr int kAmThreads = 256;
 constexpr int kAmWaves = kAmThreads / 64;
 constexpr int kTp = 33;            // LDS tile pitch (floats): [32 rows][33]
 
+// A wave's own LDS writes complete before its following reads (and its
+// reads before its following writes): wait for the LDS counter and keep the
+// compiler from moving LDS accesses across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float2* am_row(const Rows& r, int row)
 {
     return row < r.nrow0 ? r.p0 + (uint64_t)row * r.N : r.p1 + (uint64_t)(row - r.nrow0) * r.N;
@@ -65,21 +76,37 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
                   ((uint64_t)h << q3);
     f64x4 s00 = {0, 0, 0, 0}, s01 = {0, 0, 0, 0}, s10 = {0, 0, 0, 0}, s11 = {0, 0, 0, 0};
     const uint64_t groups = a.N >> 9;          // 32 columns of 16 amplitudes
-    // the loop is uniform over the workgroup (barriers inside); a wave whose
-    // group is past the end works on zeros and stores nothing
-    for (uint64_t gb = (uint64_t)blockIdx.x * kAmWaves; gb < groups; gb += (uint64_t)gridDim.x * kAmWaves) {
-        const uint64_t grp = gb + w;
-        const bool valid = grp < groups;
+    const uint64_t stride = (uint64_t)gridDim.x * kAmWaves;
+    // column base of a group for this lane (zeros at the block's qubits)
+    auto column = [&](uint64_t grp) {
         uint64_t u = grp * 32 + cu;
         u = ((u >> q0) << (q0 + 1)) | (u & ((1ull << q0) - 1));
         u = ((u >> q1) << (q1 + 1)) | (u & ((1ull << q1) - 1));
         u = ((u >> q2) << (q2 + 1)) | (u & ((1ull << q2) - 1));
-        u = ((u >> q3) << (q3 + 1)) | (u & ((1ull << q3) - 1));
-        float2 x[8], l[8];
+        return ((u >> q3) << (q3 + 1)) | (u & ((1ull << q3) - 1));
+    };
+    // the next group's columns are loaded while this group's products run;
+    // each wave works through its own groups (its LDS tiles are its own, so
+    // only the wave itself has to be in step between writing and reading them)
+    float2 x[8], l[8];
+    uint64_t grp = (uint64_t)blockIdx.x * kAmWaves + w;
+    {
+        const uint64_t u0 = column(grp);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            x[t] = valid ? psi[u | offa[t]] : make_float2(0.f, 0.f);
-            l[t] = valid ? lam[u | offa[t]] : make_float2(0.f, 0.f);
+            x[t] = grp < groups ? psi[u0 | offa[t]] : make_float2(0.f, 0.f);
+            l[t] = grp < groups ? lam[u0 | offa[t]] : make_float2(0.f, 0.f);
+        }
+    }
+    for (; grp < groups; grp += stride) {
+        const uint64_t u = column(grp);
+        const uint64_t gn = grp + stride;
+        const uint64_t un = column(gn);
+        float2 xn[8], ln[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            xn[t] = gn < groups ? psi[un | offa[t]] : make_float2(0.f, 0.f);
+            ln[t] = gn < groups ? lam[un | offa[t]] : make_float2(0.f, 0.f);
         }
         // transpose: tile row = real index (amplitude 8h + t: row 8h + t real,
         // row 16 + 8h + t imaginary), tile column = column of the group
@@ -90,7 +117,7 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             tl[w][8 * h + t][cu] = l[t].x;
             tl[w][16 + 8 * h + t][cu] = l[t].y;
         }
-        __syncthreads();
+        wave_lds_sync();
         // S_real[16I + i][16J + j] += sum_k tp[16I + i][k] tl[16J + j][k]
         // (A lane holds row lane % 16 of step column lane / 16)
 #pragma unroll
@@ -103,7 +130,7 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, s10, 0, 0, 0);
             s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
         }
-        __syncthreads();
+        wave_lds_sync();
         // un-apply: y = M x for both vectors (step s: component s & 1 of
         // amplitude 8h + (s >> 1); output register r: component r & 1 of
         // amplitude 8h + (r >> 1))
@@ -113,18 +140,22 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             yp = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? x[s >> 1].y : x[s >> 1].x, yp, 0, 0, 0);
             yl = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? l[s >> 1].y : l[s >> 1].x, yl, 0, 0, 0);
         }
-        if (valid) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                psi[u | offa[t]] = make_float2(yp[2 * t], yp[2 * t + 1]);
-                lam[u | offa[t]] = make_float2(yl[2 * t], yl[2 * t + 1]);
-            }
+        for (int t = 0; t < 8; ++t) {
+            psi[u | offa[t]] = make_float2(yp[2 * t], yp[2 * t + 1]);
+            lam[u | offa[t]] = make_float2(yl[2 * t], yl[2 * t + 1]);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            x[t] = xn[t];
+            l[t] = ln[t];
         }
     }
     // the workgroup's S_real (32 x 32, row-major): the waves' parts summed in
     // wave order through LDS (the tiles are free now); the FP64 product's
     // output register r of lane l is row 4r + l / 16, column l % 16 of a
     // 16 x 16 part
+    __syncthreads();       // every wave is done with its tiles
     double* red = reinterpret_cast<double*>(&tiles[0][0][0][0]);    // [kAmWaves][1024]
     const int col = lane & 15;
 #pragma unroll

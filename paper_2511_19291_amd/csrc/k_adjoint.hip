@@ -187,13 +187,13 @@ __global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t
         double re = 0.0, im = 0.0;
         int t = 0;
         while (t < nt) {
-            const uint64_t xm = terms[t].x_mask;
+            const uint64_t xm = ld_const(&terms[t].x_mask);
             const uint64_t src = c ^ xm;
             const float2 v = psi[src];
             double fr = 0.0, fi = 0.0;       // sum of coeff * sign * i^y over the terms of this x_mask
-            for (; t < nt && terms[t].x_mask == xm; ++t) {
-                const PauliTermDev tm = terms[t];
-                const double cf = crow ? crow[tm.orig] : tm.coeff;
+            for (; t < nt && ld_const(&terms[t].x_mask) == xm; ++t) {
+                const PauliTermDev tm = ld_const(terms + t);     // uniform: the scalar cache
+                const double cf = crow ? ld_const(crow + tm.orig) : tm.coeff;
                 const double sg = (__popcll(src & tm.z_mask) & 1) ? -cf : cf;
                 switch (tm.y_count & 3) {
                 case 0: fr += sg; break;

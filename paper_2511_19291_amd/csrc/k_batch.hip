@@ -246,21 +246,6 @@ __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a)
     if (i == 0) *a.counter = 0;
 }
 
-// Load of a launch table entry at a uniform address through the scalar
-// cache: the task, circuit, pass and phase tables are read-only while the
-// persistent kernel runs, so they may be read as constant memory.
-template <class T>
-__device__ __forceinline__ T ld_const(const T* p)
-{
-    static_assert(sizeof(T) % 4 == 0, "whole words");
-    typedef const __attribute__((address_space(4))) uint32_t cword;
-    const cword* q = (const cword*)p;
-    uint32_t w[sizeof(T) / 4];
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
-    return __builtin_bit_cast(T, w);
-}
-
 __device__ __forceinline__ uint32_t ins0(uint32_t g, const int* pos, int np)
 {
     for (int i = 0; i < np; ++i) {

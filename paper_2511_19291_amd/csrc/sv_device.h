@@ -21,6 +21,21 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const int* pos, int
     return g;
 }
 
+// Load of a table entry at a uniform address through the scalar cache: for
+// tables that stay read-only while the kernel runs (launch tables, Pauli
+// terms), read as constant memory, a word at a time.
+template <class T>
+__device__ __forceinline__ T ld_const(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    typedef const __attribute__((address_space(4))) uint32_t cword;
+    const cword* q = (const cword*)p;
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+    return __builtin_bit_cast(T, w);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
