@@ -177,12 +177,49 @@ __global__ __launch_bounds__(kBlock) void k_adj(KAdj a, double* part)
 // distinct x_mask reads psi[c ^ x] once and applies the summed factor of its
 // terms.
 __global__ __launch_bounds__(kBlock) void k_pauli_sum(Rows rp, Rows rl, uint64_t N, const PauliTermDev* terms, int nt,
-                                                   const double* coeff_rows)
+                                                   const double* coeff_rows, int zonly, int n)
 {
     const int row = blockIdx.y;
     const double* crow = coeff_rows ? coeff_rows + (uint64_t)row * nt : nullptr;
     const float2* psi = mrow(rp, row);
     float2* lam = mrow(rl, row);
+    if (zonly) {
+        // every term is c Z_q: lambda_b = (G - 2 sum_{q: bit q of b} c_q) psi_b
+        // with c_q summed per qubit (in term order) and per-byte tables of
+        // the sums in LDS, so an amplitude takes one lookup per 8 qubits
+        __shared__ double cq[64];
+        __shared__ double tab[8][256];
+        __shared__ double gsum;
+        if (threadIdx.x == 0) {
+            for (int q = 0; q < 64; ++q) cq[q] = 0.0;
+            double g = 0.0;
+            for (int t = 0; t < nt; ++t) {
+                const PauliTermDev tm = terms[t];
+                const double cf = crow ? crow[tm.orig] : tm.coeff;
+                cq[__builtin_ctzll(tm.z_mask)] += cf;
+                g += cf;
+            }
+            gsum = g;
+        }
+        __syncthreads();
+        const int nb = (n + 7) / 8;
+        for (int j = 0; j < nb; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 8; ++k)
+                if ((threadIdx.x >> k) & 1) v += cq[8 * j + k];
+            tab[j][threadIdx.x] = v;
+        }
+        __syncthreads();
+        const double G = gsum;
+        for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (uint64_t)gridDim.x * kBlock) {
+            double sb = 0.0;
+            for (int j = 0; j < nb; ++j) sb += tab[j][(c >> (8 * j)) & 255];
+            const double f = G - 2.0 * sb;
+            const float2 v = psi[c];
+            lam[c] = make_float2((float)(f * v.x), (float)(f * v.y));
+        }
+        return;
+    }
     for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < N; c += (uint64_t)gridDim.x * kBlock) {
         double re = 0.0, im = 0.0;
         int t = 0;
@@ -292,12 +329,12 @@ void launch_diag_lambda(const Rows& psi, const Rows& lam, int n, const double* w
 }
 
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
-                            const double* coeff_rows, hipStream_t st)
+                            const double* coeff_rows, hipStream_t st, bool zonly)
 {
     const uint64_t N = 1ull << n;
     const uint64_t blocks = std::min<uint64_t>((N + kBlock - 1) / kBlock, (uint64_t)device_info().cu_count * 16);
     hipLaunchKernelGGL(k_pauli_sum, dim3((unsigned)blocks, psi.nrows), dim3(kBlock), 0, st, psi, lam, N, terms, nt,
-                       coeff_rows);
+                       coeff_rows, zonly ? 1 : 0, n);
     SV_HIP(hipGetLastError());
 }
 

@@ -301,6 +301,14 @@ void ensure_lambda(sv_state s, void* user, float2** lam)
 
 // Terms (and optional per-row coefficients, [rows][n_obs] in the caller's
 // term order) to device memory kept in the state.
+// every term a single-qubit Z (sum_q c_q Z_q): the observable kernel's table path
+bool z_only_terms(const sv_pauli_term* obs, int n_obs)
+{
+    for (int i = 0; i < n_obs; ++i)
+        if (obs[i].x_mask != 0 || __builtin_popcountll(obs[i].z_mask) != 1) return false;
+    return n_obs > 0;
+}
+
 void upload_terms(sv_state s, const sv_pauli_term* obs, int n_obs, const double* coeff_rows, int rows,
                   PauliTermDev** out, const double** dcoeff)
 {
@@ -622,7 +630,7 @@ sv_status adjoint_impl(sv_state s, const sv_op* ops, int n_ops, const double* pa
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
         if (diag_w) launch_diag_lambda(prow, lrow, s->n, diag_w, s->stream);
-        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream, z_only_terms(obs, n_obs));
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
         const Rows both{s->psi, lam, B, 2 * B, s->N};
@@ -866,7 +874,7 @@ sv_status adjoint_blocked_impl(sv_state s, const sv_op* ops, int n_ops, const do
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
         if (diag_w) launch_diag_lambda(prow, lrow, s->n, diag_w, s->stream);
-        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream, z_only_terms(obs, n_obs));
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
         struct Slot { int row; int param; };
@@ -1176,7 +1184,7 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
         if (diag_w) launch_diag_lambda(prow, lrow, s->n, diag_w, s->stream);
-        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream);
+        else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream, z_only_terms(obs, n_obs));
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
         uint64_t cur = 0;

@@ -115,10 +115,12 @@ struct PauliTermDev {
 };
 // lam <- O psi, O = sum of terms (device array of nt terms). coeff_rows:
 // NULL, or device [rows][nt] coefficients (caller's term order) replacing
-// each term's coeff row by row.
+// each term's coeff row by row. zonly: every term is a single-qubit Z (the
+// table path).
 void launch_diag_lambda(const Rows& psi, const Rows& lam, int n, const double* w, hipStream_t st);
 void launch_apply_pauli_sum(const Rows& psi, const Rows& lam, int n, const PauliTermDev* terms, int nt,
-                            const double* coeff_rows, hipStream_t st);
+                            const double* coeff_rows, hipStream_t st,
+                            bool zonly = false);
 
 // ------------------------------------------------------------ shots
 struct ShotLaunch {
