@@ -52,6 +52,13 @@ __device__ __forceinline__ float2* am_row(const Rows& r, int row)
     return row < r.nrow0 ? r.p0 + (uint64_t)row * r.N : r.p1 + (uint64_t)(row - r.nrow0) * r.N;
 }
 
+// COAL: a block qubit below 5. Consecutive columns are then up to 128 B
+// apart, so the group's 512 amplitudes move in memory order instead: the
+// group's nine varying address bits (the block's qubits and the five lowest
+// other qubits) then include bits 0..5, so each load or store of the wave
+// covers 512 contiguous bytes; the per-wave LDS tiles convert between
+// memory order and the lane layout of the products.
+template <bool COAL>
 __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
 {
     // the psi and lambda tiles of every wave; at the end the same memory holds
@@ -69,57 +76,20 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
 #pragma unroll
     for (int s = 0; s < 16; ++s) fr[s] = a.frag[lane * 16 + s];
     const int q0 = a.q[0], q1 = a.q[1], q2 = a.q[2], q3 = a.q[3];
-    uint64_t offa[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-        offa[t] = ((uint64_t)(t & 1) << q0) | ((uint64_t)((t >> 1) & 1) << q1) | ((uint64_t)((t >> 2) & 1) << q2) |
-                  ((uint64_t)h << q3);
     f64x4 s00 = {0, 0, 0, 0}, s01 = {0, 0, 0, 0}, s10 = {0, 0, 0, 0}, s11 = {0, 0, 0, 0};
     const uint64_t groups = a.N >> 9;          // 32 columns of 16 amplitudes
     const uint64_t stride = (uint64_t)gridDim.x * kAmWaves;
-    // column base of a group for this lane (zeros at the block's qubits)
-    auto column = [&](uint64_t grp) {
-        uint64_t u = grp * 32 + cu;
+    // column base of a group for column c (zeros at the block's qubits)
+    auto column = [&](uint64_t grp, int c) {
+        uint64_t u = grp * 32 + c;
         u = ((u >> q0) << (q0 + 1)) | (u & ((1ull << q0) - 1));
         u = ((u >> q1) << (q1 + 1)) | (u & ((1ull << q1) - 1));
         u = ((u >> q2) << (q2 + 1)) | (u & ((1ull << q2) - 1));
         return ((u >> q3) << (q3 + 1)) | (u & ((1ull << q3) - 1));
     };
-    // the next group's columns are loaded while this group's products run;
-    // each wave works through its own groups (its LDS tiles are its own, so
-    // only the wave itself has to be in step between writing and reading them)
-    float2 x[8], l[8];
-    uint64_t grp = (uint64_t)blockIdx.x * kAmWaves + w;
-    {
-        const uint64_t u0 = column(grp);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            x[t] = grp < groups ? psi[u0 | offa[t]] : make_float2(0.f, 0.f);
-            l[t] = grp < groups ? lam[u0 | offa[t]] : make_float2(0.f, 0.f);
-        }
-    }
-    for (; grp < groups; grp += stride) {
-        const uint64_t u = column(grp);
-        const uint64_t gn = grp + stride;
-        const uint64_t un = column(gn);
-        float2 xn[8], ln[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            xn[t] = gn < groups ? psi[un | offa[t]] : make_float2(0.f, 0.f);
-            ln[t] = gn < groups ? lam[un | offa[t]] : make_float2(0.f, 0.f);
-        }
-        // transpose: tile row = real index (amplitude 8h + t: row 8h + t real,
-        // row 16 + 8h + t imaginary), tile column = column of the group
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            tp[w][8 * h + t][cu] = x[t].x;
-            tp[w][16 + 8 * h + t][cu] = x[t].y;
-            tl[w][8 * h + t][cu] = l[t].x;
-            tl[w][16 + 8 * h + t][cu] = l[t].y;
-        }
-        wave_lds_sync();
-        // S_real[16I + i][16J + j] += sum_k tp[16I + i][k] tl[16J + j][k]
-        // (A lane holds row lane % 16 of step column lane / 16)
+    // S_real[16I + i][16J + j] += sum_k tp[16I + i][k] tl[16J + j][k]
+    // (A lane holds row lane % 16 of step column lane / 16)
+    auto correlate = [&]() {
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const int kk = 4 * st + (lane >> 4), ii = lane & 15;
@@ -130,25 +100,144 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, s10, 0, 0, 0);
             s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
         }
-        wave_lds_sync();
-        // un-apply: y = M x for both vectors (step s: component s & 1 of
-        // amplitude 8h + (s >> 1); output register r: component r & 1 of
-        // amplitude 8h + (r >> 1))
-        f32x16 yp = {0}, yl = {0};
+    };
+    // un-apply: y = M x for both vectors (step s: component s & 1 of
+    // amplitude 8h + (s >> 1); output register r: component r & 1 of
+    // amplitude 8h + (r >> 1))
+    auto unapply = [&](const float2 (&x)[8], const float2 (&l)[8], f32x16& yp, f32x16& yl) {
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             yp = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? x[s >> 1].y : x[s >> 1].x, yp, 0, 0, 0);
             yl = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? l[s >> 1].y : l[s >> 1].x, yl, 0, 0, 0);
         }
+    };
+    uint64_t grp = (uint64_t)blockIdx.x * kAmWaves + w;
+    if constexpr (COAL) {
+        // memory order: element m (9 bits) of a group sits at the group's base
+        // plus m's bits deposited on the group's nine varying bits; lane and
+        // pass k hold m = 64 k + lane. mo: its offset; ti: its tile entry.
+        const uint64_t qmask = (1ull << q0) | (1ull << q1) | (1ull << q2) | (1ull << q3);
+        uint64_t cmask = 0;
+        for (int b = 0, c = 0; c < 5; ++b)
+            if (!((qmask >> b) & 1)) {
+                cmask |= 1ull << b;
+                ++c;
+            }
+        const uint64_t vmask = qmask | cmask;
+        uint64_t mo[8];
+        int ti[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            psi[u | offa[t]] = make_float2(yp[2 * t], yp[2 * t + 1]);
-            lam[u | offa[t]] = make_float2(yl[2 * t], yl[2 * t + 1]);
+        for (int k = 0; k < 8; ++k) {
+            uint32_t m = 64 * k + lane;
+            uint64_t x = 0, vm = vmask;
+            for (int r = 0; r < 9; ++r) {
+                const uint64_t low = vm & (~vm + 1);
+                if ((m >> r) & 1) x |= low;
+                vm ^= low;
+            }
+            int j = 0, c = 0;
+            j |= (int)((x >> q0) & 1) | (int)(((x >> q1) & 1) << 1) | (int)(((x >> q2) & 1) << 2) |
+                 (int)(((x >> q3) & 1) << 3);
+            uint64_t cm = cmask;
+            for (int r = 0; r < 5; ++r) {
+                const uint64_t low = cm & (~cm + 1);
+                if (x & low) c |= 1 << r;
+                cm ^= low;
+            }
+            mo[k] = x;
+            ti[k] = j * kTp + c;
         }
+        float* tpw = &tp[w][0][0];
+        float* tlw = &tl[w][0][0];
+        for (; grp < groups; grp += stride) {
+            const uint64_t base = column(grp, 0);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            x[t] = xn[t];
-            l[t] = ln[t];
+            for (int k = 0; k < 8; ++k) {
+                const float2 v = psi[base | mo[k]], e = lam[base | mo[k]];
+                tpw[ti[k]] = v.x;
+                tpw[ti[k] + 16 * kTp] = v.y;
+                tlw[ti[k]] = e.x;
+                tlw[ti[k] + 16 * kTp] = e.y;
+            }
+            wave_lds_sync();
+            float2 x[8], l[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                x[t] = make_float2(tp[w][8 * h + t][cu], tp[w][16 + 8 * h + t][cu]);
+                l[t] = make_float2(tl[w][8 * h + t][cu], tl[w][16 + 8 * h + t][cu]);
+            }
+            correlate();
+            wave_lds_sync();
+            f32x16 yp = {0}, yl = {0};
+            unapply(x, l, yp, yl);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                tp[w][8 * h + t][cu] = yp[2 * t];
+                tp[w][16 + 8 * h + t][cu] = yp[2 * t + 1];
+                tl[w][8 * h + t][cu] = yl[2 * t];
+                tl[w][16 + 8 * h + t][cu] = yl[2 * t + 1];
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                psi[base | mo[k]] = make_float2(tpw[ti[k]], tpw[ti[k] + 16 * kTp]);
+                lam[base | mo[k]] = make_float2(tlw[ti[k]], tlw[ti[k] + 16 * kTp]);
+            }
+            wave_lds_sync();
+        }
+    } else {
+        uint64_t offa[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            offa[t] = ((uint64_t)(t & 1) << q0) | ((uint64_t)((t >> 1) & 1) << q1) |
+                      ((uint64_t)((t >> 2) & 1) << q2) | ((uint64_t)h << q3);
+        // the next group's columns are loaded while this group's products
+        // run; each wave works through its own groups (its LDS tiles are its
+        // own, so only the wave itself has to be in step between writing and
+        // reading them)
+        float2 x[8], l[8];
+        {
+            const uint64_t u0 = column(grp, cu);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                x[t] = grp < groups ? psi[u0 | offa[t]] : make_float2(0.f, 0.f);
+                l[t] = grp < groups ? lam[u0 | offa[t]] : make_float2(0.f, 0.f);
+            }
+        }
+        for (; grp < groups; grp += stride) {
+            const uint64_t u = column(grp, cu);
+            const uint64_t gn = grp + stride;
+            const uint64_t un = column(gn, cu);
+            float2 xn[8], ln[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                xn[t] = gn < groups ? psi[un | offa[t]] : make_float2(0.f, 0.f);
+                ln[t] = gn < groups ? lam[un | offa[t]] : make_float2(0.f, 0.f);
+            }
+            // transpose: tile row = real index (amplitude 8h + t: row 8h + t
+            // real, row 16 + 8h + t imaginary), tile column = column of the group
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                tp[w][8 * h + t][cu] = x[t].x;
+                tp[w][16 + 8 * h + t][cu] = x[t].y;
+                tl[w][8 * h + t][cu] = l[t].x;
+                tl[w][16 + 8 * h + t][cu] = l[t].y;
+            }
+            wave_lds_sync();
+            correlate();
+            wave_lds_sync();
+            f32x16 yp = {0}, yl = {0};
+            unapply(x, l, yp, yl);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                psi[u | offa[t]] = make_float2(yp[2 * t], yp[2 * t + 1]);
+                lam[u | offa[t]] = make_float2(yl[2 * t], yl[2 * t + 1]);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                x[t] = xn[t];
+                l[t] = ln[t];
+            }
         }
     }
     // the workgroup's S_real (32 x 32, row-major): the waves' parts summed in
@@ -213,7 +302,7 @@ int adj_mfma_grid(int n)
     static int resident = 0;
     if (resident == 0) {
         int nb = 0;
-        SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_adj_mfma),
+        SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_adj_mfma<false>),
                                                              kAmThreads, 0));
         resident = std::max(nb, 1);
     }
@@ -230,7 +319,8 @@ uint64_t adj_mfma_part_doubles(int grid, int rows)
 
 void launch_adj_mfma(const AdjMfmaLaunch& a, int rows, double* s_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adj_mfma, dim3(a.grid, rows), dim3(kAmThreads), 0, st, a);
+    if (a.q[0] < 5) hipLaunchKernelGGL(k_adj_mfma<true>, dim3(a.grid, rows), dim3(kAmThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_adj_mfma<false>, dim3(a.grid, rows), dim3(kAmThreads), 0, st, a);
     SV_HIP(hipGetLastError());
     double* mid = a.spart + (uint64_t)rows * a.grid * 1024;
     hipLaunchKernelGGL(k_adj_mfma_reduce1, dim3(kAmChunks, rows), dim3(kAmThreads), 0, st, a.spart, a.grid, mid);
