@@ -203,28 +203,40 @@ __device__ void build_fragment_column(const BatchArgs& a, int f, int c)
         dev_gate_matrix(op.kind, prm, m);
         phase_gate_d(v, op, m);
     }
-    // v = U e_c. Real form: row i (0..31) of the 32 x 32 operand is output
-    // component (i & 1) of amplitude jo(i) = 8 ((i >> 2) & 1) + 2 (i >> 3) +
-    // ((i >> 1) & 1); the input column is (amplitude c, component ci).
+    // v = U e_c.
+    if (a.phase_mode == kPhaseFp32) {
+        // three real 16 x 16 products (Gauss): Ur, Ui and Ur + Ui, rows in the
+        // order of the FP32 16 x 16 x 4 output (row 4 iq + r <-> amplitude
+        // 4 r + iq), as A operands: lane i + 16 (c & 3), step c >> 2
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int jo = 4 * (i & 3) + (i >> 2);
+            const double ur = v[jo].x, ui = v[jo].y;
+            float* fr = a.frag + ((size_t)f * 64 + i + 16 * (c & 3)) * kFragFloats;
+            fr[0 * 4 + (c >> 2)] = (float)ur;
+            fr[1 * 4 + (c >> 2)] = (float)ui;
+            fr[2 * 4 + (c >> 2)] = (float)(ur + ui);
+        }
+        return;
+    }
+    // BF16 x3: real form [[Ur, -Ui], [Ui, Ur]]; row i (0..31) of the 32 x 32
+    // operand is output component (i & 1) of amplitude jo(i) = 8 ((i >> 2) &
+    // 1) + 2 (i >> 3) + ((i >> 1) & 1); the input column is (amplitude c,
+    // component ci).
     const int lane_hi = 32 * (c >> 3);
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
         const int jo = 8 * ((i >> 2) & 1) + 2 * (i >> 3) + ((i >> 1) & 1);
         const double ur = v[jo].x, ui = v[jo].y;
         for (int ci = 0; ci < 2; ++ci) {
-            // [[Ur, -Ui], [Ui, Ur]]
             const double e = (i & 1) == 0 ? (ci == 0 ? ur : -ui) : (ci == 0 ? ui : ur);
             float* fr = a.frag + ((size_t)f * 64 + lane_hi + i) * kFragFloats;
-            if (a.phase_mode == kPhaseFp32) {
-                fr[2 * (c & 7) + ci] = (float)e;
-            } else {
-                const float ef = (float)e;
-                const __bf16 hi = (__bf16)ef;
-                const __bf16 lo = (__bf16)(ef - (float)hi);
-                __bf16* fb = reinterpret_cast<__bf16*>(fr);
-                fb[(ci * 2 + 0) * 8 + (c & 7)] = hi;
-                fb[(ci * 2 + 1) * 8 + (c & 7)] = lo;
-            }
+            const float ef = (float)e;
+            const __bf16 hi = (__bf16)ef;
+            const __bf16 lo = (__bf16)(ef - (float)hi);
+            __bf16* fb = reinterpret_cast<__bf16*>(fr);
+            fb[(ci * 2 + 0) * 8 + (c & 7)] = hi;
+            fb[(ci * 2 + 1) * 8 + (c & 7)] = lo;
         }
     }
 }
@@ -432,20 +444,13 @@ __device__ __forceinline__ bf16x8 frag_b(const Frag& fr, int idx)
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// The products of one fused phase for two groups of 32 units (operand
-// layouts as described for fused_phase).
+// The BF16 x3 products of one fused phase for two groups of 32 units
+// (operand layouts as described for fused_phase).
 template <int PM>
 __device__ __forceinline__ void product2(const Frag& fr, const float2 (&xa)[8], const float2 (&xb)[8], f32x16& acca,
                                          f32x16& accb)
 {
-    if constexpr (PM == kPhaseFp32) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const float f = frag_f(fr, s);
-            acca = __builtin_amdgcn_mfma_f32_32x32x2f32(f, (s & 1) ? xa[s >> 1].y : xa[s >> 1].x, acca, 0, 0, 0);
-            accb = __builtin_amdgcn_mfma_f32_32x32x2f32(f, (s & 1) ? xb[s >> 1].y : xb[s >> 1].x, accb, 0, 0, 0);
-        }
-    } else {
+    {
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci) {
             bf16x8 ha, la, hb, lb;
@@ -469,17 +474,23 @@ __device__ __forceinline__ void product2(const Frag& fr, const float2 (&xa)[8], 
 }
 
 // A fused phase: every unit's 16 amplitudes y = U x with U the product of
-// the phase's gates, on the matrix cores. As a real product Y = M X with
-// M = [[Ur, -Ui], [Ui, Ur]] (32 x 32) and X one 32-real column per unit, a
-// wave takes 32 units at a time (the 32 columns of one 32 x 32 x K product).
-// Lane (h, u) (h = lane / 32, unit u = lane % 32 of the group) reads and
-// writes amplitudes 8h .. 8h+7 of its unit: input step s of the FP32 form
-// (v_mfma_f32_32x32x2_f32, K = 2 per step) is component s & 1 of amplitude
-// 8h + (s >> 1); step s of the BF16 x3 form (v_mfma_f32_32x32x16_bf16,
-// K = 16 per step) is component s of amplitudes 8h .. 8h+7. The output
-// register r is component r & 1 of amplitude 8h + (r >> 1), so each lane
-// writes back exactly what it read. The fragment builder orders the rows and
-// columns of M to match.
+// the phase's gates, on the matrix cores; a wave takes 32 units at a time.
+//
+// FP32 (Gauss's three real products): yr = Ur xr - Ui xi, yi = Ur xi + Ui xr
+// from P1 = Ur xr, P2 = Ui xi, P3 = (Ur + Ui)(xr + xi) as yr = P1 - P2,
+// yi = P3 - P1 - P2, each a 16 x 16 x 16 real product on
+// v_mfma_f32_16x16x4_f32 (3/4 of the multiply-adds of the 32 x 32 real
+// form). Per half-group of 16 units, lane (kq, u) (kq = lane / 16, unit u =
+// lane % 16) supplies amplitude 4s + kq at step s and receives output row
+// 4 kq + r, which the fragment builder maps to amplitude 4r + kq: each lane
+// writes back exactly the four amplitudes it read.
+//
+// BF16 x3: the real product Y = M X with M = [[Ur, -Ui], [Ui, Ur]]
+// (32 x 32) and X one 32-real column per unit (the 32 columns of one
+// 32 x 32 x K product). Lane (h, u) (h = lane / 32, unit u = lane % 32 of
+// the group) reads and writes amplitudes 8h .. 8h+7 of its unit: step s of
+// v_mfma_f32_32x32x16_bf16 (K = 16) is component s of amplitudes 8h .. 8h+7,
+// and output register r is component r & 1 of amplitude 8h + (r >> 1).
 template <int NT, int PM>
 __device__ __forceinline__ void fused_phase(float2* tile, int m, const BPhase& ph, const Frag& fr)
 {
@@ -488,6 +499,49 @@ __device__ __forceinline__ void fused_phase(float2* tile, int m, const BPhase& p
     const int h = lane >> 5;
     const uint32_t groups = 1u << (m - kRegBits - 5);
     const int g0 = ph.g[0], g1 = ph.g[1], g2 = ph.g[2], g3 = ph.g[3];
+    if constexpr (PM == kPhaseFp32) {
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        const int kq = lane >> 4, u16 = lane & 15;
+        uint32_t offk[4];     // swizzled offsets of amplitudes 4s + kq
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int amp = 4 * st + kq;
+            offk[st] = swz(((uint32_t)(amp & 1) << g0) | ((uint32_t)((amp >> 1) & 1) << g1) |
+                           ((uint32_t)((amp >> 2) & 1) << g2) | ((uint32_t)((amp >> 3) & 1) << g3));
+        }
+        for (uint32_t grp = wave; grp < groups; grp += NW) {
+            uint32_t ub[2];
+            float2 x[2][4];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                uint32_t u = grp * 32 + nb * 16 + u16;
+                u = ((u >> g0) << (g0 + 1)) | (u & ((1u << g0) - 1u));
+                u = ((u >> g1) << (g1 + 1)) | (u & ((1u << g1) - 1u));
+                u = ((u >> g2) << (g2 + 1)) | (u & ((1u << g2) - 1u));
+                ub[nb] = swz(((u >> g3) << (g3 + 1)) | (u & ((1u << g3) - 1u)));
+#pragma unroll
+                for (int st = 0; st < 4; ++st) x[nb][st] = tile[ub[nb] ^ offk[st]];
+            }
+            f32x4 p1[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, p2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}},
+                  p3[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const float fr_r = frag_f(fr, st), fr_i = frag_f(fr, 4 + st), fr_s = frag_f(fr, 8 + st);
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    p1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr_r, x[nb][st].x, p1[nb], 0, 0, 0);
+                    p2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr_i, x[nb][st].y, p2[nb], 0, 0, 0);
+                    p3[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr_s, x[nb][st].x + x[nb][st].y, p3[nb], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    tile[ub[nb] ^ offk[r]] = make_float2(p1[nb][r] - p2[nb][r], p3[nb][r] - p1[nb][r] - p2[nb][r]);
+        }
+        return;
+    }
     uint32_t offa[8];     // swizzled offsets of the lane's amplitudes within a unit
 #pragma unroll
     for (int q = 0; q < 8; ++q)
