@@ -422,10 +422,11 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         "gates_per_s": round(gates / (graph_ms / 1e3), 1),
         "speedup_vs_per_gate": round(pergate_ms / graph_ms, 2),
         "default_config_ms": round(timings["default"], 3),
-        # a fused phase amplitude costs one 32-wide real row of a 32x32
-        # product: 64 multiply-adds = 128 FLOP (BF16x3: three such products)
+        # a fused phase amplitude costs, FP32 (Gauss): three real 16-wide
+        # rows = 48 multiply-adds = 96 FLOP; BF16x3: three rows of the real
+        # 32x32 form, 3 x 64 multiply-adds = 384 FLOP
         "phase_arithmetic": {"gate_by_gate": mode_entry("gate_by_gate", 0, None),
-                             "fused_fp32": mode_entry("fused_fp32", 128, 157.3),
+                             "fused_fp32": mode_entry("fused_fp32", 96, 157.3),
                              "fused_bf16x3": mode_entry("fused_bf16x3", 3 * 128, 2500.0)},
         "autotune": {"chosen": info["config"], "grid": info["grid"], "tasks": info["n_tasks"],
                      "passes": info["n_passes"], "configs_tried": len(trials), "tune_s": round(tune_s, 2)},
