@@ -2,7 +2,7 @@
 execution, Sec. 4.4 and the `invertible=True` device of Appendix A).
 
 Forward: reset the state to |0..0>, run the circuit with the given
-parameters, return L = sum_t coeff_t <P_t> per batch row. From 14 qubits on
+parameters, return L = sum_t coeff_t <P_t> per batch row. From 20 qubits on
 (``fuse``), gates whose angles are equal on every row are fused into
 5-qubit blocks on the matrix cores (Sec. 4.1.1); per-row gates (an input
 encoding) stay per-gate sweeps. Backward: the
@@ -26,8 +26,9 @@ from . import sv
 
 
 # The forward fuses row-shared gates into matrix-core blocks from this width
-# on (below it a per-gate sweep is cheaper than planning the blocks).
-FUSED_FORWARD_MIN_QUBITS = 14
+# on (below it the per-gate sweeps are about as fast as planning the blocks
+# and running them: measured equal at 18 qubits, batch 16).
+FUSED_FORWARD_MIN_QUBITS = 20
 
 
 def default_fuse(circuit) -> bool:
