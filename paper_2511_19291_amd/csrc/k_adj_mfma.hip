@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
     float2* lam = am_row(a.lam, row);
     float fr[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) fr[s] = a.frag[lane * 16 + s];
+    for (int s = 0; s < 16; ++s) fr[s] = a.frag[(size_t)row * a.frag_stride + lane * 16 + s];
     const int q0 = a.q[0], q1 = a.q[1], q2 = a.q[2], q3 = a.q[3];
     f64x4 s00 = {0, 0, 0, 0}, s01 = {0, 0, 0, 0}, s10 = {0, 0, 0, 0}, s11 = {0, 0, 0, 0};
     const uint64_t groups = a.N >> 9;          // 32 columns of 16 amplitudes

@@ -953,22 +953,66 @@ void embed16(const cd* m, int k, const int* tl, int cm, bool id, cd* E)
     }
 }
 
-// C = A B (16 x 16, row-major); complex products written out in real
-// arithmetic (the library's complex operator* keeps the C99 special-value
-// rules and is many times slower)
-void mm16(const cd* A, const cd* B, cd* C)
+// A block's embedded gate as its nonzero entries: at most four per column
+// for a gate on at most two targets. Products with it cost 16 complex
+// multiply-adds per entry instead of 256 per column. Complex products are
+// written out in real arithmetic (the library's complex operator* keeps the
+// C99 special-value rules and is many times slower).
+struct Sp16 {
+    int n = 0;
+    uint8_t r[64], c[64];
+    cd v[64];
+};
+
+void sparse16(const cd* E, Sp16& S)
 {
+    S.n = 0;
     for (int r = 0; r < 16; ++r)
-        for (int c = 0; c < 16; ++c) {
-            double re = 0.0, im = 0.0;
-            for (int j = 0; j < 16; ++j) {
-                const double ar = A[r * 16 + j].real(), ai = A[r * 16 + j].imag();
-                const double br = B[j * 16 + c].real(), bi = B[j * 16 + c].imag();
-                re += ar * br - ai * bi;
-                im += ar * bi + ai * br;
+        for (int c = 0; c < 16; ++c)
+            if (E[r * 16 + c] != cd(0.0)) {
+                need(S.n < 64, SV_ERR_UNSUPPORTED, "embedded gate has more than 64 entries");
+                S.r[S.n] = (uint8_t)r;
+                S.c[S.n] = (uint8_t)c;
+                S.v[S.n++] = E[r * 16 + c];
             }
-            C[r * 16 + c] = cd(re, im);
+}
+
+// C += v a, over a row of 16
+inline void axpy16(cd v, const cd* a, cd* o)
+{
+    const double vr = v.real(), vi = v.imag();
+    for (int c = 0; c < 16; ++c) {
+        const double ar = a[c].real(), ai = a[c].imag();
+        o[c] = cd(o[c].real() + vr * ar - vi * ai, o[c].imag() + vr * ai + vi * ar);
+    }
+}
+
+// C = E A
+void sp_left(const Sp16& E, const cd* A, cd* C)
+{
+    std::fill(C, C + 256, cd(0.0));
+    for (int k = 0; k < E.n; ++k) axpy16(E.v[k], A + E.c[k] * 16, C + E.r[k] * 16);
+}
+
+// C = E^* A
+void sp_adj_left(const Sp16& E, const cd* A, cd* C)
+{
+    std::fill(C, C + 256, cd(0.0));
+    for (int k = 0; k < E.n; ++k) axpy16(std::conj(E.v[k]), A + E.r[k] * 16, C + E.c[k] * 16);
+}
+
+// C = A E
+void sp_right(const cd* A, const Sp16& E, cd* C)
+{
+    std::fill(C, C + 256, cd(0.0));
+    for (int k = 0; k < E.n; ++k) {
+        const int j = E.r[k], c = E.c[k];
+        const double vr = E.v[k].real(), vi = E.v[k].imag();
+        for (int r = 0; r < 16; ++r) {
+            const double ar = A[r * 16 + j].real(), ai = A[r * 16 + j].imag();
+            C[r * 16 + c] = cd(C[r * 16 + c].real() + ar * vr - ai * vi, C[r * 16 + c].imag() + ar * vi + ai * vr);
         }
+    }
 }
 
 // C = A B^*
@@ -1042,23 +1086,54 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         const double* dcoeff = nullptr;
         if (!diag_w) upload_terms(s, obs, n_obs, coeff_rows, B, &dterms, &dcoeff);
 
-        // ---- plan on the host: one launch per block (per row where a gate's
-        // parameters differ between rows) and its fragments; the X_k are
-        // formed after the launches are queued, while the GPU sweeps
+        // ---- plan on the host: one launch per block over every row; a block
+        // holding gates whose parameters differ between rows gets its product
+        // (fragments) per row. For a block shared by all rows the X_k are
+        // formed after the launches are queued, while the GPU sweeps; for a
+        // per-row block the derivatives come from S itself once it is back,
+        // S_t = W_t^* S W_t stepped down the gates (Tr(X_k S) = Tr(G_k S_k)),
+        // since the X_k would be needed per row.
         struct Deriv { int param; size_t x; };      // X_k at xs[x * 256]
         struct Launch {
-            int row;
             int q[4];
             const GateBlock* gb;
             std::vector<int> tl, cm;                 // local targets (2 per gate), control masks
-            size_t e_at;                             // E matrices of its gates at es[e_at]
-            std::vector<Deriv> d;
+            int nfr;                                 // 1: one product for all rows; B: one per row
+            size_t frag_at;                          // first fragment block (1024 floats each)
+            std::vector<size_t> e_at;                // per product: E of its gates at es[e_at + t]
+            std::vector<Deriv> d;                    // shared product: its X_k
         };
         std::vector<Launch> launches;
         std::vector<float> frags;
-        std::vector<cd> es, xs;
+        std::vector<Sp16> es;
+        std::vector<cd> xs;
         const std::vector<GateBlock> blocks = plan_gate_blocks(masks, lb);
-        std::vector<cd> U(256), T1(256), T2(256), W(256), G(256);
+        std::vector<cd> U(256), T1(256), T2(256), W(256), Ed(256);
+        Sp16 Gs;
+        // G = dG_k G_k^* of parameter d of gate t, embedded in the block
+        auto gate_derivative = [&](const Launch& L, int t, const double* prow, int d, Sp16& out) {
+            const sv_op& op = ops[L.gb->gates[t]];
+            const OpInfo& oi = info[L.gb->gates[t]];
+            const int D = 1 << oi.k;
+            double prm[3];
+            op_params(op, oi, prow, prm);
+            cd m[16], md[16], dm[16], g[16];
+            op_matrix(op, oi, prow, m);
+            dagger(oi.k, m, md);
+            kind_dmatrix(op.kind, prm, d, dm);
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) {
+                    double re = 0.0, im = 0.0;
+                    for (int j = 0; j < D; ++j) {
+                        const cd x = dm[r * D + j], y = md[j * D + c];
+                        re += x.real() * y.real() - x.imag() * y.imag();
+                        im += x.real() * y.imag() + x.imag() * y.real();
+                    }
+                    g[r * D + c] = cd(re, im);
+                }
+            embed16(g, oi.k, &L.tl[2 * t], L.cm[t], false, Ed.data());
+            sparse16(Ed.data(), out);
+        };
         for (int bi = (int)blocks.size() - 1; bi >= 0; --bi) {
             const GateBlock& gb = blocks[bi];
             uint64_t used = 0;
@@ -1077,32 +1152,35 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                 for (int gi : gb.gates)
                     if (info[gi].np > 0 && !same_params_all_rows(ops[gi], info[gi], params, params_batch_stride, B))
                         rows_differ = true;
-            const int nrl = rows_differ ? B : 1;
             const int ng = (int)gb.gates.size();
-            for (int rl = 0; rl < nrl; ++rl) {
+            Launch L{};
+            for (int i = 0; i < 4; ++i) L.q[i] = lq[i];
+            L.gb = &gb;
+            L.tl.assign(ng * 2, 0);
+            L.cm.assign(ng, 0);
+            for (int t = 0; t < ng; ++t) {
+                const sv_op& op = ops[gb.gates[t]];
+                L.tl[2 * t] = local(op.targets[0]);
+                L.tl[2 * t + 1] = info[gb.gates[t]].k == 2 ? local(op.targets[1]) : 0;
+                for (int j = 0; j < op.n_controls; ++j) L.cm[t] |= 1 << local(op.controls[j]);
+            }
+            L.nfr = rows_differ ? B : 1;
+            L.frag_at = frags.size() / 1024;
+            for (int rl = 0; rl < L.nfr; ++rl) {
                 const double* prow = params + (rows_differ ? rl * params_batch_stride : 0);
-                Launch L{};
-                L.row = rows_differ ? rl : -1;
-                for (int i = 0; i < 4; ++i) L.q[i] = lq[i];
-                L.gb = &gb;
-                L.tl.assign(ng * 2, 0);
-                L.cm.assign(ng, 0);
-                L.e_at = es.size();
-                es.resize(es.size() + (size_t)ng * 256);
-                for (int t = 0; t < ng; ++t) {
-                    const sv_op& op = ops[gb.gates[t]];
-                    const OpInfo& oi = info[gb.gates[t]];
-                    L.tl[2 * t] = local(op.targets[0]);
-                    L.tl[2 * t + 1] = oi.k == 2 ? local(op.targets[1]) : 0;
-                    for (int j = 0; j < op.n_controls; ++j) L.cm[t] |= 1 << local(op.controls[j]);
-                    cd m[16];
-                    op_matrix(op, oi, prow, m);
-                    embed16(m, oi.k, &L.tl[2 * t], L.cm[t], true, &es[L.e_at + (size_t)t * 256]);
-                }
+                const size_t ea = es.size();
+                L.e_at.push_back(ea);
+                es.resize(ea + ng);
                 // U_B = E_last ... E_first; the kernel applies M = U_B^*
                 for (int q = 0; q < 256; ++q) U[q] = (q % 17 == 0) ? 1.0 : 0.0;
                 for (int t = 0; t < ng; ++t) {
-                    mm16(&es[L.e_at + (size_t)t * 256], U.data(), T1.data());
+                    const sv_op& op = ops[gb.gates[t]];
+                    const OpInfo& oi = info[gb.gates[t]];
+                    cd m[16];
+                    op_matrix(op, oi, prow, m);
+                    embed16(m, oi.k, &L.tl[2 * t], L.cm[t], true, Ed.data());
+                    sparse16(Ed.data(), es[ea + t]);
+                    sp_left(es[ea + t], U.data(), T1.data());
                     U.swap(T1);
                 }
                 for (int r = 0; r < 16; ++r)
@@ -1110,48 +1188,26 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                 const size_t fo = frags.size();
                 frags.resize(fo + 1024);
                 mfma_fragments(T1.data(), &frags[fo]);
-                launches.push_back(std::move(L));
             }
+            launches.push_back(std::move(L));
         }
         // X_k = W_k (dG_k G_k^*) W_k^*, W_k the gates after k (host, FP64)
         auto form_derivatives = [&] {
             for (Launch& L : launches) {
-                const GateBlock& gb = *L.gb;
-                const int ng = (int)gb.gates.size();
-                const double* prow = params + (L.row >= 0 ? L.row * params_batch_stride : 0);
+                if (L.nfr > 1) continue;
+                const int ng = (int)L.gb->gates.size();
+                const size_t ea = L.e_at[0];
                 for (int q = 0; q < 256; ++q) W[q] = (q % 17 == 0) ? 1.0 : 0.0;
                 for (int t = ng - 1; t >= 0; --t) {
-                    const int gi = gb.gates[t];
-                    const sv_op& op = ops[gi];
-                    const OpInfo& oi = info[gi];
-                    if (oi.np > 0) {
-                        const int D = 1 << oi.k;
-                        double prm[3];
-                        op_params(op, oi, prow, prm);
-                        cd m[16], md[16];
-                        op_matrix(op, oi, prow, m);
-                        dagger(oi.k, m, md);
-                        for (int d = 0; d < oi.np; ++d) {
-                            cd dm[16], g[16];
-                            kind_dmatrix(op.kind, prm, d, dm);
-                            for (int r = 0; r < D; ++r)
-                                for (int c = 0; c < D; ++c) {
-                                    double re = 0.0, im = 0.0;
-                                    for (int j = 0; j < D; ++j) {
-                                        const cd x = dm[r * D + j], y = md[j * D + c];
-                                        re += x.real() * y.real() - x.imag() * y.imag();
-                                        im += x.real() * y.imag() + x.imag() * y.real();
-                                    }
-                                    g[r * D + c] = cd(re, im);
-                                }
-                            embed16(g, oi.k, &L.tl[2 * t], L.cm[t], false, G.data());
-                            mm16(W.data(), G.data(), T1.data());
-                            mm16_adj(T1.data(), W.data(), T2.data());
-                            L.d.push_back(Deriv{op.param[d], xs.size() / 256});
-                            xs.insert(xs.end(), T2.begin(), T2.end());
-                        }
+                    const int gi = L.gb->gates[t];
+                    for (int d = 0; d < info[gi].np; ++d) {
+                        gate_derivative(L, t, params, d, Gs);
+                        sp_right(W.data(), Gs, T1.data());
+                        mm16_adj(T1.data(), W.data(), T2.data());
+                        L.d.push_back(Deriv{ops[gi].param[d], xs.size() / 256});
+                        xs.insert(xs.end(), T2.begin(), T2.end());
                     }
-                    mm16(W.data(), &es[L.e_at + (size_t)t * 256], T1.data());
+                    sp_right(W.data(), es[ea + t], T1.data());
                     W.swap(T1);
                 }
             }
@@ -1159,13 +1215,9 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
 
         // ---- device buffers: fragments, the waves' S parts, S per launch and row
         const int grid_full = adj_mfma_grid(s->n);
-        uint64_t spart_max = 1, s_total = 0;
-        for (const Launch& L : launches) {
-            const int rows_here = L.row < 0 ? B : 1;
-            const int grid = std::max(1, std::min(grid_full, (grid_full + rows_here - 1) / rows_here));
-            spart_max = std::max<uint64_t>(spart_max, adj_mfma_part_doubles(grid, rows_here));
-            s_total += (uint64_t)rows_here * 1024;
-        }
+        const int grid = std::max(1, std::min(grid_full, (grid_full + B - 1) / B));
+        const uint64_t spart_max = std::max<uint64_t>(1, adj_mfma_part_doubles(grid, B));
+        const uint64_t s_total = (uint64_t)launches.size() * B * 1024;
         const uint64_t red = std::max<uint64_t>(inner_parts(s->n, B), drift_parts(s->n, B));
         const uint64_t frag_doubles = (frags.size() + 1) / 2 + 2;
         const uint64_t frag_at = (spart_max + red + 1) & ~1ull;
@@ -1187,25 +1239,18 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream, z_only_terms(obs, n_obs));
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
-        uint64_t cur = 0;
         for (size_t li = 0; li < launches.size(); ++li) {
             const Launch& L = launches[li];
-            const int rows_here = L.row < 0 ? B : 1;
             AdjMfmaLaunch a{};
-            if (L.row >= 0) {
-                a.psi = one_row(s, s->psi, L.row);
-                a.lam = one_row(s, lam, L.row);
-            } else {
-                a.psi = prow;
-                a.lam = lrow;
-            }
+            a.psi = prow;
+            a.lam = lrow;
             a.N = s->N;
             for (int i = 0; i < 4; ++i) a.q[i] = L.q[i];
-            a.frag = dfrag + li * 1024;
+            a.frag = dfrag + L.frag_at * 1024;
+            a.frag_stride = L.nfr > 1 ? 1024 : 0;
             a.spart = spart;
-            a.grid = std::max(1, std::min(grid_full, (grid_full + rows_here - 1) / rows_here));
-            launch_adj_mfma(a, rows_here, d_s + cur, s->stream);
-            cur += (uint64_t)rows_here * 1024;
+            a.grid = grid;
+            launch_adj_mfma(a, B, d_s + li * B * 1024, s->stream);
         }
         launch_drift(prow, s->n, rscratch, d_drift, s->stream);
         SV_HIP(hipMemcpyAsync(s->hout, s->dout, nout * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -1216,26 +1261,49 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         const double* h_drift = h_loss + 2ull * B;
         if (n_params > 0) std::fill(grad_out, grad_out + (size_t)B * n_params, 0.0);
         // derivatives in launch (reverse block) order, then gate order
-        cur = 0;
         std::vector<cd> S(256);
-        for (const Launch& L : launches) {
-            const int rows_here = L.row < 0 ? B : 1;
-            for (int r = 0; r < rows_here; ++r) {
-                const double* sr = h_s + cur + (uint64_t)r * 1024;     // S_real[32][32]
+        for (size_t li = 0; li < launches.size(); ++li) {
+            const Launch& L = launches[li];
+            const int ng = (int)L.gb->gates.size();
+            for (int r = 0; r < B; ++r) {
+                const double* sr = h_s + (li * B + r) * 1024;     // S_real[32][32]
                 for (int b = 0; b < 16; ++b)
                     for (int a2 = 0; a2 < 16; ++a2)
                         S[b * 16 + a2] = cd(sr[b * 32 + a2] + sr[(16 + b) * 32 + 16 + a2],
                                             sr[(16 + b) * 32 + a2] - sr[b * 32 + 16 + a2]);
-                const int row = L.row >= 0 ? L.row : r;
-                for (const Deriv& dv : L.d) {
-                    const cd* X = &xs[dv.x * 256];
-                    double tr = 0.0;       // Re Tr(X S)
-                    for (int a2 = 0; a2 < 16; ++a2)
-                        for (int b = 0; b < 16; ++b) tr += (X[a2 * 16 + b] * S[b * 16 + a2]).real();
-                    grad_out[(size_t)row * n_params + dv.param] += 2.0 * tr;
+                double* g = grad_out + (size_t)r * n_params;
+                if (L.nfr == 1) {
+                    for (const Deriv& dv : L.d) {
+                        const cd* X = &xs[dv.x * 256];
+                        double tr = 0.0;       // Re Tr(X S)
+                        for (int a2 = 0; a2 < 16; ++a2)
+                            for (int b = 0; b < 16; ++b) {
+                                const cd x = X[a2 * 16 + b], y = S[b * 16 + a2];
+                                tr += x.real() * y.real() - x.imag() * y.imag();
+                            }
+                        g[dv.param] += 2.0 * tr;
+                    }
+                    continue;
+                }
+                const double* prow = params + r * params_batch_stride;
+                const size_t ea = L.e_at[r];
+                for (int t = ng - 1; t >= 0; --t) {       // S holds S_t = W_t^* S W_t
+                    const int gi = L.gb->gates[t];
+                    for (int d = 0; d < info[gi].np; ++d) {
+                        gate_derivative(L, t, prow, d, Gs);
+                        double tr = 0.0;       // Re Tr(G S_t)
+                        for (int k = 0; k < Gs.n; ++k) {
+                            const cd x = Gs.v[k], y = S[Gs.c[k] * 16 + Gs.r[k]];
+                            tr += x.real() * y.real() - x.imag() * y.imag();
+                        }
+                        g[ops[gi].param[d]] += 2.0 * tr;
+                    }
+                    if (t > 0) {
+                        sp_right(S.data(), es[ea + t], T1.data());
+                        sp_adj_left(es[ea + t], T1.data(), S.data());
+                    }
                 }
             }
-            cur += (uint64_t)rows_here * 1024;
         }
         for (int r = 0; r < B; ++r) {
             if (loss_out) loss_out[r] = h_loss[2 * r];

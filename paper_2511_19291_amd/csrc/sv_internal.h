@@ -171,6 +171,7 @@ struct AdjMfmaLaunch {
     uint64_t N;
     int q[4];                 // block qubits, ascending
     const float* frag;        // 64 lanes x 16 floats: operands of [[Re M, -Im M], [Im M, Re M]], M = U_B^*
+    int frag_stride;          // floats between rows' operands (0: one product for all rows)
     double* spart;            // adj_mfma_part_doubles(grid, rows): [rows][grid][1024], then the chunk sums
     int grid;                 // workgroups per row
 };

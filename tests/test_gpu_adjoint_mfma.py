@@ -70,7 +70,7 @@ def test_matches_per_gate_backward(sv):
 
 
 def test_batched_rows_weighted(sv):
-    """Per-row inputs (launches per row for the blocks holding them) and
+    """Per-row inputs (per-row block products inside one launch) and
     per-row observable weights."""
     n, B = 10, 4
     circ, rows = C.profiling_ladder(n, 3, B, seed=12)
