@@ -266,33 +266,43 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
     }
 }
 
-// Two-level fixed-order sum of the workgroups' S_real: level 1, chunk c of
-// the workgroups (in order) per row; level 2, the chunks in order.
-constexpr int kAmChunks = 16;
+// Two-level fixed-order sum of the workgroups' S_real. Level 1: chunk c of
+// the workgroups (in order) per row, one element per thread, so that a launch
+// has kAmChunks x 4 workgroups per row; level 2: the chunks in order. Four
+// accumulators in a fixed pattern keep four loads in flight per thread.
+constexpr int kAmChunks = 64;
+
+__device__ __forceinline__ double sum_strided(const double* __restrict__ p, int count, size_t stride)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int v = 0;
+    for (; v + 4 <= count; v += 4) {
+        a0 += p[(size_t)v * stride];
+        a1 += p[(size_t)(v + 1) * stride];
+        a2 += p[(size_t)(v + 2) * stride];
+        a3 += p[(size_t)(v + 3) * stride];
+    }
+    for (; v < count; ++v) a0 += p[(size_t)v * stride];
+    return (a0 + a1) + (a2 + a3);
+}
 
 __global__ __launch_bounds__(kAmThreads) void k_adj_mfma_reduce1(const double* __restrict__ spart, int parts,
                                                                  double* __restrict__ mid)
 {
-    const int c = blockIdx.x, row = blockIdx.y;
+    const int c = blockIdx.x >> 2, row = blockIdx.y;
+    const int e = (blockIdx.x & 3) * kAmThreads + threadIdx.x;
     const int per = (parts + kAmChunks - 1) / kAmChunks;
-    const int p0 = c * per, p1 = min(parts, p0 + per);
-    const double* p = spart + (size_t)row * parts * 1024;
-    for (int e = threadIdx.x; e < 1024; e += kAmThreads) {
-        double acc = 0.0;
-        for (int v = p0; v < p1; ++v) acc += p[(size_t)v * 1024 + e];
-        mid[((size_t)row * kAmChunks + c) * 1024 + e] = acc;
-    }
+    const int p0 = min(parts, c * per), p1 = min(parts, p0 + per);
+    const double* p = spart + ((size_t)row * parts + p0) * 1024 + e;
+    mid[((size_t)row * kAmChunks + c) * 1024 + e] = sum_strided(p, p1 - p0, 1024);
 }
 
 __global__ __launch_bounds__(kAmThreads) void k_adj_mfma_reduce2(const double* __restrict__ mid,
                                                                  double* __restrict__ out)
 {
-    const int row = blockIdx.x;
-    for (int e = threadIdx.x; e < 1024; e += kAmThreads) {
-        double acc = 0.0;
-        for (int c = 0; c < kAmChunks; ++c) acc += mid[((size_t)row * kAmChunks + c) * 1024 + e];
-        out[(size_t)row * 1024 + e] = acc;
-    }
+    const int row = blockIdx.y;
+    const int e = blockIdx.x * kAmThreads + threadIdx.x;
+    out[(size_t)row * 1024 + e] = sum_strided(mid + (size_t)row * kAmChunks * 1024 + e, kAmChunks, 1024);
 }
 
 }  // namespace
@@ -323,9 +333,11 @@ void launch_adj_mfma(const AdjMfmaLaunch& a, int rows, double* s_out, hipStream_
     else hipLaunchKernelGGL(k_adj_mfma<false>, dim3(a.grid, rows), dim3(kAmThreads), 0, st, a);
     SV_HIP(hipGetLastError());
     double* mid = a.spart + (uint64_t)rows * a.grid * 1024;
-    hipLaunchKernelGGL(k_adj_mfma_reduce1, dim3(kAmChunks, rows), dim3(kAmThreads), 0, st, a.spart, a.grid, mid);
+    static_assert(4 * kAmThreads == 1024, "the reductions give each thread one of the 1024 entries");
+    hipLaunchKernelGGL(k_adj_mfma_reduce1, dim3(kAmChunks * 4, rows), dim3(kAmThreads), 0, st, a.spart, a.grid,
+                       mid);
     SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_adj_mfma_reduce2, dim3(rows), dim3(kAmThreads), 0, st, mid, s_out);
+    hipLaunchKernelGGL(k_adj_mfma_reduce2, dim3(4, rows), dim3(kAmThreads), 0, st, mid, s_out);
     SV_HIP(hipGetLastError());
 }
 

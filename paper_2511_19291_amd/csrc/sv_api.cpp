@@ -1059,6 +1059,7 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
 {
     return guarded([&] {
         constexpr int lb = 4;
+        constexpr int kRecurRows = 4;
         check_state(s);
         need(s->n >= 9, SV_ERR_UNSUPPORTED, "the matrix-core adjoint needs at least 9 qubits");
         need(n_ops >= 0 && (n_ops == 0 || ops != nullptr), SV_ERR_INVALID_ARGUMENT, "ops is NULL");
@@ -1088,17 +1089,19 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
 
         // ---- plan on the host: one launch per block over every row; a block
         // holding gates whose parameters differ between rows gets its product
-        // (fragments) per row. For a block shared by all rows the X_k are
-        // formed after the launches are queued, while the GPU sweeps; for a
-        // per-row block the derivatives come from S itself once it is back,
-        // S_t = W_t^* S W_t stepped down the gates (Tr(X_k S) = Tr(G_k S_k)),
-        // since the X_k would be needed per row.
+        // (fragments) per row. The derivatives come either from X_k formed
+        // on the host while the GPU sweeps (a block shared by more than
+        // kRecurRows rows: one X_k serves every row), or from S itself once
+        // it is back, S_t = W_t^* S W_t stepped down the gates
+        // (Tr(X_k S) = Tr(G_k S_t)): a few times cheaper per row, but after
+        // the sweeps.
         struct Deriv { int param; size_t x; };      // X_k at xs[x * 256]
         struct Launch {
             int q[4];
             const GateBlock* gb;
             std::vector<int> tl, cm;                 // local targets (2 per gate), control masks
             int nfr;                                 // 1: one product for all rows; B: one per row
+            bool recur;                              // derivatives by the S_t recursion
             size_t frag_at;                          // first fragment block (1024 floats each)
             std::vector<size_t> e_at;                // per product: E of its gates at es[e_at + t]
             std::vector<Deriv> d;                    // shared product: its X_k
@@ -1165,6 +1168,7 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                 for (int j = 0; j < op.n_controls; ++j) L.cm[t] |= 1 << local(op.controls[j]);
             }
             L.nfr = rows_differ ? B : 1;
+            L.recur = rows_differ || B <= kRecurRows;
             L.frag_at = frags.size() / 1024;
             for (int rl = 0; rl < L.nfr; ++rl) {
                 const double* prow = params + (rows_differ ? rl * params_batch_stride : 0);
@@ -1194,7 +1198,7 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         // X_k = W_k (dG_k G_k^*) W_k^*, W_k the gates after k (host, FP64)
         auto form_derivatives = [&] {
             for (Launch& L : launches) {
-                if (L.nfr > 1) continue;
+                if (L.recur) continue;
                 const int ng = (int)L.gb->gates.size();
                 const size_t ea = L.e_at[0];
                 for (int q = 0; q < 256; ++q) W[q] = (q % 17 == 0) ? 1.0 : 0.0;
@@ -1272,7 +1276,7 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                         S[b * 16 + a2] = cd(sr[b * 32 + a2] + sr[(16 + b) * 32 + 16 + a2],
                                             sr[(16 + b) * 32 + a2] - sr[b * 32 + 16 + a2]);
                 double* g = grad_out + (size_t)r * n_params;
-                if (L.nfr == 1) {
+                if (!L.recur) {
                     for (const Deriv& dv : L.d) {
                         const cd* X = &xs[dv.x * 256];
                         double tr = 0.0;       // Re Tr(X S)
@@ -1285,8 +1289,8 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                     }
                     continue;
                 }
-                const double* prow = params + r * params_batch_stride;
-                const size_t ea = L.e_at[r];
+                const double* prow = params + (L.nfr > 1 ? r * params_batch_stride : 0);
+                const size_t ea = L.e_at[L.nfr > 1 ? r : 0];
                 for (int t = ng - 1; t >= 0; --t) {       // S holds S_t = W_t^* S W_t
                     const int gi = L.gb->gates[t];
                     for (int d = 0; d < info[gi].np; ++d) {
