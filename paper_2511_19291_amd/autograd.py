@@ -43,28 +43,22 @@ def _forward(state, circuit, p, fuse: bool) -> None:
         state.run(circuit, params=p)
 
 
-# Backward form by width (measured on one MI355X): below 14 qubits the
-# per-gate backward (launch-bound sizes), from 14 the 4-qubit VALU blocks,
-# from 22 the matrix-core blocks (their host planning and per-row launches
-# pay off only on large states).
-BLOCKED_MIN_QUBITS = 14
-MFMA_MIN_QUBITS = 22
+# Backward form by width (measured on one MI355X, rings and batched ladders of
+# 10 to 28 qubits): below 13 qubits the per-gate backward (launch-bound
+# sizes), from 13 the matrix-core blocks, which from there on match or beat
+# both the per-gate and the 4-qubit VALU blocked backward. The VALU blocks stay
+# available through ``block_qubits``.
+MFMA_MIN_QUBITS = 13
 
 
 def default_block_qubits(circuit) -> int:
     """Backward form for this circuit: ``sv.ADJOINT_MFMA`` (matrix-core
-    blocks) from 22 qubits when every gate fits in four qubits; 4 (VALU
-    blocks) from 14 qubits when every gate fits and the parameterised
-    two-target gates are Pauli rotations; else 0 (per gate)."""
+    blocks) from 13 qubits when every gate fits in four qubits, else 0 (per
+    gate)."""
     fits = all(len(op.targets) + len(op.controls) <= 4 for op in circuit.ops)
-    if not fits or circuit.n < BLOCKED_MIN_QUBITS:
-        return 0
-    if circuit.n >= MFMA_MIN_QUBITS:
+    if fits and circuit.n >= MFMA_MIN_QUBITS:
         return sv.ADJOINT_MFMA
-    for op in circuit.ops:
-        if len(op.targets) == 2 and op.params and op.kind not in ("rxx", "ryy", "rzz"):
-            return 0
-    return 4
+    return 0
 
 
 class AdjointExpval(torch.autograd.Function):

@@ -161,6 +161,29 @@ void ensure_dout(sv_state s, uint64_t doubles)
     s->dout_cap = cap;
 }
 
+void ensure_hstage(sv_state s, uint64_t floats)
+{
+    if (floats <= s->hstage_cap) return;
+    if (s->hstage) {
+        SV_HIP(hipStreamSynchronize(s->stream));
+        SV_HIP(hipHostFree(s->hstage));
+        s->hstage = nullptr;
+        s->hstage_cap = 0;
+    }
+    const uint64_t cap = std::max<uint64_t>(floats, 4096);
+    SV_HIP(hipHostMalloc(&s->hstage, cap * sizeof(float), hipHostMallocDefault));
+    s->hstage_cap = cap;
+}
+
+constexpr int kAmEvents = 16;
+static_assert(sizeof(sv_state_s::events) / sizeof(hipEvent_t) == kAmEvents, "one event per chunk");
+
+void ensure_events(sv_state s)
+{
+    for (int i = 0; i < kAmEvents; ++i)
+        if (!s->events[i]) SV_HIP(hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming));
+}
+
 // copy `doubles` results from dout to hout and wait
 void fetch(sv_state s, uint64_t doubles)
 {
@@ -413,6 +436,9 @@ sv_status sv_free(sv_state s)
         if (s->scratch) (void)hipFree(s->scratch);
         if (s->dout) (void)hipFree(s->dout);
         if (s->hout) (void)hipHostFree(s->hout);
+        if (s->hstage) (void)hipHostFree(s->hstage);
+        for (hipEvent_t e : s->events)
+            if (e) (void)hipEventDestroy(e);
         if (s->dterms) (void)hipFree(s->dterms);
         if (s->dfused) (void)hipFree(s->dfused);
         delete s;
@@ -1107,7 +1133,6 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
             std::vector<Deriv> d;                    // shared product: its X_k
         };
         std::vector<Launch> launches;
-        std::vector<float> frags;
         std::vector<Sp16> es;
         std::vector<cd> xs;
         const std::vector<GateBlock> blocks = plan_gate_blocks(masks, lb);
@@ -1137,6 +1162,8 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
             embed16(g, oi.k, &L.tl[2 * t], L.cm[t], false, Ed.data());
             sparse16(Ed.data(), out);
         };
+        // structure of every launch (its matrices come later, chunk by chunk)
+        size_t n_frag = 0, n_es = 0;
         for (int bi = (int)blocks.size() - 1; bi >= 0; --bi) {
             const GateBlock& gb = blocks[bi];
             uint64_t used = 0;
@@ -1169,17 +1196,26 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
             }
             L.nfr = rows_differ ? B : 1;
             L.recur = rows_differ || B <= kRecurRows;
-            L.frag_at = frags.size() / 1024;
+            L.frag_at = n_frag;
+            n_frag += L.nfr;
             for (int rl = 0; rl < L.nfr; ++rl) {
-                const double* prow = params + (rows_differ ? rl * params_batch_stride : 0);
-                const size_t ea = es.size();
-                L.e_at.push_back(ea);
-                es.resize(ea + ng);
+                L.e_at.push_back(n_es);
+                n_es += ng;
+            }
+            launches.push_back(std::move(L));
+        }
+        es.resize(n_es);
+        // the embedded gates E of launch L and its products' fragments
+        auto form_products = [&](const Launch& L, float* frag) {
+            const int ng = (int)L.gb->gates.size();
+            for (int rl = 0; rl < L.nfr; ++rl) {
+                const double* prow = params + (L.nfr > 1 ? rl * params_batch_stride : 0);
+                const size_t ea = L.e_at[rl];
                 // U_B = E_last ... E_first; the kernel applies M = U_B^*
                 for (int q = 0; q < 256; ++q) U[q] = (q % 17 == 0) ? 1.0 : 0.0;
                 for (int t = 0; t < ng; ++t) {
-                    const sv_op& op = ops[gb.gates[t]];
-                    const OpInfo& oi = info[gb.gates[t]];
+                    const sv_op& op = ops[L.gb->gates[t]];
+                    const OpInfo& oi = info[L.gb->gates[t]];
                     cd m[16];
                     op_matrix(op, oi, prow, m);
                     embed16(m, oi.k, &L.tl[2 * t], L.cm[t], true, Ed.data());
@@ -1189,12 +1225,9 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                 }
                 for (int r = 0; r < 16; ++r)
                     for (int c = 0; c < 16; ++c) T1[r * 16 + c] = std::conj(U[c * 16 + r]);
-                const size_t fo = frags.size();
-                frags.resize(fo + 1024);
-                mfma_fragments(T1.data(), &frags[fo]);
+                mfma_fragments(T1.data(), frag + (size_t)rl * 1024);
             }
-            launches.push_back(std::move(L));
-        }
+        };
         // X_k = W_k (dG_k G_k^*) W_k^*, W_k the gates after k (host, FP64)
         auto form_derivatives = [&] {
             for (Launch& L : launches) {
@@ -1223,19 +1256,23 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         const uint64_t spart_max = std::max<uint64_t>(1, adj_mfma_part_doubles(grid, B));
         const uint64_t s_total = (uint64_t)launches.size() * B * 1024;
         const uint64_t red = std::max<uint64_t>(inner_parts(s->n, B), drift_parts(s->n, B));
-        const uint64_t frag_doubles = (frags.size() + 1) / 2 + 2;
+        const uint64_t frag_doubles = n_frag * 512 + 2;
         const uint64_t frag_at = (spart_max + red + 1) & ~1ull;
         ensure_scratch(s, frag_at + frag_doubles);
+        ensure_hstage(s, n_frag * 1024);
         double* spart = s->scratch;
         double* rscratch = s->scratch + spart_max;
         float* dfrag = reinterpret_cast<float*>(s->scratch + frag_at);
-        if (!frags.empty())
-            SV_HIP(hipMemcpyAsync(dfrag, frags.data(), frags.size() * sizeof(float), hipMemcpyHostToDevice, s->stream));
-        const uint64_t nout = std::max<uint64_t>(s_total, 1) + 3ull * B;
+        float* hfrag = s->hstage;
+        const uint64_t s_room = std::max<uint64_t>(s_total, 1);
+        const uint64_t nout = s_room + 3ull * B;
         ensure_dout(s, nout + 2ull * B);
         double* d_s = s->dout;
-        double* d_loss = s->dout + std::max<uint64_t>(s_total, 1);
+        double* d_loss = s->dout + s_room;
         double* d_drift = d_loss + 2ull * B;
+        const double* h_s = s->hout;
+        const double* h_loss = s->hout + s_room;
+        const double* h_drift = h_loss + 2ull * B;
 
         const Rows prow{s->psi, s->psi, B, B, s->N};
         const Rows lrow{lam, lam, B, B, s->N};
@@ -1243,72 +1280,93 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         else launch_apply_pauli_sum(prow, lrow, s->n, dterms, n_obs, dcoeff, s->stream, z_only_terms(obs, n_obs));
         launch_inner(prow, lrow, s->n, rscratch, d_loss, s->stream);
 
-        for (size_t li = 0; li < launches.size(); ++li) {
-            const Launch& L = launches[li];
-            AdjMfmaLaunch a{};
-            a.psi = prow;
-            a.lam = lrow;
-            a.N = s->N;
-            for (int i = 0; i < 4; ++i) a.q[i] = L.q[i];
-            a.frag = dfrag + L.frag_at * 1024;
-            a.frag_stride = L.nfr > 1 ? 1024 : 0;
-            a.spart = spart;
-            a.grid = grid;
-            launch_adj_mfma(a, B, d_s + li * B * 1024, s->stream);
+        // chunks of launches: the host forms a chunk's products while the
+        // GPU runs the one before, and traces a chunk's S as soon as its copy
+        // is back
+        const int nl = (int)launches.size();
+        const int n_chunks = std::max(1, std::min(kAmEvents, (nl + 3) / 4));
+        ensure_events(s);
+        auto chunk_begin = [&](int c) { return (int)((int64_t)nl * c / n_chunks); };
+        for (int c = 0; c < n_chunks; ++c) {
+            const int l0 = chunk_begin(c), l1 = chunk_begin(c + 1);
+            if (l0 == l1) continue;
+            for (int li = l0; li < l1; ++li) form_products(launches[li], hfrag + launches[li].frag_at * 1024);
+            const size_t f0 = launches[l0].frag_at, f1 = launches[l1 - 1].frag_at + launches[l1 - 1].nfr;
+            SV_HIP(hipMemcpyAsync(dfrag + f0 * 1024, hfrag + f0 * 1024, (f1 - f0) * 1024 * sizeof(float),
+                                  hipMemcpyHostToDevice, s->stream));
+            for (int li = l0; li < l1; ++li) {
+                const Launch& L = launches[li];
+                AdjMfmaLaunch a{};
+                a.psi = prow;
+                a.lam = lrow;
+                a.N = s->N;
+                for (int i = 0; i < 4; ++i) a.q[i] = L.q[i];
+                a.frag = dfrag + L.frag_at * 1024;
+                a.frag_stride = L.nfr > 1 ? 1024 : 0;
+                a.spart = spart;
+                a.grid = grid;
+                launch_adj_mfma(a, B, d_s + (size_t)li * B * 1024, s->stream);
+            }
+            SV_HIP(hipMemcpyAsync(s->hout + (size_t)l0 * B * 1024, d_s + (size_t)l0 * B * 1024,
+                                  (size_t)(l1 - l0) * B * 1024 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+            SV_HIP(hipEventRecord(s->events[c], s->stream));
         }
         launch_drift(prow, s->n, rscratch, d_drift, s->stream);
-        SV_HIP(hipMemcpyAsync(s->hout, s->dout, nout * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        SV_HIP(hipMemcpyAsync(s->hout + s_room, d_loss, 3ull * B * sizeof(double), hipMemcpyDeviceToHost,
+                              s->stream));
         form_derivatives();        // while the sweeps run
-        SV_HIP(hipStreamSynchronize(s->stream));
-        const double* h_s = s->hout;
-        const double* h_loss = s->hout + std::max<uint64_t>(s_total, 1);
-        const double* h_drift = h_loss + 2ull * B;
         if (n_params > 0) std::fill(grad_out, grad_out + (size_t)B * n_params, 0.0);
         // derivatives in launch (reverse block) order, then gate order
         std::vector<cd> S(256);
-        for (size_t li = 0; li < launches.size(); ++li) {
-            const Launch& L = launches[li];
-            const int ng = (int)L.gb->gates.size();
-            for (int r = 0; r < B; ++r) {
-                const double* sr = h_s + (li * B + r) * 1024;     // S_real[32][32]
-                for (int b = 0; b < 16; ++b)
-                    for (int a2 = 0; a2 < 16; ++a2)
-                        S[b * 16 + a2] = cd(sr[b * 32 + a2] + sr[(16 + b) * 32 + 16 + a2],
-                                            sr[(16 + b) * 32 + a2] - sr[b * 32 + 16 + a2]);
-                double* g = grad_out + (size_t)r * n_params;
-                if (!L.recur) {
-                    for (const Deriv& dv : L.d) {
-                        const cd* X = &xs[dv.x * 256];
-                        double tr = 0.0;       // Re Tr(X S)
+        for (int c = 0; c < n_chunks; ++c) {
+            const int l0 = chunk_begin(c), l1 = chunk_begin(c + 1);
+            if (l0 == l1) continue;
+            SV_HIP(hipEventSynchronize(s->events[c]));
+            for (int li = l0; li < l1; ++li) {
+                const Launch& L = launches[li];
+                const int ng = (int)L.gb->gates.size();
+                for (int r = 0; r < B; ++r) {
+                    const double* sr = h_s + ((size_t)li * B + r) * 1024;     // S_real[32][32]
+                    for (int b = 0; b < 16; ++b)
                         for (int a2 = 0; a2 < 16; ++a2)
-                            for (int b = 0; b < 16; ++b) {
-                                const cd x = X[a2 * 16 + b], y = S[b * 16 + a2];
+                            S[b * 16 + a2] = cd(sr[b * 32 + a2] + sr[(16 + b) * 32 + 16 + a2],
+                                                sr[(16 + b) * 32 + a2] - sr[b * 32 + 16 + a2]);
+                    double* g = grad_out + (size_t)r * n_params;
+                    if (!L.recur) {
+                        for (const Deriv& dv : L.d) {
+                            const cd* X = &xs[dv.x * 256];
+                            double tr = 0.0;       // Re Tr(X S)
+                            for (int a2 = 0; a2 < 16; ++a2)
+                                for (int b = 0; b < 16; ++b) {
+                                    const cd x = X[a2 * 16 + b], y = S[b * 16 + a2];
+                                    tr += x.real() * y.real() - x.imag() * y.imag();
+                                }
+                            g[dv.param] += 2.0 * tr;
+                        }
+                        continue;
+                    }
+                    const double* prow_r = params + (L.nfr > 1 ? r * params_batch_stride : 0);
+                    const size_t ea = L.e_at[L.nfr > 1 ? r : 0];
+                    for (int t = ng - 1; t >= 0; --t) {       // S holds S_t = W_t^* S W_t
+                        const int gi = L.gb->gates[t];
+                        for (int d = 0; d < info[gi].np; ++d) {
+                            gate_derivative(L, t, prow_r, d, Gs);
+                            double tr = 0.0;       // Re Tr(G S_t)
+                            for (int k = 0; k < Gs.n; ++k) {
+                                const cd x = Gs.v[k], y = S[Gs.c[k] * 16 + Gs.r[k]];
                                 tr += x.real() * y.real() - x.imag() * y.imag();
                             }
-                        g[dv.param] += 2.0 * tr;
-                    }
-                    continue;
-                }
-                const double* prow = params + (L.nfr > 1 ? r * params_batch_stride : 0);
-                const size_t ea = L.e_at[L.nfr > 1 ? r : 0];
-                for (int t = ng - 1; t >= 0; --t) {       // S holds S_t = W_t^* S W_t
-                    const int gi = L.gb->gates[t];
-                    for (int d = 0; d < info[gi].np; ++d) {
-                        gate_derivative(L, t, prow, d, Gs);
-                        double tr = 0.0;       // Re Tr(G S_t)
-                        for (int k = 0; k < Gs.n; ++k) {
-                            const cd x = Gs.v[k], y = S[Gs.c[k] * 16 + Gs.r[k]];
-                            tr += x.real() * y.real() - x.imag() * y.imag();
+                            g[ops[gi].param[d]] += 2.0 * tr;
                         }
-                        g[ops[gi].param[d]] += 2.0 * tr;
-                    }
-                    if (t > 0) {
-                        sp_right(S.data(), es[ea + t], T1.data());
-                        sp_adj_left(es[ea + t], T1.data(), S.data());
+                        if (t > 0) {
+                            sp_right(S.data(), es[ea + t], T1.data());
+                            sp_adj_left(es[ea + t], T1.data(), S.data());
+                        }
                     }
                 }
             }
         }
+        SV_HIP(hipStreamSynchronize(s->stream));
         for (int r = 0; r < B; ++r) {
             if (loss_out) loss_out[r] = h_loss[2 * r];
             if (drift_out) drift_out[r] = std::sqrt(std::max(0.0, h_drift[r]));

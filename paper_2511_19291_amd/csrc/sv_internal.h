@@ -289,6 +289,9 @@ struct sv_state_s {
     double* dout = nullptr;         // device small outputs
     size_t dout_cap = 0;            // doubles
     double* hout = nullptr;         // pinned host mirror of dout
+    float* hstage = nullptr;        // pinned host staging for uploads
+    size_t hstage_cap = 0;          // floats
+    hipEvent_t events[16] = {};     // completion marks of a call's chunks (created on first use)
     void* dterms = nullptr;         // device copy of observable terms
     size_t dterms_cap = 0;
     void* dfused = nullptr;         // device copy of fused block matrices
