@@ -326,7 +326,7 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         "params": n_par, "forward_ms": round(fwd_ms, 2), "forward_fused_ms": round(fwd_fused_ms, 2),
         "train_step_ms": round(fwd_fused_ms + blocked["mfma4"]["backward_ms"], 2),
         "backward_ms": round(default_ms, 2),
-        "backward_kind": "matrix-core blocks of 4 qubits (the autograd default from 22 qubits)",
+        "backward_kind": "matrix-core blocks of 4 qubits (the autograd default from 13 qubits)",
         "backward_over_forward": round(default_ms / fwd_ms, 3),
         "backward_per_gate_ms": round(bwd_ms, 2), "per_gate_over_forward": round(bwd_ms / fwd_ms, 3),
         "param_shift_ms_est": round(shift_ms, 1),
