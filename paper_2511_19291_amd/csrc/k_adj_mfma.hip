@@ -34,7 +34,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kAmThreads = 256;
 constexpr int kAmWaves = kAmThreads / 64;
-constexpr int kTp = 33;            // LDS tile pitch (floats): [32 rows][33]
+constexpr int kTp = 34;            // LDS tile pitch (floats): [32 rows][34]; 2 mod 32 keeps the
+                                   // correlation's reads (16 rows x 2 columns per half-wave) on distinct banks
 
 // A wave's own LDS writes complete before its following reads (and its
 // reads before its following writes): wait for the LDS counter and keep the
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
     static_assert(sizeof(tiles) >= kAmWaves * 1024 * sizeof(double), "S parts fit the tiles");
     float (*tp)[32][kTp] = tiles[0];
     float (*tl)[32][kTp] = tiles[1];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);     // uniform: groups and bases are scalar
     const int h = lane >> 5, cu = lane & 31;
     const int row = blockIdx.y;
     float2* psi = am_row(a.psi, row);
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
 #pragma unroll
     for (int s = 0; s < 16; ++s) fr[s] = a.frag[(size_t)row * a.frag_stride + lane * 16 + s];
     const int q0 = a.q[0], q1 = a.q[1], q2 = a.q[2], q3 = a.q[3];
-    f64x4 s00 = {0, 0, 0, 0}, s01 = {0, 0, 0, 0}, s10 = {0, 0, 0, 0}, s11 = {0, 0, 0, 0};
+    f64x4 s00 = {0, 0, 0, 0}, s10 = {0, 0, 0, 0}, s11 = {0, 0, 0, 0};
     const uint64_t groups = a.N >> 9;          // 32 columns of 16 amplitudes
     const uint64_t stride = (uint64_t)gridDim.x * kAmWaves;
     // column base of a group for column c (zeros at the block's qubits)
@@ -87,8 +89,13 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
         u = ((u >> q2) << (q2 + 1)) | (u & ((1ull << q2) - 1));
         return ((u >> q3) << (q3 + 1)) | (u & ((1ull << q3) - 1));
     };
-    // S_real[16I + i][16J + j] += sum_k tp[16I + i][k] tl[16J + j][k]
-    // (A lane holds row lane % 16 of step column lane / 16)
+    // Three real products give S (Gauss): with the tile rows 0..15 the real
+    // parts and 16..31 the imaginary parts,
+    //   s00 += Re psi Re lam^T,  s11 += Im psi Im lam^T,
+    //   s10 += (Re psi + Im psi)(Re lam - Im lam)^T,
+    // so Re S = s00 + s11 and Im S = s10 - s00 + s11. The sums of two FP32
+    // values are exact in FP64 (A lane holds row lane % 16 of step column
+    // lane / 16).
     auto correlate = [&]() {
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
@@ -96,19 +103,8 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             const double a0 = tp[w][ii][kk], a1 = tp[w][16 + ii][kk];
             const double b0 = tl[w][ii][kk], b1 = tl[w][16 + ii][kk];
             s00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, s00, 0, 0, 0);
-            s01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, s01, 0, 0, 0);
-            s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, s10, 0, 0, 0);
             s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
-        }
-    };
-    // un-apply: y = M x for both vectors (step s: component s & 1 of
-    // amplitude 8h + (s >> 1); output register r: component r & 1 of
-    // amplitude 8h + (r >> 1))
-    auto unapply = [&](const float2 (&x)[8], const float2 (&l)[8], f32x16& yp, f32x16& yl) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            yp = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? x[s >> 1].y : x[s >> 1].x, yp, 0, 0, 0);
-            yl = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], (s & 1) ? l[s >> 1].y : l[s >> 1].x, yl, 0, 0, 0);
+            s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0 + a1, b0 - b1, s10, 0, 0, 0);
         }
     };
     uint64_t grp = (uint64_t)blockIdx.x * kAmWaves + w;
@@ -160,22 +156,29 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
                 tlw[ti[k] + 16 * kTp] = e.y;
             }
             wave_lds_sync();
-            float2 x[8], l[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                x[t] = make_float2(tp[w][8 * h + t][cu], tp[w][16 + 8 * h + t][cu]);
-                l[t] = make_float2(tl[w][8 * h + t][cu], tl[w][16 + 8 * h + t][cu]);
-            }
             correlate();
-            wave_lds_sync();
-            f32x16 yp = {0}, yl = {0};
-            unapply(x, l, yp, yl);
+            // un-apply in place, one vector after the other: a lane's inputs
+            // and outputs are the same tile entries (rows 8h + t and
+            // 16 + 8h + t of column cu), and the wave's LDS accesses run in order
+            f32x16 y = {0};
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tp[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                                                         0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                tp[w][8 * h + t][cu] = yp[2 * t];
-                tp[w][16 + 8 * h + t][cu] = yp[2 * t + 1];
-                tl[w][8 * h + t][cu] = yl[2 * t];
-                tl[w][16 + 8 * h + t][cu] = yl[2 * t + 1];
+                tp[w][8 * h + t][cu] = y[2 * t];
+                tp[w][16 + 8 * h + t][cu] = y[2 * t + 1];
+            }
+            y = f32x16{0};
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tl[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                                                         0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                tl[w][8 * h + t][cu] = y[2 * t];
+                tl[w][16 + 8 * h + t][cu] = y[2 * t + 1];
             }
             wave_lds_sync();
 #pragma unroll
@@ -186,34 +189,30 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             wave_lds_sync();
         }
     } else {
-        uint64_t offa[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-            offa[t] = ((uint64_t)(t & 1) << q0) | ((uint64_t)((t >> 1) & 1) << q1) |
-                      ((uint64_t)((t >> 2) & 1) << q2) | ((uint64_t)h << q3);
-        // the next group's columns are loaded while this group's products
-        // run; each wave works through its own groups (its LDS tiles are its
-        // own, so only the wave itself has to be in step between writing and
-        // reading them)
+        // with every block qubit >= 5 the 32 columns of a group are 32
+        // consecutive amplitudes: column(grp, cu) = column(grp, 0) | cu, so
+        // amplitude 8h + t of a lane's column sits at a scalar base (the
+        // group's, plus t's block bits) plus one per-lane offset
+        const uint64_t lh = ((uint64_t)h << q3) | (uint64_t)cu;
+        auto toff = [&](int t) {
+            return ((uint64_t)(t & 1) << q0) | ((uint64_t)((t >> 1) & 1) << q1) | ((uint64_t)((t >> 2) & 1) << q2);
+        };
+        // the next group's columns are loaded (into the same registers) while
+        // this group's products run: the products read their inputs from the
+        // LDS tiles. Each wave works through its own groups (its LDS tiles are
+        // its own, so only the wave itself has to be in step between writing
+        // and reading them).
         float2 x[8], l[8];
-        {
-            const uint64_t u0 = column(grp, cu);
+        if (grp < groups) {
+            const float2* pb = psi + column(grp, 0);
+            const float2* lb = lam + column(grp, 0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                x[t] = grp < groups ? psi[u0 | offa[t]] : make_float2(0.f, 0.f);
-                l[t] = grp < groups ? lam[u0 | offa[t]] : make_float2(0.f, 0.f);
+                x[t] = pb[toff(t) + lh];
+                l[t] = lb[toff(t) + lh];
             }
         }
         for (; grp < groups; grp += stride) {
-            const uint64_t u = column(grp, cu);
-            const uint64_t gn = grp + stride;
-            const uint64_t un = column(gn, cu);
-            float2 xn[8], ln[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                xn[t] = gn < groups ? psi[un | offa[t]] : make_float2(0.f, 0.f);
-                ln[t] = gn < groups ? lam[un | offa[t]] : make_float2(0.f, 0.f);
-            }
             // transpose: tile row = real index (amplitude 8h + t: row 8h + t
             // real, row 16 + 8h + t imaginary), tile column = column of the group
 #pragma unroll
@@ -223,21 +222,38 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
                 tl[w][8 * h + t][cu] = l[t].x;
                 tl[w][16 + 8 * h + t][cu] = l[t].y;
             }
+            const uint64_t gn = grp + stride;
+            if (gn < groups) {
+                const float2* pn = psi + column(gn, 0);
+                const float2* ln = lam + column(gn, 0);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    x[t] = pn[toff(t) + lh];
+                    l[t] = ln[toff(t) + lh];
+                }
+            }
             wave_lds_sync();
             correlate();
-            wave_lds_sync();
-            f32x16 yp = {0}, yl = {0};
-            unapply(x, l, yp, yl);
+            // un-apply y = M x, one vector after the other (step s: component
+            // s & 1 of amplitude 8h + (s >> 1), tile row 16 (s & 1) + 8h + (s >> 1);
+            // output register r: component r & 1 of amplitude 8h + (r >> 1))
+            float2* pb = psi + column(grp, 0);
+            float2* lb = lam + column(grp, 0);
+            f32x16 y = {0};
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                psi[u | offa[t]] = make_float2(yp[2 * t], yp[2 * t + 1]);
-                lam[u | offa[t]] = make_float2(yl[2 * t], yl[2 * t + 1]);
-            }
+            for (int s = 0; s < 16; ++s)
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tp[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                                                         0);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                x[t] = xn[t];
-                l[t] = ln[t];
-            }
+            for (int t = 0; t < 8; ++t) pb[toff(t) + lh] = make_float2(y[2 * t], y[2 * t + 1]);
+            y = f32x16{0};
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tl[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                                                         0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) lb[toff(t) + lh] = make_float2(y[2 * t], y[2 * t + 1]);
+            wave_lds_sync();        // this group's tile reads are done before the next group's writes
         }
     }
     // the workgroup's S_real (32 x 32, row-major): the waves' parts summed in
@@ -251,9 +267,12 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
     for (int r = 0; r < 4; ++r) {
         const int ri = 4 * r + (lane >> 4);
         double* rw = red + w * 1024;
+        // S_real in its four-quadrant form: [Re psi Re lam^T, Re psi Im lam^T;
+        // Im psi Re lam^T, Im psi Im lam^T], here with the lower-left block
+        // holding Im S + upper-right (so that Im S = lower-left - upper-right)
         rw[ri * 32 + col] = s00[r];
-        rw[ri * 32 + 16 + col] = s01[r];
-        rw[(16 + ri) * 32 + col] = s10[r];
+        rw[ri * 32 + 16 + col] = 0.0;
+        rw[(16 + ri) * 32 + col] = s10[r] - s00[r] + s11[r];
         rw[(16 + ri) * 32 + 16 + col] = s11[r];
     }
     __syncthreads();
