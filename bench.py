@@ -229,6 +229,32 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     stream = torch.cuda.current_stream()
     res = {}
 
+    # -- one dense U3 sweep on every target of the n-qubit state (16 B per
+    # amplitude each), four launches per target after one untimed
+    st = sv.State(n)
+    st.reset()
+    per_t = []
+    for t in range(n):
+        b = C._Builder(n)
+        b.gate("u3", [t], values=[0.3 + 0.1 * t, 1.1, 2.3])
+        c1 = b.build(f"u3_t{t}")
+        tab = sv.OpTable(c1.ops)
+        p1 = np.ascontiguousarray(c1.params)
+        st.run_ops(tab, 0, 1, p1)
+        ms = _timed_ms(lambda: [st.run_ops(tab, 0, 1, p1) for _ in range(4)], stream) / 4
+        per_t.append(16 * (1 << n) / (ms / 1e3) / 1e9)
+    st.free()
+    del st
+    torch.cuda.empty_cache()
+    srt = sorted(per_t)
+    res["per_target_u3"] = {
+        "workload": f"one U3 sweep of the {n}-qubit complex64 state on each target 0..{n - 1}; 16 B/amplitude",
+        "GBps": [round(x, 1) for x in per_t],
+        "min_GBps": round(srt[0], 1), "median_GBps": round(srt[len(srt) // 2], 1),
+        "min_frac_of_8TBps": round(srt[0] / 8000.0, 3), "median_frac_of_8TBps": round(srt[len(srt) // 2] / 8000.0, 3),
+        "argmin_target": int(np.argmin(per_t)),
+    }
+
     # -- fused blocks: the same 30-qubit brickwork, and the 32-qubit instance
     fused = {}
     for nq, seed, with_plain in ((n, 2, False), (32, 3, True)):
@@ -472,6 +498,17 @@ def shots_extra(st, circ, blocks, stream) -> dict:
     }
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(circ, seconds: float) -> dict:
     """The CPU oracle, as it is, on a bounded sample of the same workload: the
     same n-qubit complex128 state and the circuit's first gates, as many as
@@ -498,6 +535,7 @@ def cpu_baseline(circ, seconds: float) -> dict:
         "value": round(done / dt, 4),
         "unit": "gates/s",
         "cores": threads,
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": f"first {done} gates of the {n}-qubit workload on a complex128 state "
                   f"({dt:.1f} s; state init {t_init:.1f} s not counted)",
