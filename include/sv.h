@@ -176,6 +176,16 @@ typedef struct sv_block {
  * conditions), SV_ERR_QUBIT_*, SV_ERR_HIP. */
 sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_blocks, int mode);
 
+/* sv_apply_fused with a matrix per batch row (Alg. 1 per row, e.g. a fused
+ * input encoding whose angles differ between rows): each block's matrix
+ * points to batch consecutive 2^k x 2^k complex128 matrices, row r's at
+ * matrix + r * 2 * 4^k doubles; row r of the state is swept with its own.
+ * The blocks take the same target lists on every row.
+ * Matrix-core modes only (SV_FUSED_FP32_MFMA, SV_FUSED_BF16X3), k <= 5,
+ * n >= 10. Errors: as sv_apply_fused, plus SV_ERR_UNSUPPORTED for
+ * SV_FUSED_VALU or k = 6. */
+sv_status sv_apply_fused_rows(sv_state s, const sv_block* blocks, int n_blocks, int mode);
+
 /* Host-only fusion planner (no GPU work): group the gates of a circuit, in
  * order, into blocks of at most max_k qubits (controls count as qubits) and
  * multiply each block's gates into one complex128 matrix. Gates on disjoint

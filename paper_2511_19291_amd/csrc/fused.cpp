@@ -378,7 +378,12 @@ extern "C" sv_status sv_fuse_plan(int n_qubits, const sv_op* ops, int n_ops, con
     }
 }
 
-extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_blocks, int mode)
+namespace {
+
+// sv_apply_fused and sv_apply_fused_rows: with per_row, each block's matrix
+// holds one 2^k x 2^k matrix per batch row (row r at matrix + r 2 4^k
+// doubles), and each row's sweep reads its own.
+sv_status apply_fused_impl(sv_state s, const sv_block* blocks, int n_blocks, int mode, bool per_row)
 {
     try {
         need(s != nullptr && s->psi != nullptr, SV_ERR_INVALID_ARGUMENT, "null state");
@@ -386,6 +391,8 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
              SV_ERR_INVALID_ARGUMENT, "unknown fused mode");
         need(n_blocks >= 0 && (n_blocks == 0 || blocks), SV_ERR_INVALID_ARGUMENT, "blocks is NULL");
         const bool mfma = mode != SV_FUSED_VALU;
+        if (per_row) need(mfma, SV_ERR_UNSUPPORTED, "per-row matrices run in the MFMA modes only");
+        const int nmat = per_row ? s->batch : 1;
         for (int i = 0; i < n_blocks; ++i) {
             const sv_block& b = blocks[i];
             need(b.k >= 1 && b.k <= SV_MAX_FUSED_TARGETS, SV_ERR_INVALID_ARGUMENT, "block k must be 1..6");
@@ -398,6 +405,7 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
             }
             if (mfma) need(s->n >= 10, SV_ERR_INVALID_ARGUMENT, "the MFMA fused modes need n >= 10");
             if (b.k == 6) {
+                need(!per_row, SV_ERR_UNSUPPORTED, "per-row matrices take blocks of at most five qubits");
                 need(mode == SV_FUSED_BF16X3, SV_ERR_UNSUPPORTED, "six-qubit blocks run in the BF16X3 mode only");
                 need((seen & 63) == 0, SV_ERR_UNSUPPORTED, "six-qubit blocks need every target >= 6");
                 need(s->n >= 12 && s->n <= 32, SV_ERR_UNSUPPORTED, "six-qubit blocks need 12 <= n <= 32");
@@ -409,7 +417,7 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
                                  : (size_t)32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t) + 8 * sizeof(int);
         std::vector<size_t> off(n_blocks + 1, 0);
         for (int i = 0; i < n_blocks; ++i)
-            off[i + 1] = off[i] + ((blocks[i].k == 6 ? fused6_matrix_bytes() : per5) + 15) / 16 * 16;
+            off[i + 1] = off[i] + (size_t)nmat * (((blocks[i].k == 6 ? fused6_matrix_bytes() : per5) + 15) / 16 * 16);
         std::vector<unsigned char> host(off[n_blocks], 0);
         std::vector<std::array<int, 6>> tgt(n_blocks);
         for (int i = 0; i < n_blocks; ++i) {
@@ -442,13 +450,15 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
                     if (!((used >> q) & 1)) { t5[kk++] = q; used |= 1ull << q; }
                 const int pad = 5 - k;
                 for (int j = 0; j < 5; ++j) tgt[i][j] = t5[j];
-                float* A = reinterpret_cast<float*>(dst);
+                for (int mi = 0; mi < nmat; ++mi) {
+                const double* bm = b.matrix + (size_t)mi * 2 * D * D;
+                float* A = reinterpret_cast<float*>(dst + (size_t)mi * per5);
                 for (int r = 0; r < 32; ++r)
                     for (int c = 0; c < 32; ++c) {
                         // M5 = M (x) I_{2^pad}
                         cd v = 0.0;
                         if ((r & ((1 << pad) - 1)) == (c & ((1 << pad) - 1))) {
-                            const double* e = b.matrix + 2 * ((size_t)(r >> pad) * D + (c >> pad));
+                            const double* e = bm + 2 * ((size_t)(r >> pad) * D + (c >> pad));
                             v = cd(e[0], e[1]);
                         }
                         const float re = (float)v.real(), im = (float)v.imag();
@@ -464,6 +474,7 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
                         L[q] = A[q] - hi;
                         A[q] = hi;
                     }
+                }
                 }
             } else {
                 float2* m = reinterpret_cast<float2*>(dst);
@@ -503,6 +514,7 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
                 for (int j = 0; j < 5; ++j) f.targets[j] = tgt[i][j];
                 f.mode = mode;
                 f.amat = reinterpret_cast<const float*>(p);
+                f.amat_stride = per_row ? (uint32_t)(per5 / sizeof(float)) : 0u;
                 launch_fused_mfma(f, s->stream);
             } else {
                 FusedValuLaunch f{};
@@ -523,4 +535,16 @@ extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_bl
     } catch (...) {
         return SV_ERR_INVALID_ARGUMENT;
     }
+}
+
+}  // namespace
+
+extern "C" sv_status sv_apply_fused(sv_state s, const sv_block* blocks, int n_blocks, int mode)
+{
+    return apply_fused_impl(s, blocks, n_blocks, mode, false);
+}
+
+extern "C" sv_status sv_apply_fused_rows(sv_state s, const sv_block* blocks, int n_blocks, int mode)
+{
+    return apply_fused_impl(s, blocks, n_blocks, mode, true);
 }

@@ -47,6 +47,7 @@ struct KFused {
     int bit_row[10];           // row-index contribution of tile bit b (0 if a column bit)
     int bit_col[10];           // column-index contribution of tile bit b (0 if a row bit)
     const float* amat;         // FP32: A~[64][64]; BF16X3: hi A~[64][64] then lo A~[64][64] (as float)
+    uint32_t amat_stride;      // floats between batch rows' matrices (0: one matrix for every row)
 };
 
 __device__ __forceinline__ bf16x8 to_bf16(const float (&x)[8])
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
     const int wave = threadIdx.x >> 6;
     float* xs = lds + wave * kWaveLds;
     float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+    const float* am = a.amat + (size_t)blockIdx.y * a.amat_stride;      // this row's matrix
     const int h = lane >> 5, c32 = lane & 31;
 
     // per-lane part of the tile index L = 2*lane + 128*i (+ e): bits 1..6
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int s = 0; s < 32; ++s) afr[b][s] = a.amat[(32 * b + c32) * 64 + 2 * s + h];
+            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -111,8 +113,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
                 float th[8], tl[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    th[q] = a.amat[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                    tl[q] = a.amat[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    th[q] = am[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    tl[q] = am[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
                 }
                 ahi[b][s] = to_bf16(th);
                 alo[b][s] = to_bf16(tl);
@@ -222,6 +224,7 @@ struct KFusedDirect {
     int pos[10];               // tile bits ascending: 0..4 and the targets
     uint32_t toff[5];          // 1 << target j (T[0] = most significant row bit)
     const float* amat;
+    uint32_t amat_stride;      // floats between batch rows' matrices (0: shared)
 };
 
 __device__ __forceinline__ uint32_t row_off(const KFusedDirect& a, int r)
@@ -240,6 +243,7 @@ __global__ __launch_bounds__(256) void k_fused_direct(KFusedDirect a)
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5, c32 = lane & 31;
     float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+    const float* am = a.amat + (size_t)blockIdx.y * a.amat_stride;      // this row's matrix
 
     uint32_t ro_in[16], ro_out[16];
 #pragma unroll
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(256) void k_fused_direct(KFusedDirect a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int s = 0; s < 32; ++s) afr[b][s] = a.amat[(32 * b + c32) * 64 + 2 * s + h];
+            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -263,8 +267,8 @@ __global__ __launch_bounds__(256) void k_fused_direct(KFusedDirect a)
                 float th[8], tl[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    th[q] = a.amat[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                    tl[q] = a.amat[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    th[q] = am[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    tl[q] = am[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
                 }
                 ahi[b][s] = to_bf16(th);
                 alo[b][s] = to_bf16(tl);
@@ -341,6 +345,7 @@ struct KFusedWide {
     int pos[11];               // tile bits ascending: 0..5 and the targets
     uint32_t toff[5];
     const float* amat;
+    uint32_t amat_stride;      // floats between batch rows' matrices (0: shared)
 };
 
 template <int MODE>
@@ -350,6 +355,7 @@ __global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5, c32 = lane & 31;
     float2* psi = a.psi + (uint64_t)blockIdx.y * a.N;
+    const float* am = a.amat + (size_t)blockIdx.y * a.amat_stride;      // this row's matrix
 
     auto roff = [&](int r) {
         uint32_t o = 0;
@@ -370,7 +376,7 @@ __global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int s = 0; s < 32; ++s) afr[b][s] = a.amat[(32 * b + c32) * 64 + 2 * s + h];
+            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -379,8 +385,8 @@ __global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
                 float th[8], tl[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    th[q] = a.amat[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                    tl[q] = a.amat[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    th[q] = am[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
+                    tl[q] = am[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
                 }
                 ahi[b][s] = to_bf16(th);
                 alo[b][s] = to_bf16(tl);
@@ -612,6 +618,7 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         for (int b = 0; b < 6; ++b) d.pos[b] = b;
         for (int b = 0; b < 5; ++b) d.pos[6 + b] = t5[b];
         d.amat = f.amat;
+        d.amat_stride = f.amat_stride;
         // persistent grid: two workgroups per CU are resident (registers)
         const uint64_t want = (d.n_tiles + 3) / 4;
         const uint64_t cap = (uint64_t)device_info().cu_count * 2;
@@ -637,6 +644,7 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         for (int b = 0; b < 5; ++b) d.pos[b] = b;
         for (int b = 0; b < 5; ++b) d.pos[5 + b] = t5[b];
         d.amat = f.amat;
+        d.amat_stride = f.amat_stride;
         // persistent grid: two workgroups per CU are resident (registers)
         const uint64_t want = (d.n_tiles + 3) / 4;
         const uint64_t cap = (uint64_t)device_info().cu_count * 2;
@@ -674,6 +682,7 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
             if (cols[c] == q) a.bit_col[b] = 1 << c;
     }
     a.amat = f.amat;
+    a.amat_stride = f.amat_stride;
     // persistent grid: eight single-wave workgroups per CU are resident (registers)
     const uint64_t want = (a.n_tiles + kWaves - 1) / kWaves;
     const uint64_t cap = (uint64_t)device_info().cu_count * 8;

@@ -106,6 +106,7 @@ def lib() -> C.CDLL:
         "sv_apply_gate": [vp, ip, C.c_int, ip, C.c_int, dp, i64, C.c_uint],
         "sv_run": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int],
         "sv_apply_fused": [vp, C.POINTER(SvBlock), C.c_int, C.c_int],
+        "sv_apply_fused_rows": [vp, C.POINTER(SvBlock), C.c_int, C.c_int],
         "sv_fuse_plan": [C.c_int, C.POINTER(SvOp), C.c_int, dp, C.c_int, C.c_int, C.POINTER(SvBlock),
                          C.c_int, dp, ip],
         "sv_expval_pauli": [vp, C.POINTER(SvPauliTerm), C.c_int, dp],
@@ -286,9 +287,11 @@ class State:
         """Apply the circuit with the gates whose angles are equal on every
         row fused into blocks of <= max_k qubits (``fuse_plan``, then
         ``apply_fused`` in ``mode``, FP32 MFMA by default); gates whose
-        angles differ between rows (an input encoding) run as per-gate
-        sweeps with per-row parameters. The gate order is kept: the circuit
-        is cut into maximal runs of row-shared and per-row gates."""
+        angles differ between rows (an input encoding) are fused the same
+        way with one matrix per row (``apply_fused_rows``) in the
+        matrix-core modes from 10 qubits, and run as per-gate sweeps with
+        per-row parameters otherwise. The gate order is kept: the circuit is
+        cut into maximal runs of row-shared and per-row gates."""
         from .circuits import Circuit
 
         if mode is None:
@@ -303,10 +306,20 @@ class State:
                 segs[-1][1].append(op)
             else:
                 segs.append((shared, [op]))
+        mfma = mode in (FUSED_FP32_MFMA, FUSED_BF16X3) and circuit.n >= 10
         for shared, ops in segs:
             sub = Circuit(circuit.n, ops, rows[0])
             if shared:
                 self.apply_fused(fuse_plan(sub, min(max_k, circuit.n), rows[0]), mode)
+            elif mfma and rows.shape[0] == self.batch and len(ops) > 1:
+                # the same plan on every row (it depends on the qubits only),
+                # each row's matrices from its own angles
+                plans = [fuse_plan(sub, min(max_k, 5, circuit.n), rows[r]) for r in range(self.batch)]
+                shape = [t for t, _ in plans[0]]
+                if any([t for t, _ in pl] != shape for pl in plans):
+                    raise RuntimeError("fusion plans differ between rows")
+                self.apply_fused_rows([(shape[b], np.stack([pl[b][1] for pl in plans]))
+                                       for b in range(len(shape))], mode)
             else:
                 self.run(sub, params=p)
         return self
@@ -328,6 +341,26 @@ class State:
             keep.append(buf)
             arr[i].matrix = _dptr(buf)
         check(lib().sv_apply_fused(self.h, arr, len(blocks), mode))
+        return self
+
+    def apply_fused_rows(self, blocks: Sequence[Tuple[Sequence[int], np.ndarray]],
+                         mode: int = FUSED_FP32_MFMA) -> "State":
+        """Blocks with one matrix per batch row: ``(targets, m)`` with m of
+        shape [batch, 2^k, 2^k] (``sv_apply_fused_rows``)."""
+        arr = (SvBlock * max(1, len(blocks)))()
+        keep = []
+        for i, (targets, m) in enumerate(blocks):
+            d = 1 << len(targets)
+            m = np.asarray(m)
+            if m.shape != (self.batch, d, d):
+                raise ValueError(f"block {i}: matrices of shape {m.shape}, expected {(self.batch, d, d)}")
+            arr[i].k = len(targets)
+            for j, t in enumerate(targets):
+                arr[i].targets[j] = t
+            buf = np.ascontiguousarray(m, dtype=np.complex128).view(np.float64).reshape(-1)
+            keep.append(buf)
+            arr[i].matrix = _dptr(buf)
+        check(lib().sv_apply_fused_rows(self.h, arr, len(blocks), mode))
         return self
 
     # -- measurement

@@ -69,6 +69,51 @@ def test_small_blocks_padded(sv, mode, k):
     assert np.max(np.abs(st.to_numpy()[0] - ref)) <= AMP_TOL
 
 
+@pytest.mark.parametrize("mode", MODES[:2])
+@pytest.mark.parametrize("n,targets", [
+    (10, (9, 8, 7, 6, 5)),        # wide form
+    (12, (5, 11, 7, 9, 6)),       # direct form
+    (13, (3, 0, 12, 6, 1)),       # LDS-staged form
+    (11, (4, 9)),                 # padded to five qubits
+])
+def test_per_row_matrices(sv, mode, n, targets):
+    """sv_apply_fused_rows: every row of a batch of 3 (different states) with
+    its own Haar-random matrix, each row against the oracle; two blocks in a
+    row, the second on other targets."""
+    B = 3
+    rng = np.random.default_rng(n * 11 + len(targets))
+    psi0 = [pins.random_state(n, rng) for _ in range(B)]
+    k = len(targets)
+    ms = np.stack([pins.haar_unitary(1 << k, rng) for _ in range(B)])
+    t2 = tuple(int(x) for x in rng.permutation(n)[:5])
+    ms2 = np.stack([pins.haar_unitary(32, rng) for _ in range(B)])
+    st = sv.State(n, B)
+    st.from_numpy(np.stack(psi0).astype(np.complex64))
+    st.apply_fused_rows([(targets, ms), (t2, ms2)], mode)
+    out = st.to_numpy()
+    for r in range(B):
+        ref = psi0[r].astype(np.complex64).astype(np.complex128)
+        oracle.apply_matrix(ref, n, ms[r], list(targets))
+        oracle.apply_matrix(ref, n, ms2[r], list(t2))
+        assert np.max(np.abs(out[r] - ref)) <= AMP_TOL
+
+
+def test_per_row_matrices_refusals(sv):
+    n, B = 12, 2
+    st = sv.State(n, B).reset()
+    rng = np.random.default_rng(5)
+    m5 = np.stack([pins.haar_unitary(32, rng) for _ in range(B)])
+    with pytest.raises(svmod.SvError) as e:
+        st.apply_fused_rows([((0, 1, 2, 3, 4), m5)], svmod.FUSED_VALU)
+    assert e.value.status == 4
+    m6 = np.stack([pins.haar_unitary(64, rng) for _ in range(B)])
+    with pytest.raises(svmod.SvError) as e:
+        st.apply_fused_rows([((11, 10, 9, 8, 7, 6), m6)], svmod.FUSED_BF16X3)
+    assert e.value.status == 4
+    with pytest.raises(ValueError):
+        st.apply_fused_rows([((0, 1, 2, 3, 4), m5[:1])], svmod.FUSED_FP32_MFMA)
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("n", [10, 14, 18])
 def test_planned_brickwork_vs_unfused_oracle(sv, mode, n):

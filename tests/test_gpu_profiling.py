@@ -87,8 +87,9 @@ def test_expvalz_forward_and_backward(sv, block_qubits, n, fuse):
 def test_run_fused_forward(sv, shared):
     """The fused forward of the autograd layers: gates whose angles are equal
     on every row as 5-qubit matrix-core blocks, per-row gates (the input
-    encoding) as per-gate sweeps, in circuit order. Equal to the per-gate
-    forward (2e-6) and to the oracle (1e-5) row by row."""
+    encoding) as matrix-core blocks with one matrix per row, in circuit
+    order. Equal to the per-gate forward (2e-6) and to the oracle (1e-5) row
+    by row."""
     n, B = 14, 3
     circ, rows = C.profiling_ladder(n, 3, B, seed=11)
     if not shared:
