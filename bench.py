@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the fused/adjoint/batched comparisons")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="one forward + matrix-core adjoint backward of the n-qubit RX/RY ring, for counters")
     return ap.parse_args()
 
 
@@ -94,6 +96,8 @@ def main() -> int:
 
     if args.pmc_probe:
         return run_pmc_probe(n)
+    if args.adjoint_probe:
+        return run_adjoint_probe(n)
 
     circ = C.brickwork_u3_cz(n, 20, 2)
     table = sv.OpTable(circ.ops)
@@ -582,6 +586,22 @@ def run_pmc_probe(n: int) -> int:
     print(json.dumps({"pmc_probe": True, "n": n, "dense_launches": 4, "fused_launches_per_mode": len(blocks),
                       "copy_bytes": 8 * (1 << n),
                       "kernel_source_digest": kernel_source_digest()}), flush=True)
+    return 0
+
+
+def run_adjoint_probe(n: int) -> int:
+    """One forward (plain sweeps) and one matrix-core adjoint backward of the
+    n-qubit ring of 10 RX/RY layers with CNOT rings, loss <sum Z_i>."""
+    import torch
+
+    from paper_2511_19291_amd import circuits as C
+    from paper_2511_19291_amd import sv
+
+    circ = C.rxry_ring(n, 10, 5)
+    st = sv.State(n).reset().run(circ)
+    loss, grad, drift = st.adjoint_grad(circ, C.z_sum_terms(n), block_qubits=sv.ADJOINT_MFMA)
+    torch.cuda.synchronize()
+    print(json.dumps({"adjoint_probe": True, "n": n, "loss": float(loss[0]), "drift": float(drift[0])}), flush=True)
     return 0
 
 
