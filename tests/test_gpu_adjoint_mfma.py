@@ -2,7 +2,9 @@
 per 4-qubit block, one sweep computes the block's correlation
 S = sum_c psi_c lambda_c^* on FP64 matrix cores and un-applies the block's
 product on FP32 matrix cores; each derivative is 2 Re Tr(X_k S) with X_k
-formed on the host in FP64.
+formed on the host in FP64, or, for blocks whose parameters differ between
+rows and for batches of at most four rows, Tr(G_k S_t) with S stepped down
+the block's gates on the host (S_t = W_t^* S W_t).
 
 References: the oracle's FP64 adjoint (pinned against parameter shift and
 central differences) and parameter shift itself, relative 1e-4 (2-norm and
@@ -75,6 +77,26 @@ def test_batched_rows_weighted(sv):
     n, B = 10, 4
     circ, rows = C.profiling_ladder(n, 3, B, seed=12)
     coeff = np.random.default_rng(13).normal(size=(B, n))
+    terms = [(1.0, 0, 1 << i) for i in range(n)]
+    st = sv.State(n, B)
+    st.reset().run(circ, params=rows)
+    loss, g, drift = st.adjoint_grad(circ, terms, params=rows, coeff_rows=coeff, block_qubits=MF)
+    for r in range(B):
+        wt = [(float(coeff[r, i]), 0, 1 << i) for i in range(n)]
+        ref_loss, ref, _ = oracle.grad_adjoint(circ, wt, params=rows[r])
+        _close(g[r], ref)
+        assert abs(loss[r] - ref_loss) < 1e-4
+    assert np.all(drift < 1e-4)
+
+
+def test_batched_shared_and_per_row_blocks(sv):
+    """Batch 6 (more rows than the host's S recursion takes for shared
+    blocks): the shared ansatz blocks take their derivatives from X_k formed
+    on the host, the per-row encoding blocks from the S recursion, in one
+    chunked pipeline; every row against the oracle's adjoint."""
+    n, B = 11, 6
+    circ, rows = C.profiling_ladder(n, 3, B, seed=21)
+    coeff = np.random.default_rng(22).normal(size=(B, n))
     terms = [(1.0, 0, 1 << i) for i in range(n)]
     st = sv.State(n, B)
     st.reset().run(circ, params=rows)
