@@ -3,16 +3,16 @@ execution, Sec. 4.4 and the `invertible=True` device of Appendix A).
 
 Forward: reset the state to |0..0>, run the circuit with the given
 parameters, return L = sum_t coeff_t <P_t> per batch row. From 20 qubits on
-(``fuse``), gates whose angles are equal on every row are fused into
-5-qubit blocks on the matrix cores (Sec. 4.1.1); per-row gates (an input
-encoding) stay per-gate sweeps. Backward: the
-library un-applies the gates from the forward output (x = U^* y) and
-accumulates dL/dtheta in FP64; nothing is stored between the passes except
-the final state itself. By default the backward groups the gates into
-4-qubit blocks (one sweep per block: ``sv_adjoint_grad_blocked`` from 14
-qubits, the matrix-core ``sv_adjoint_grad_mfma`` from 22) when every gate
-fits; ``block_qubits=0`` selects the per-gate backward. The state object therefore holds one pending
-forward at a time: run backward before the next forward on the same state.
+(``fuse``), the gates are fused into 5-qubit blocks on the matrix cores
+(Sec. 4.1.1); runs of per-row gates (an input encoding) with one matrix per
+row. Backward: the library un-applies the gates from the forward output
+(x = U^* y) and accumulates dL/dtheta in FP64; nothing is stored between the
+passes except the final state itself. By default the backward groups the
+gates into 4-qubit blocks on the matrix cores (``sv_adjoint_grad_mfma``, one
+sweep per block) from 13 qubits when every gate fits; ``block_qubits=0``
+selects the per-gate backward, 3..5 the VALU blocks. The state object
+therefore holds one pending forward at a time: run backward before the next
+forward on the same state.
 """
 
 from __future__ import annotations
