@@ -49,12 +49,44 @@ __device__ double wg_sum256(double v, double* sh)
     return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// 1. probability mass of each block of 2^bb amplitudes (bb <= kShotBits)
-__global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ psi, int bb, double* __restrict__ mass)
+// Blocks of at least 2^kChunkBits amplitudes are also cut into chunks of
+// 2^kChunkBits (128: one float4 per lane of a wave).
+constexpr int kChunkBits = 7;
+static_assert(kShotBits - kChunkBits <= 6, "a lane per chunk");
+
+// 1. probability mass of each block of 2^bb amplitudes (bb <= kShotBits).
+// With chunks: wave w's pass k reads chunk 4k + w in memory order (lane l:
+// amplitudes 2l, 2l + 1 of the chunk); the chunk's mass is the wave's sum in
+// a fixed order (butterfly; lane 0's value is stored), and the block's mass
+// is the sum of its chunks' in chunk order.
+__global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ psi, int bb, double* __restrict__ mass,
+                                                    double* __restrict__ csum)
 {
-    __shared__ double sh[kST / 64];
+    __shared__ double sh[(1 << (kShotBits - kChunkBits)) > kST / 64 ? (1 << (kShotBits - kChunkBits)) : kST / 64];
     const uint64_t base = (uint64_t)blockIdx.x << bb;
     const uint32_t bs = 1u << bb;
+    if (bb >= kChunkBits) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const uint32_t nch = 1u << (bb - kChunkBits);
+        const float4* p4 = reinterpret_cast<const float4*>(psi + base);
+        for (uint32_t c = w; c < nch; c += kST / 64) {
+            const float4 v = p4[c * 64 + lane];
+            double t = prob(make_float2(v.x, v.y)) + prob(make_float2(v.z, v.w));
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (lane == 0) {
+                sh[c] = t;
+                csum[((uint64_t)blockIdx.x << (kShotBits - kChunkBits)) + c] = t;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            for (uint32_t c = 0; c < nch; ++c) m += sh[c];
+            mass[blockIdx.x] = m;
+        }
+        return;
+    }
     double acc = 0.0;
     if (bs >= 2) {
         const float4* p4 = reinterpret_cast<const float4*>(psi + base);
@@ -157,9 +189,10 @@ __global__ __launch_bounds__(kST) void k_shot_scatter(const uint32_t* __restrict
     order[pos] = (uint32_t)s;
 }
 
-// 4. per block with shots, one wave per block. Lane l owns the `per`
-// contiguous amplitudes [per l, per (l + 1)) of the block (per = 64 for
-// blocks of 4096); the lanes' masses are scanned across the wave with
+// 4. per block with shots, one wave per block (blocks of at least 128
+// amplitudes: resolve_chunked below). Smaller blocks (states below 7
+// qubits): lane l owns the `per` contiguous amplitudes [per l, per (l + 1))
+// of the block; the lanes' masses are scanned across the wave with
 // shuffles in a fixed order. Each shot of the block finds its lane by binary
 // search over the lanes' inclusive sums (shuffles: every lane takes part in
 // every step), then its index by re-reading that lane's amplitudes in the
@@ -168,15 +201,108 @@ __global__ __launch_bounds__(kST) void k_shot_scatter(const uint32_t* __restrict
 // (or, past the last lane, in the block).
 __device__ __forceinline__ double lane_prob(const float2* __restrict__ p, uint32_t i) { return prob(p[i]); }
 
+// Last index of non-zero probability in chunk c of a block (-1 if none).
+__device__ int chunk_last_nonzero(const float2* __restrict__ blk, uint32_t c)
+{
+    const float2* ch = blk + ((uint64_t)c << kChunkBits);
+    int last = -1;
+    for (int i = 0; i < (1 << kChunkBits); ++i)
+        if (prob(ch[i]) > 0.0) last = (int)(c << kChunkBits) + i;
+    return last;
+}
+
+// Blocks of at least 128 amplitudes: lane c takes chunk c's mass as
+// k_block_mass stored it, and an inclusive scan over the lanes (fixed order)
+// gives the chunks' running masses. Each shot (a lane per shot) finds its
+// chunk by binary search over those sums and its index by reading that
+// chunk in order (sixteen float4 loads in flight at a time): the first
+// index whose running sum exceeds the remainder; if rounding leaves none,
+// the last index of non-zero probability in the chunk (or, past the last
+// chunk, in the block: in the last chunk of non-zero mass). Only the chunks
+// that hold a shot are read.
+__device__ __forceinline__ void resolve_chunked(const float2* __restrict__ blk, int bb, uint64_t base, int lane,
+                                                const double* __restrict__ csum, uint32_t first, uint32_t nshot,
+                                                const uint32_t* __restrict__ order, const double* __restrict__ rem,
+                                                int64_t* __restrict__ out)
+{
+    const uint32_t nch = 1u << (bb - kChunkBits);
+    const bool own = (uint32_t)lane < nch;
+    const double mine = own ? csum[lane] : 0.0;
+    const uint64_t nz = __ballot(own && mine > 0.0);        // chunks holding a non-zero probability
+    double cincl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(cincl, off, 64);
+        if (lane >= off) cincl += t;
+    }
+    for (uint32_t j0 = 0; j0 < nshot; j0 += 64) {
+        const bool have = j0 + lane < nshot;
+        const uint32_t s = have ? order[first + j0 + lane] : 0;
+        const double r = have ? rem[s] : 0.0;
+        // first chunk whose inclusive mass exceeds r
+        uint32_t lo = 0, hi = nch;
+#pragma unroll
+        for (int step = 0; step < 7; ++step) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            const double im = __shfl(cincl, (int)min(mid, 63u), 64);
+            if (lo < hi) {
+                if (im > r) hi = mid;
+                else lo = mid + 1;
+            }
+        }
+        const double excl = __shfl(cincl, (int)(lo > 0 ? min(lo - 1, 63u) : 0u), 64);
+        if (!have) continue;
+        int idx = -1;
+        if (lo < nch) {
+            // the chunk in index order, 32 amplitudes (16 independent loads)
+            // at a time
+            const double need = r - (lo > 0 ? excl : 0.0);
+            const float4* c4 = reinterpret_cast<const float4*>(blk + ((uint64_t)lo << kChunkBits));
+            double acc = 0.0;
+            int at = -1, lastnz = -1;
+            for (uint32_t g = 0; g < (1u << kChunkBits) / 2 && at < 0; g += 16) {
+                float4 w[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) w[q] = c4[g + q];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const double p0 = prob(make_float2(w[q].x, w[q].y)), p1 = prob(make_float2(w[q].z, w[q].w));
+                    acc += p0;
+                    if (p0 > 0.0) lastnz = (int)(2 * (g + q));
+                    if (at < 0 && acc > need) at = (int)(2 * (g + q));
+                    acc += p1;
+                    if (p1 > 0.0) lastnz = (int)(2 * (g + q) + 1);
+                    if (at < 0 && acc > need) at = (int)(2 * (g + q) + 1);
+                }
+            }
+            // (when at < 0 the whole chunk was read, so lastnz is its last)
+            const int pick = at >= 0 ? at : lastnz;
+            if (pick >= 0) idx = (int)(lo << kChunkBits) + pick;
+        }
+        if (idx < 0 && nz) idx = chunk_last_nonzero(blk, 63u - (uint32_t)__builtin_clzll(nz));
+        out[s] = idx >= 0 ? (int64_t)(base + (uint32_t)idx) : -1;
+    }
+}
+
 __global__ __launch_bounds__(kST) void k_shot_resolve(const float2* __restrict__ psi, int bb, uint32_t nb,
                                                       const uint32_t* __restrict__ cinc, const uint32_t* __restrict__ cnt,
                                                       const uint32_t* __restrict__ order, const double* __restrict__ rem,
-                                                      int64_t* __restrict__ out)
+                                                      const double* __restrict__ csum, int64_t* __restrict__ out)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (kST / 64) + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * (kST / 64);
     const uint32_t bs = 1u << bb;
+    if (bb >= kChunkBits) {
+        for (uint32_t b = wave; b < nb; b += nwaves) {
+            const uint32_t nshot = cnt[b];
+            if (nshot == 0) continue;
+            const uint64_t co = (uint64_t)b << (kShotBits - kChunkBits);
+            resolve_chunked(psi + ((uint64_t)b << bb), bb, (uint64_t)b << bb, lane, csum + co, cinc[b] - nshot,
+                            nshot, order, rem, out);
+        }
+        return;
+    }
     const uint32_t per = bs >= 64 ? bs / 64 : 1;
     const uint32_t nl = bs >= 64 ? 64 : bs;            // lanes that own amplitudes
     for (uint32_t b = wave; b < nb; b += nwaves) {
@@ -530,9 +656,11 @@ size_t shot_scratch_bytes(int n, int64_t shots)
 {
     const uint64_t nb = 1ull << (n - shot_block_bits(n));
     const uint64_t st = scan_tmp(nb);
+    const uint64_t nch = (uint64_t)nb << (kShotBits - kChunkBits);   // chunk slots
     return (nb + st) * sizeof(double)                 // scanned masses + scan totals
            + (3 * nb + st) * sizeof(uint32_t)         // counts, fill, (count scan totals)
-           + (uint64_t)shots * (sizeof(double) + 2 * sizeof(uint32_t)) + 64;
+           + nch * sizeof(double)                     // chunk masses
+           + (uint64_t)shots * (sizeof(double) + 2 * sizeof(uint32_t)) + 80;
 }
 
 void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
@@ -555,8 +683,10 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
     double* rem = reinterpret_cast<double*>(take((size_t)a.shots * sizeof(double)));
     uint32_t* blk = reinterpret_cast<uint32_t*>(take((size_t)a.shots * sizeof(uint32_t)));
     uint32_t* order = reinterpret_cast<uint32_t*>(take((size_t)a.shots * sizeof(uint32_t)));
+    const uint64_t nch = nb << (kShotBits - kChunkBits);
+    double* csum = reinterpret_cast<double*>(take(nch * sizeof(double)));
 
-    hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, mass);
+    hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, mass, csum);
     SV_HIP(hipGetLastError());
     scan_inclusive<double>(mass, nb, dtmp, st);
     if (a.shots == 0) return;
@@ -574,7 +704,7 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
     SV_HIP(hipGetLastError());
     const unsigned rg = (unsigned)std::min<uint64_t>((nb + 3) / 4, (uint64_t)device_info().cu_count * 8);
     hipLaunchKernelGGL(k_shot_resolve, dim3(rg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, cnt, order, rem,
-                       a.out);
+                       csum, a.out);
     SV_HIP(hipGetLastError());
 }
 
