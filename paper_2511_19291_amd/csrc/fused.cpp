@@ -451,30 +451,30 @@ sv_status apply_fused_impl(sv_state s, const sv_block* blocks, int n_blocks, int
                 const int pad = 5 - k;
                 for (int j = 0; j < 5; ++j) tgt[i][j] = t5[j];
                 for (int mi = 0; mi < nmat; ++mi) {
-                const double* bm = b.matrix + (size_t)mi * 2 * D * D;
-                float* A = reinterpret_cast<float*>(dst + (size_t)mi * per5);
-                for (int r = 0; r < 32; ++r)
-                    for (int c = 0; c < 32; ++c) {
-                        // M5 = M (x) I_{2^pad}
-                        cd v = 0.0;
-                        if ((r & ((1 << pad) - 1)) == (c & ((1 << pad) - 1))) {
-                            const double* e = bm + 2 * ((size_t)(r >> pad) * D + (c >> pad));
-                            v = cd(e[0], e[1]);
+                    const double* bm = b.matrix + (size_t)mi * 2 * D * D;
+                    float* A = reinterpret_cast<float*>(dst + (size_t)mi * per5);
+                    for (int r = 0; r < 32; ++r)
+                        for (int c = 0; c < 32; ++c) {
+                            // M5 = M (x) I_{2^pad}
+                            cd v = 0.0;
+                            if ((r & ((1 << pad) - 1)) == (c & ((1 << pad) - 1))) {
+                                const double* e = bm + 2 * ((size_t)(r >> pad) * D + (c >> pad));
+                                v = cd(e[0], e[1]);
+                            }
+                            const float re = (float)v.real(), im = (float)v.imag();
+                            A[r * 64 + c] = re;
+                            A[r * 64 + 32 + c] = -im;
+                            A[(32 + r) * 64 + c] = im;
+                            A[(32 + r) * 64 + 32 + c] = re;
                         }
-                        const float re = (float)v.real(), im = (float)v.imag();
-                        A[r * 64 + c] = re;
-                        A[r * 64 + 32 + c] = -im;
-                        A[(32 + r) * 64 + c] = im;
-                        A[(32 + r) * 64 + 32 + c] = re;
+                    if (mode == SV_FUSED_BF16X3) {
+                        float* L = A + 64 * 64;
+                        for (int q = 0; q < 64 * 64; ++q) {
+                            const float hi = bf16_round(A[q]);
+                            L[q] = A[q] - hi;
+                            A[q] = hi;
+                        }
                     }
-                if (mode == SV_FUSED_BF16X3) {
-                    float* L = A + 64 * 64;
-                    for (int q = 0; q < 64 * 64; ++q) {
-                        const float hi = bf16_round(A[q]);
-                        L[q] = A[q] - hi;
-                        A[q] = hi;
-                    }
-                }
                 }
             } else {
                 float2* m = reinterpret_cast<float2*>(dst);
