@@ -79,6 +79,23 @@ def test_exact_sparse_states_never_draw_zero_probability(sv):
     assert set(np.unique(got)) <= {0, (1 << 12) - 1}
 
 
+@pytest.mark.parametrize("offset", [0, 1, 127])
+def test_exact_one_index_per_chunk(sv, offset):
+    """Non-zero probability only at index `offset` of every 128-amplitude
+    chunk (the sampler's unit inside a block): each draw must land exactly
+    there, the first or the last index a chunk scan reaches."""
+    rng = np.random.default_rng(40 + offset)
+    n = 15
+    p = np.zeros(1 << n)
+    p[offset::128] = rng.random((1 << n) // 128) + 0.1
+    psi = np.sqrt(p / p.sum()).astype(np.complex128)
+    st, psi = _upload(sv, psi)
+    u = np.concatenate([[0.0, np.nextafter(1.0, 0.0)], rng.random(40000)])
+    got = st.sample_exact(u).cpu().numpy()
+    assert np.all(got % 128 == offset)
+    _check_exact(got, psi, n, u)
+
+
 def test_exact_zero_state_no_shots_and_determinism(sv):
     st = sv.State(10).from_numpy(np.zeros((1, 1 << 10), dtype=np.complex64))
     assert np.all(st.sample_exact(np.array([0.0, 0.3, 0.9])).cpu().numpy() == -1)
