@@ -1118,9 +1118,9 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         // (fragments) per row. The derivatives come either from X_k formed
         // on the host while the GPU sweeps (a block shared by more than
         // kRecurRows rows: one X_k serves every row), or from S itself once
-        // it is back, S_t = W_t^* S W_t stepped down the gates
-        // (Tr(X_k S) = Tr(G_k S_t)): a few times cheaper per row, but after
-        // the sweeps.
+        // its copy is back, S_t = W_t^* S W_t stepped down the gates
+        // (Tr(X_k S) = Tr(G_k S_t)): a few times cheaper per row, but only
+        // after that block's sweep.
         struct Deriv { int param; size_t x; };      // X_k at xs[x * 256]
         struct Launch {
             int q[4];
