@@ -350,7 +350,10 @@ sv_status sv_gaussian_expval_z_backward(sv_state s, int row, const double* dev_n
  * vectors before the block are U_B^* psi, U_B^* lambda. One sweep per block
  * computes S on FP64 matrix cores (the FP32 data's products exact, FP64
  * sums) and the un-apply on FP32 matrix cores; X_k and the traces are FP64
- * on the host. Any gate kind on at most four qubits (targets and controls).
+ * on the host (for blocks whose parameters differ between rows, and for
+ * batches of at most four rows, the same traces as Tr(G_k S_t) with
+ * S_t = W_k^* S W_k stepped down the block's gates). Rows share each block's
+ * launch. Any gate kind on at most four qubits (targets and controls).
  * Needs n >= 9 (SV_ERR_UNSUPPORTED otherwise). Arguments, outputs and errors
  * otherwise as sv_adjoint_grad_weighted (coeff_rows may be NULL). */
 sv_status sv_adjoint_grad_mfma(sv_state s, const sv_op* ops, int n_ops, const double* params,
