@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the fused/adjoint/batched comparisons")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--shots-probe", action="store_true",
+                    help="the shot-sampling part of the bench alone (n-qubit brickwork output state), for profiles")
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="one forward + matrix-core adjoint backward of the n-qubit RX/RY ring, for counters")
     return ap.parse_args()
@@ -98,6 +100,11 @@ def main() -> int:
         return run_pmc_probe(n)
     if args.adjoint_probe:
         return run_adjoint_probe(n)
+    if args.shots_probe:
+        circ = C.brickwork_u3_cz(n, 20, 2)
+        st = sv.State(n)
+        print(json.dumps({"shots_probe": shots_extra(st, circ, sv.fuse_plan(circ, 5), stream)}), flush=True)
+        return 0
 
     circ = C.brickwork_u3_cz(n, 20, 2)
     table = sv.OpTable(circ.ops)
