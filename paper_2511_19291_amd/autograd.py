@@ -2,10 +2,10 @@
 execution, Sec. 4.4 and the `invertible=True` device of Appendix A).
 
 Forward: reset the state to |0..0>, run the circuit with the given
-parameters, return L = sum_t coeff_t <P_t> per batch row. From 20 qubits on
-(``fuse``), the gates are fused into 5-qubit blocks on the matrix cores
-(Sec. 4.1.1); runs of per-row gates (an input encoding) with one matrix per
-row. Backward: the library un-applies the gates from the forward output
+parameters, return L = sum_t coeff_t <P_t> per batch row. Once
+2n + log2(batch) >= 44 (``fuse``: batch 16 from 20 qubits, batch 1 from 22),
+the gates are fused into 5-qubit blocks on the matrix cores (Sec. 4.1.1);
+runs of per-row gates (an input encoding) with one matrix per row. Backward: the library un-applies the gates from the forward output
 (x = U^* y) and accumulates dL/dtheta in FP64; nothing is stored between the
 passes except the final state itself. By default the backward groups the
 gates into 4-qubit blocks on the matrix cores (``sv_adjoint_grad_mfma``, one
@@ -25,14 +25,16 @@ import torch
 from . import sv
 
 
-# The forward fuses row-shared gates into matrix-core blocks from this width
-# on (below it the per-gate sweeps are about as fast as planning the blocks
-# and running them: measured equal at 18 qubits, batch 16).
+# The forward fuses the gates into matrix-core blocks once the state is
+# large enough for the blocks to repay their host planning: measured on one
+# MI355X, batch 16 from 20 qubits (18: 1.9 ms per-gate vs 2.8 ms fused; 20:
+# 5.9 vs 4.5) and batch 1 from 22 (20: 2.8 vs 3.9 ms; 22: 6.5 vs 5.1), i.e.
+# 2n + log2(batch) >= 44.
 FUSED_FORWARD_MIN_QUBITS = 20
 
 
-def default_fuse(circuit) -> bool:
-    return circuit.n >= FUSED_FORWARD_MIN_QUBITS
+def default_fuse(circuit, batch: int = 1) -> bool:
+    return 2 * circuit.n + np.log2(max(int(batch), 1)) >= 2 * FUSED_FORWARD_MIN_QUBITS + 4
 
 
 def _forward(state, circuit, p, fuse: bool) -> None:
@@ -98,7 +100,7 @@ class QuantumExpval(torch.nn.Module):
         self.terms = list(terms)
         self.state = sv.State(circuit.n, batch, device=device)
         self.block_qubits = default_block_qubits(circuit) if block_qubits is None else block_qubits
-        self.fuse = default_fuse(circuit) if fuse is None else bool(fuse)
+        self.fuse = default_fuse(circuit, batch) if fuse is None else bool(fuse)
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
         return AdjointExpval.apply(params, self.circuit, self.terms, self.state, self.block_qubits, self.fuse)
@@ -144,7 +146,7 @@ class MeasureAllZ(torch.nn.Module):
         self.circuit = circuit
         self.state = sv.State(circuit.n, batch, device=device)
         self.block_qubits = default_block_qubits(circuit) if block_qubits is None else block_qubits
-        self.fuse = default_fuse(circuit) if fuse is None else bool(fuse)
+        self.fuse = default_fuse(circuit, batch) if fuse is None else bool(fuse)
 
     def forward(self, params: torch.Tensor) -> torch.Tensor:
         return ExpvalZ.apply(params, self.circuit, self.state, self.block_qubits, self.fuse)

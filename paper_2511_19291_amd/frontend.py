@@ -216,13 +216,13 @@ def measure_allZ(qdev: QuantumDevice, shots: int = 0, training: bool = True, gen
     circ, mat = qdev._program()
     mat = mat.to(torch.float64)
     if shots == 0:
-        z = ExpvalZ.apply(mat, circ, qdev.state, default_block_qubits(circ), default_fuse(circ))
+        z = ExpvalZ.apply(mat, circ, qdev.state, default_block_qubits(circ), default_fuse(circ, qdev.bsz))
         return z.to(qdev.device) if qdev.device.type == "cuda" else z
     if training:
         normals = torch.randn((qdev.bsz, 1 << qdev.n_wires), dtype=torch.float64, device=qdev.device,
                               generator=generator)
         z = GaussianExpvalZ.apply(mat, circ, qdev.state, normals, float(shots), default_block_qubits(circ),
-                                  default_fuse(circ))
+                                  default_fuse(circ, qdev.bsz))
         return z.to(qdev.device)
     with torch.no_grad():
         p = mat.detach().numpy()
