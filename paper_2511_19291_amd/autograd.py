@@ -12,7 +12,11 @@ gates into 4-qubit blocks on the matrix cores (``sv_adjoint_grad_mfma``, one
 sweep per block) from 13 qubits when every gate fits; ``block_qubits=0``
 selects the per-gate backward, 3..5 the VALU blocks. The state object
 therefore holds one pending forward at a time: run backward before the next
-forward on the same state.
+forward on the same state. Every backward checks this: it raises
+``StaleStateError`` when the state changed after the forward that saved it
+(a second forward on the same state, or a second backward through the same
+graph, whose first backward has already un-applied the gates), and when the
+recomputed start state drifts from |0..0> by more than ``DRIFT_MAX``.
 """
 
 from __future__ import annotations
@@ -23,6 +27,38 @@ import numpy as np
 import torch
 
 from . import sv
+
+
+class StaleStateError(RuntimeError):
+    """The state no longer holds the forward output a backward needs."""
+
+
+# Largest accepted distance ||psi_recomputed - |0..0>|| after the backward has
+# un-applied every gate (Sec. 4.4: the layer inputs are recomputed from the
+# output, so the recomputed start state must be the true one). Complex64
+# rounding of the forward and of the un-apply grows like sqrt(G) 2^-24 per
+# sweep, about 1e-4 for 10^6 gates; a state that is not the forward's output
+# is off by O(1).
+DRIFT_MAX = 1e-3
+
+
+def _saved_version(ctx, state) -> None:
+    ctx.state = state
+    ctx.version = state.version
+
+
+def _check_fresh(ctx) -> None:
+    if ctx.state.version != ctx.version:
+        raise StaleStateError(
+            "the state changed after this forward (another forward on the same state, or a second "
+            "backward through the same graph): the adjoint backward needs the forward's output state")
+
+
+def _check_drift(drift) -> None:
+    d = float(np.max(drift)) if np.size(drift) else 0.0
+    if not d <= DRIFT_MAX:
+        raise StaleStateError(f"recomputed start state drifts by {d:.3e} (> {DRIFT_MAX:.0e}): "
+                              "the backward did not start from this forward's output")
 
 
 # The forward fuses the gates into matrix-core blocks once the state is
@@ -74,7 +110,7 @@ class AdjointExpval(torch.autograd.Function):
         loss = vals.sum(axis=1)
         ctx.circuit = circuit
         ctx.terms = list(terms)
-        ctx.state = state
+        _saved_version(ctx, state)
         ctx.p = p
         ctx.shape = params.shape
         out = torch.from_numpy(loss).to(device=params.device, dtype=params.dtype)
@@ -82,7 +118,9 @@ class AdjointExpval(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, ctx.terms, params=ctx.p, block_qubits=ctx.block_qubits)
+        _check_fresh(ctx)
+        _, grad, drift = ctx.state.adjoint_grad(ctx.circuit, ctx.terms, params=ctx.p, block_qubits=ctx.block_qubits)
+        _check_drift(drift)
         go = grad_out.detach().to("cpu", torch.float64).reshape(-1, 1).numpy()
         g = grad * go                              # [batch, n_params]
         g = torch.from_numpy(g.reshape(ctx.shape)).to(device=grad_out.device, dtype=grad_out.dtype)
@@ -119,7 +157,7 @@ class ExpvalZ(torch.autograd.Function):
         _forward(state, circuit, p if state.batch > 1 else p[0], fuse)
         z = state.expval_z_all()[:, : circuit.n]
         ctx.circuit = circuit
-        ctx.state = state
+        _saved_version(ctx, state)
         ctx.p = p
         ctx.shape = params.shape
         return torch.from_numpy(np.ascontiguousarray(z)).to(device=params.device, dtype=params.dtype)
@@ -130,7 +168,10 @@ class ExpvalZ(torch.autograd.Function):
         terms = [(1.0, 0, 1 << i) for i in range(n)]
         g = np.ascontiguousarray(grad_z.detach().to("cpu", torch.float64).numpy().reshape(ctx.state.batch, n))
         p = ctx.p if ctx.state.batch > 1 else ctx.p[0]
-        _, grad, _ = ctx.state.adjoint_grad(ctx.circuit, terms, params=p, coeff_rows=g, block_qubits=ctx.block_qubits)
+        _check_fresh(ctx)
+        _, grad, drift = ctx.state.adjoint_grad(ctx.circuit, terms, params=p, coeff_rows=g,
+                                                block_qubits=ctx.block_qubits)
+        _check_drift(drift)
         out = torch.from_numpy(grad.reshape(ctx.shape)).to(device=grad_z.device, dtype=grad_z.dtype)
         return out, None, None, None, None
 
@@ -166,18 +207,21 @@ class GaussianExpvalZ(torch.autograd.Function):
         p = np.ascontiguousarray(params.detach().to("cpu", torch.float64).numpy().reshape(state.batch, circuit.n_params))
         _forward(state, circuit, p if state.batch > 1 else p[0], fuse)
         est = np.stack([state.gaussian_expval_z(normals[r], shots, row=r) for r in range(state.batch)])
-        ctx.circuit, ctx.state, ctx.p, ctx.shape = circuit, state, p, params.shape
+        ctx.circuit, ctx.p, ctx.shape = circuit, p, params.shape
+        _saved_version(ctx, state)
         ctx.normals, ctx.shots, ctx.block_qubits = normals, shots, block_qubits
         return torch.from_numpy(est).to(device=params.device, dtype=params.dtype)
 
     @staticmethod
     def backward(ctx, grad_e: torch.Tensor):
+        _check_fresh(ctx)
         st = ctx.state
         g = np.ascontiguousarray(grad_e.detach().to("cpu", torch.float64).numpy().reshape(st.batch, ctx.circuit.n))
         w = torch.empty((st.batch, 1 << st.n), dtype=torch.float64, device=st.tensor.device)
         for r in range(st.batch):
             st.gaussian_expval_z_backward(ctx.normals[r], ctx.shots, g[r], row=r, out=w[r])
         p = ctx.p if st.batch > 1 else ctx.p[0]
-        _, grad, _ = st.adjoint_grad_diag(ctx.circuit, w, params=p, block_qubits=ctx.block_qubits)
+        _, grad, drift = st.adjoint_grad_diag(ctx.circuit, w, params=p, block_qubits=ctx.block_qubits)
+        _check_drift(drift)
         out = torch.from_numpy(grad.reshape(ctx.shape)).to(device=grad_e.device, dtype=grad_e.dtype)
         return out, None, None, None, None, None, None

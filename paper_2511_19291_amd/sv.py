@@ -220,7 +220,13 @@ def _params_rows(params, batch: int) -> Tuple[np.ndarray, int, int]:
 
 
 class State:
-    """A batch of n-qubit complex64 state vectors in GPU memory."""
+    """A batch of n-qubit complex64 state vectors in GPU memory.
+
+    ``version`` counts the calls that change the amplitudes (reset, copies
+    in, gates, fused blocks, the adjoint's un-apply). A caller that keeps a
+    result derived from the state -- the autograd layers keep their forward
+    output for the backward -- compares it to detect a state that changed
+    since. Writes through ``tensor`` by other code are not counted."""
 
     def __init__(self, n: int, batch: int = 1, device=None, tensor=None):
         import torch
@@ -236,6 +242,10 @@ class State:
         check(lib().sv_alloc(n, batch, C.c_void_p(tensor.data_ptr()), C.c_void_p(self.stream.cuda_stream),
                              C.byref(h)))
         self.h = h
+        self.version = 0
+
+    def _changed(self) -> None:
+        self.version += 1
 
     def free(self) -> None:
         h = getattr(self, "h", None)
@@ -251,6 +261,7 @@ class State:
 
     # -- state
     def reset(self, idx: int = 0) -> "State":
+        self._changed()
         check(lib().sv_reset(self.h, idx))
         return self
 
@@ -261,6 +272,7 @@ class State:
 
     def from_numpy(self, a: np.ndarray) -> "State":
         a = np.ascontiguousarray(np.asarray(a, dtype=np.complex64).reshape(self.batch, 1 << self.n))
+        self._changed()
         check(lib().sv_copy_state(self.h, a.ctypes.data_as(C.c_void_p), 0))
         return self
 
@@ -273,6 +285,7 @@ class State:
             stride = m.shape[1] * m.shape[2]
         buf = _cmatrix(m)
         flags = (FLAG_ADJOINT if adjoint else 0) | (FLAG_CHECK_UNITARY if check_unitary else 0)
+        self._changed()
         check(lib().sv_apply_gate(self.h, _iarr(targets), len(targets), _iarr(controls), len(controls),
                                   _dptr(buf), stride, flags))
         return self
@@ -280,6 +293,7 @@ class State:
     def run(self, circuit, params=None) -> "State":
         table = OpTable(circuit.ops)
         p, stride, npar = _params_rows(circuit.params if params is None else params, self.batch)
+        self._changed()
         check(lib().sv_run(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar))
         return self
 
@@ -328,6 +342,7 @@ class State:
         """Apply ``count`` ops of a prepared table from index ``start``
         (shared parameters)."""
         ptr = C.cast(C.byref(table.arr, start * C.sizeof(SvOp)), C.POINTER(SvOp))
+        self._changed()
         check(lib().sv_run(self.h, ptr, count, _dptr(params) if len(params) else None, 0, len(params)))
 
     def apply_fused(self, blocks: Sequence[Tuple[Sequence[int], np.ndarray]], mode: int = FUSED_FP32_MFMA) -> "State":
@@ -340,6 +355,7 @@ class State:
             buf = _cmatrix(m)
             keep.append(buf)
             arr[i].matrix = _dptr(buf)
+        self._changed()
         check(lib().sv_apply_fused(self.h, arr, len(blocks), mode))
         return self
 
@@ -360,6 +376,7 @@ class State:
             buf = np.ascontiguousarray(m, dtype=np.complex128).view(np.float64).reshape(-1)
             keep.append(buf)
             arr[i].matrix = _dptr(buf)
+        self._changed()
         check(lib().sv_apply_fused_rows(self.h, arr, len(blocks), mode))
         return self
 
@@ -441,6 +458,7 @@ class State:
         loss = np.zeros(self.batch, dtype=np.float64)
         drift = np.zeros(self.batch, dtype=np.float64)
         lam = C.c_void_p(lambda_tensor.data_ptr()) if lambda_tensor is not None else None
+        self._changed()
         check(lib().sv_adjoint_grad_diag(self.h, table.ptr, table.n, _dptr(p) if npar else None, stride, npar,
                                          C.c_void_p(weights.data_ptr()), block_qubits, lam, _dptr(grad), _dptr(loss),
                                          _dptr(drift)))
@@ -462,6 +480,7 @@ class State:
         drift = np.zeros(self.batch, dtype=np.float64)
         lam = C.c_void_p(lambda_tensor.data_ptr()) if lambda_tensor is not None else None
         pp = _dptr(p) if npar else None
+        self._changed()
         if block_qubits == ADJOINT_MFMA:
             cr = None
             if coeff_rows is not None:
