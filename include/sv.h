@@ -30,6 +30,13 @@
  *     asynchronous on the state's stream; calls that return host results
  *     synchronise that stream.
  *   - A state is not thread-safe: calls on one state must not overlap.
+ *   - SV_ERR_HIP is sticky: once a HIP runtime call fails during a call on
+ *     a state, the state's contents are undefined and every later call on
+ *     it returns SV_ERR_HIP (with the first failure's detail) until sv_free,
+ *     which still releases it. sv_state_failed reports the flag.
+ *   - Calls that synchronise the stream (host results, copies) return
+ *     SV_ERR_CAPTURE without queueing anything while the state's stream is
+ *     capturing a graph.
  */
 #ifndef LIBSV_SV_H_
 #define LIBSV_SV_H_
@@ -86,6 +93,16 @@ sv_status sv_free(sv_state s);
 
 /* Device pointer of row 0 (rows follow at a stride of 2^n amplitudes). */
 sv_status sv_device_ptr(sv_state s, void** out);
+
+/* *failed := 1 if an earlier call on s failed with SV_ERR_HIP (the state
+ * is then unusable), else 0. */
+sv_status sv_state_failed(sv_state s, int* failed);
+
+/* Testing hook for the sticky-error path (no GPU work): the next call on s
+ * that validates the state fails with SV_ERR_HIP before queueing anything,
+ * exactly as if a HIP runtime call inside it had failed; from then on the
+ * state is failed. */
+sv_status sv_inject_hip_error(sv_state s);
 
 /* Every row := e_idx (the basis state |idx>; idx = 0 gives |0..0>, the start
  * state of a circuit). Asynchronous. SV_ERR_INVALID_ARGUMENT if idx >= 2^n. */
@@ -486,6 +503,16 @@ sv_status sv_batch_launch(sv_batch_plan p, const double* dev_params, double* dev
 /* Same work as sv_batch_launch without the graph: one kernel launch per gate
  * per circuit (the plain per-gate form the batched launch is compared with). */
 sv_status sv_batch_launch_pergate(sv_batch_plan p, const double* dev_params, double* dev_out);
+
+/* Testing hook for the bounded inter-pass wait of the batched launch (no
+ * effect on results otherwise). A tile of pass p > 0 of a circuit waits until
+ * every tile of pass p - 1 is done, polling at most `limit` times (default
+ * 2^24, far beyond any real wait); if it gives up, the circuit is marked
+ * late and its outputs out[c][*] become NaN instead of a value computed from
+ * an incomplete state. limit < 0: every such wait gives up at once (so a
+ * test can force the late path while every kernel still ends normally).
+ * Waits for the plan's stream. */
+sv_status sv_batch_set_spin_limit(sv_batch_plan p, int limit);
 
 sv_status sv_batch_plan_free(sv_batch_plan p);
 

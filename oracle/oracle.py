@@ -28,9 +28,15 @@ Term = Tuple[float, int, int]
 
 
 def load() -> C.CDLL:
-    """Load liboracle.so, building it first if it is missing."""
+    """Load liboracle.so, building it first if it is missing. The
+    environment variable SV_ORACLE_LIB names another build of sv_oracle.c to
+    load instead (the sanitizer test runs the pins on an instrumented one)."""
     global _LIB
     if _LIB is not None:
+        return _LIB
+    other = os.environ.get("SV_ORACLE_LIB")
+    if other:
+        _LIB = bind(C.CDLL(other))
         return _LIB
     if not os.path.exists(_build.LIB):
         _build.build()

@@ -31,6 +31,8 @@ struct sv_batch_plan_s {
     double* d_zpart = nullptr;
     int* d_counter = nullptr;
     int* d_done = nullptr;
+    int* d_late = nullptr;                     // per circuit: a wait gave up
+    int* d_spin = nullptr;                     // spin limit of the inter-pass waits
     int n_tasks = 0;
     int n_ops = 0;
     int n_pass = 0;
@@ -213,6 +215,8 @@ void destroy(sv_batch_plan p)
     (void)hipFree(p->d_zpart);
     (void)hipFree(p->d_counter);
     (void)hipFree(p->d_done);
+    (void)hipFree(p->d_late);
+    (void)hipFree(p->d_spin);
     (void)hipFree(p->pg_arena);
     delete p;
 }
@@ -268,6 +272,9 @@ BatchArgs args_of(sv_batch_plan p, const double* params, double* out)
     a.out = out;
     a.counter = p->d_counter;
     a.done = p->d_done;
+    a.late = p->d_late;
+    a.spin = p->d_spin;
+    a.n_circ = p->n_circ;
     return a;
 }
 
@@ -499,6 +506,12 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
         dev_alloc((void**)&p->d_zpart, (size_t)zrows * (kBatchMaxQubits + 1) * sizeof(double), "partials");
         dev_alloc((void**)&p->d_done, (size_t)p->n_pass * sizeof(int), "pass counters");
         dev_alloc((void**)&p->d_counter, sizeof(int), "queue counter");
+        dev_alloc((void**)&p->d_late, (size_t)n_circuits * sizeof(int), "late flags");
+        dev_alloc((void**)&p->d_spin, sizeof(int), "spin limit");
+        {
+            const int spin = kDefaultSpinLimit;
+            SV_HIP(hipMemcpy(p->d_spin, &spin, sizeof(int), hipMemcpyHostToDevice));
+        }
         // persistent grid: the requested workgroups per CU, at most as many
         // as are resident at once (LDS, registers), at most one per task
         const int resident = batch_max_wg_per_cu(cfg.threads, cfg.tile_bits, cfg.phase_mode);
@@ -630,6 +643,16 @@ sv_status sv_batch_launch_pergate(sv_batch_plan p, const double* dev_params, dou
         }
         SV_HIP(hipMemcpyAsync(dev_out, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
         SV_HIP(hipStreamSynchronize(p->stream));
+    });
+}
+
+sv_status sv_batch_set_spin_limit(sv_batch_plan p, int limit)
+{
+    return guarded([&] {
+        need(p != nullptr, SV_ERR_INVALID_ARGUMENT, "null plan");
+        if (p->stream) SV_HIP(hipStreamSynchronize(p->stream));
+        else SV_HIP(hipDeviceSynchronize());
+        SV_HIP(hipMemcpy(p->d_spin, &limit, sizeof(int), hipMemcpyHostToDevice));
     });
 }
 

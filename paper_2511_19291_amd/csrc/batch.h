@@ -101,7 +101,14 @@ struct BatchArgs {
     double* out;
     int* counter;                     // next task
     int* done;                        // finished tiles per pass
+    int* late;                        // per circuit: 1 once any tile gave up waiting for its previous pass
+    const int* spin;                  // polls before an inter-pass wait gives up (< 0: give up at once)
+    int n_circ;
 };
+
+// polls of the bounded inter-pass wait before it gives up (each poll sleeps
+// ~4 x 64 cycles): far beyond any real wait, short of a hang
+constexpr int kDefaultSpinLimit = 1 << 24;
 
 // dynamic LDS of one workgroup for tiles of 2^tile_bits amplitudes
 size_t batch_lds_bytes(int tile_bits);

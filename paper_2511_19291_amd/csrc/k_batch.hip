@@ -255,6 +255,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a)
     }
     if (i < a.n_frag * 16) build_fragment_column(a, i >> 4, i & 15);
     if (i < a.n_pass) a.done[i] = 0;
+    if (i < a.n_circ) a.late[i] = 0;
     if (i == 0) *a.counter = 0;
 }
 
@@ -738,14 +739,19 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
         if (threadIdx.x == 0) {
             s_late = 0;
             if (!first) {
-                // every tile of the previous pass (handed out earlier) must be done
-                int it = 0;
-                while (__hip_atomic_load(a.done + tk.pass - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c.ntiles) {
+                // every tile of the previous pass (handed out earlier) must be
+                // done; a wait that gives up marks the circuit late, and the
+                // circuit's output becomes NaN (its state is incomplete)
+                const int limit = __hip_atomic_load(a.spin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int late = limit < 0;
+                for (int it = 0; !late && __hip_atomic_load(a.done + tk.pass - 1, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT) < c.ntiles;) {
                     __builtin_amdgcn_s_sleep(4);
-                    if (++it > (1 << 24)) {
-                        s_late = 1;    // give up: the circuit's output becomes NaN
-                        break;
-                    }
+                    if (++it > limit) late = 1;
+                }
+                if (late) {
+                    s_late = 1;
+                    __hip_atomic_fetch_or(a.late + tk.circ, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 __threadfence();
             }
@@ -875,8 +881,11 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
         }
         __syncthreads();
         if (s_final && threadIdx.x < SV_BATCH_OUT_STRIDE) {
-            // every tile's partial is in: sum them in tile order
+            // every tile's partial is in: sum them in tile order. A tile of
+            // any pass that gave up waiting flagged the circuit before it
+            // counted itself done, so the flag is visible here.
             const int i = threadIdx.x;
+            const bool late = __hip_atomic_load(a.late + tk.circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             double t = 0.0, s = 0.0;
             if (i < c.n)
                 for (int q = 0; q < c.ntiles; ++q) {
@@ -884,7 +893,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a)
                     t += zp[kBatchMaxQubits];
                     s += zp[i];
                 }
-            a.out[(size_t)c.out_idx * SV_BATCH_OUT_STRIDE + i] = i < c.n ? t - 2.0 * s : 0.0;
+            a.out[(size_t)c.out_idx * SV_BATCH_OUT_STRIDE + i] =
+                late ? __builtin_nan("") : (i < c.n ? t - 2.0 * s : 0.0);
         }
         __syncthreads();
     }
@@ -926,7 +936,7 @@ int batch_max_wg_per_cu(int threads, int tile_bits, int phase_mode)
 
 void launch_batch(const BatchArgs& a, int grid, int threads, int tile_bits, hipStream_t st)
 {
-    const int items = std::max(std::max(a.n_ops, a.n_pass), std::max(a.n_frag * 16, 1));
+    const int items = std::max(std::max(std::max(a.n_ops, a.n_pass), std::max(a.n_frag * 16, 1)), a.n_circ);
     hipLaunchKernelGGL(k_batch_prep, dim3((items + 255) / 256), dim3(256), 0, st, a);
     SV_HIP(hipGetLastError());
     const size_t lds = batch_lds_bytes(tile_bits);

@@ -17,6 +17,9 @@ namespace sv {
 
 namespace {
 thread_local std::string g_last_error;
+// the state the current entry point validated (check_state); a HIP failure
+// during the call marks it failed
+thread_local sv_state g_active = nullptr;
 }
 
 [[noreturn]] void fail(sv_status st, const std::string& msg) { throw Error{st, msg}; }
@@ -66,12 +69,20 @@ namespace {
 template <class F>
 sv_status guarded(F&& f)
 {
+    g_active = nullptr;
     try {
         f();
         g_last_error.clear();
+        g_active = nullptr;
         return SV_OK;
     } catch (const Error& e) {
         g_last_error = e.msg;
+        if (e.st == SV_ERR_HIP && g_active && !g_active->failed) {
+            // sticky: the state's contents are undefined from here on
+            g_active->failed = true;
+            g_active->failed_msg = e.msg;
+        }
+        g_active = nullptr;
         return e.st;
     } catch (const std::bad_alloc&) {
         g_last_error = "host allocation failed";
@@ -113,6 +124,12 @@ void check_gate(int n, const int* targets, int nt, const int* controls, int nc, 
 void check_state(sv_state s)
 {
     need(s != nullptr && s->psi != nullptr, SV_ERR_INVALID_ARGUMENT, "null state");
+    need(!s->failed, SV_ERR_HIP, "the state is unusable after an earlier HIP error (" + s->failed_msg + ")");
+    g_active = s;
+    if (s->inject_hip_error) {
+        s->inject_hip_error = false;
+        fail(SV_ERR_HIP, "injected HIP error (testing hook)");
+    }
 }
 
 void check_not_capturing(hipStream_t st)
@@ -442,6 +459,23 @@ sv_status sv_free(sv_state s)
         if (s->dterms) (void)hipFree(s->dterms);
         if (s->dfused) (void)hipFree(s->dfused);
         delete s;
+    });
+}
+
+sv_status sv_inject_hip_error(sv_state s)
+{
+    return guarded([&] {
+        need(s != nullptr && s->psi != nullptr, SV_ERR_INVALID_ARGUMENT, "null state");
+        s->inject_hip_error = true;
+    });
+}
+
+sv_status sv_state_failed(sv_state s, int* failed)
+{
+    return guarded([&] {
+        need(s != nullptr && s->psi != nullptr, SV_ERR_INVALID_ARGUMENT, "null state");
+        need(failed != nullptr, SV_ERR_INVALID_ARGUMENT, "failed is NULL");
+        *failed = s->failed ? 1 : 0;
     });
 }
 
@@ -1543,7 +1577,11 @@ sv_status sv_stream_copy(void* dst, const void* src, uint64_t bytes, void* strea
 
 const char* sv_status_string(sv_status st)
 {
-    switch (st) {
+    // read as an int: callers may pass any value, and a value outside the
+    // enumeration must not be loaded as the enum type
+    int code = 0;
+    std::memcpy(&code, &st, sizeof code);
+    switch (code) {
     case SV_OK: return "ok";
     case SV_ERR_INVALID_ARGUMENT: return "invalid argument";
     case SV_ERR_QUBIT_OUT_OF_RANGE: return "qubit out of range";

@@ -297,4 +297,7 @@ struct sv_state_s {
     size_t dterms_cap = 0;
     void* dfused = nullptr;         // device copy of fused block matrices
     size_t dfused_cap = 0;
+    bool failed = false;            // a HIP call failed during a call on this state (sticky)
+    std::string failed_msg;         // that failure's detail
+    bool inject_hip_error = false;  // testing hook: fail the next call as a HIP error
 };

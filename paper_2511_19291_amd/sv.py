@@ -18,7 +18,9 @@ from typing import Iterable, List, Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsv.so")
+# SV_LIB_PATH loads another build of the library (the sanitizer test loads a
+# build whose host code is instrumented); the default is the in-tree build.
+LIB_PATH = os.environ.get("SV_LIB_PATH") or os.path.join(_HERE, "libsv.so")
 
 KINDS = {"h": 1, "x": 2, "y": 3, "z": 4, "s": 5, "sdg": 6, "t": 7, "tdg": 8, "sx": 9,
          "rx": 10, "ry": 11, "rz": 12, "p": 13, "u3": 14, "swap": 15, "rxx": 16, "ryy": 17,
@@ -101,6 +103,8 @@ def lib() -> C.CDLL:
         "sv_alloc": [C.c_int, C.c_int, vp, vp, C.POINTER(vp)],
         "sv_free": [vp],
         "sv_device_ptr": [vp, C.POINTER(vp)],
+        "sv_state_failed": [vp, ip],
+        "sv_inject_hip_error": [vp],
         "sv_reset": [vp, u64],
         "sv_copy_state": [vp, vp, C.c_int],
         "sv_apply_gate": [vp, ip, C.c_int, ip, C.c_int, dp, i64, C.c_uint],
@@ -131,6 +135,7 @@ def lib() -> C.CDLL:
         "sv_batch_launch": [vp, vp, vp],
         "sv_batch_launch_pergate": [vp, vp, vp],
         "sv_batch_plan_free": [vp],
+        "sv_batch_set_spin_limit": [vp, C.c_int],
         "sv_stream_copy": [vp, vp, u64, vp],
         "sv_sample_exact": [vp, C.c_int, vp, i64, vp],
         "sv_sample_gaussian": [vp, C.c_int, vp, C.c_double, vp],
@@ -260,6 +265,13 @@ class State:
             pass
 
     # -- state
+    @property
+    def failed(self) -> bool:
+        """True once a HIP call failed during a call on this state (sticky)."""
+        f = C.c_int(0)
+        check(lib().sv_state_failed(self.h, C.byref(f)))
+        return bool(f.value)
+
     def reset(self, idx: int = 0) -> "State":
         self._changed()
         check(lib().sv_reset(self.h, idx))
@@ -592,6 +604,12 @@ class BatchPlan:
         import torch
 
         return torch.zeros((len(self.circuits), BATCH_OUT_STRIDE), dtype=torch.float64, device=self.stream.device)
+
+    def set_spin_limit(self, limit: int) -> None:
+        """Testing hook of the inter-pass wait (``sv_batch_set_spin_limit``):
+        polls before a wait gives up and the circuit's outputs become NaN;
+        negative: give up at once. 2**24 is the default."""
+        check(lib().sv_batch_set_spin_limit(self.h, int(limit)))
 
     def launch(self, dev_params, dev_out, pergate: bool = False) -> None:
         f = lib().sv_batch_launch_pergate if pergate else lib().sv_batch_launch

@@ -132,3 +132,13 @@ def test_batch_config_default_and_validation_host_only(svmod):
                                                  C.byref(h))
         assert st == 1 and not h.value, cfg
         assert b"must be" in svmod.lib().sv_last_error()
+
+
+def test_error_hooks_reject_null_state_host_only(svmod):
+    """The sticky-error query and the testing hook validate their state
+    argument like every other entry point (no GPU needed)."""
+    L = svmod.lib()
+    f = C.c_int(7)
+    assert L.sv_state_failed(None, C.byref(f)) == 1 and f.value == 7
+    assert L.sv_inject_hip_error(None) == 1
+    assert b"null state" in L.sv_last_error()

@@ -117,3 +117,28 @@ def test_batch_rejects_bad_plans(sv):
     bad = C.Circuit(3, [C.Op("rx", (0,), (), (5,))], np.zeros(1))
     with pytest.raises(svmod.SvError):
         svmod.BatchPlan([bad])
+
+
+def test_wait_that_gives_up_turns_the_circuit_nan(sv):
+    """The bounded inter-pass wait: when a tile of any pass after the first
+    gives up waiting (forced from the host: limit -1 gives up at once, so
+    every kernel still ends normally), the whole circuit's output is NaN, not
+    a finite value from an incomplete state; single-pass circuits (the whole
+    state in LDS) are unaffected. Restoring the default limit restores the
+    oracle's values on the same plan."""
+    rng = np.random.default_rng(17)
+    circuits = [C.encoded_ansatz(n, 3, rng) for n in (18, 11, 20, 16, 13)]
+    plan = svmod.BatchPlan(circuits)
+    passes = plan.info()["n_passes"]
+    assert passes > 3
+    plan.set_spin_limit(-1)
+    out = plan.run()
+    for i, c in enumerate(circuits):
+        if c.n > 14:                                  # wider than the tile: several passes
+            assert np.all(np.isnan(out[i])), (i, c.n, out[i, :4])
+        else:
+            z, _ = oracle.expval_z_all(oracle.run(c), c.n)
+            np.testing.assert_allclose(out[i, : c.n], z, atol=Z_TOL)
+    plan.set_spin_limit(1 << 24)
+    _check(plan.run(), circuits)
+    plan.free()
