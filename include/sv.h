@@ -243,6 +243,25 @@ sv_status sv_expval_pauli(sv_state s, const sv_pauli_term* terms, int n_terms, d
  * host output, stream synchronised. */
 sv_status sv_expval_z_all(sv_state s, double* out);
 
+/* sv_expval_z_all without any allocation, for callers that cannot allocate
+ * device memory mid-run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same kernels, same fixed summation
+ * order, so the values are bitwise those of sv_expval_z_all.
+ *   dev_out: caller-owned device memory of batch * (n + 1) doubles, 8-byte
+ *     aligned; same layout as sv_expval_z_all's out.
+ * The partial sums live in one fixed device buffer of the library, 2^20
+ * doubles (8 MiB) per GPU, held until the process ends. A call needs
+ * batch * (n + 1) of them for n <= 14 and batch * 2^(n - 14) * 15 above, so
+ * n = 30 fits at batch 1 and n = 28 up to batch 4; larger shapes return
+ * SV_ERR_UNSUPPORTED before anything is queued. The call is asynchronous on the state's stream (no host
+ * synchronisation, no hipMalloc, hipFree or memset; every partial is written
+ * before it is read, so nothing needs clearing). All calls on one GPU share
+ * that buffer: calls that may overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller. Errors:
+ * SV_ERR_INVALID_ARGUMENT (NULL or misaligned dev_out), SV_ERR_UNSUPPORTED,
+ * SV_ERR_HIP. */
+sv_status sv_expval_z_all_noalloc(sv_state s, double* dev_out);
+
 /* ------------------------------------------------------------- adjoint */
 
 /* Gradient of L_r = <psi_r| O |psi_r>, O = sum_t coeff_t P_t, with respect

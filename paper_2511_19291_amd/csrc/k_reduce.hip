@@ -8,6 +8,15 @@
 #include "sv_device.h"
 #include "sv_internal.h"
 
+#include <map>
+#include <mutex>
+
+// Fixed partial-sum buffer of the allocation-free <Z_i> reduction: one copy
+// per GPU, held until the process ends. Host code never passes this name to a
+// kernel (on the host it is only a stand-in for the symbol); it passes the
+// per-device address that static_zall_scratch() looks up.
+static __device__ __align__(256) double scratch[sv::kStaticZallDoubles];
+
 namespace sv {
 
 namespace {
@@ -295,6 +304,22 @@ void launch_sum_slots(const double* part, int grid, int nslots, double* out, hip
 {
     hipLaunchKernelGGL(k_sum_slots, dim3(nslots), dim3(kBlock), 0, st, part, grid, out);
     SV_HIP(hipGetLastError());
+}
+
+double* static_zall_scratch()
+{
+    static std::mutex mu;
+    static std::map<int, double*> addr;   // device -> address of its copy of `scratch`
+    int dev = 0;
+    SV_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* p = nullptr;
+    SV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) fail(SV_ERR_HIP, "hipGetSymbolAddress returned a null address for the Z scratch");
+    addr.emplace(dev, static_cast<double*>(p));
+    return static_cast<double*>(p);
 }
 
 }  // namespace sv

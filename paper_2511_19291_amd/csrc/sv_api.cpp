@@ -595,6 +595,20 @@ sv_status sv_expval_z_all(sv_state s, double* out)
     });
 }
 
+sv_status sv_expval_z_all_noalloc(sv_state s, double* dev_out)
+{
+    return guarded([&] {
+        check_state(s);
+        need(dev_out != nullptr, SV_ERR_INVALID_ARGUMENT, "dev_out is NULL");
+        need(((uintptr_t)dev_out & 7) == 0, SV_ERR_INVALID_ARGUMENT, "dev_out must be 8-byte aligned");
+        const uint64_t parts = zall_parts(s->n, s->batch);
+        need(parts <= kStaticZallDoubles, SV_ERR_UNSUPPORTED,
+             "batch * 2^(n - 14) * 15 partial sums (" + std::to_string(parts) +
+                 ") exceed the fixed buffer of " + std::to_string(kStaticZallDoubles) + " doubles");
+        launch_zall(all_rows(s), s->n, static_zall_scratch(), dev_out, s->stream);
+    });
+}
+
 sv_status sv_expval_pauli(sv_state s, const sv_pauli_term* terms, int n_terms, double* out)
 {
     return guarded([&] {

@@ -88,6 +88,11 @@ void launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
 // caller; sizes from the *_parts functions.
 uint64_t zall_parts(int n, int rows);                 // doubles of scratch
 void launch_zall(const Rows& r, int n, double* scratch, double* out /*[rows][n+1]*/, hipStream_t st);
+// Size (doubles) of the library's fixed device buffer for the allocation-free
+// <Z_i> reduction, and its address on the current device (looked up once per
+// device with hipGetSymbolAddress).
+constexpr uint64_t kStaticZallDoubles = 1ull << 20;   // 8 MiB
+double* static_zall_scratch();
 
 struct PauliGroup {             // terms sharing one x mask
     uint64_t x_mask;

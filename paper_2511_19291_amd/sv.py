@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
                          C.c_int, dp, ip],
         "sv_expval_pauli": [vp, C.POINTER(SvPauliTerm), C.c_int, dp],
         "sv_expval_z_all": [vp, dp],
+        "sv_expval_z_all_noalloc": [vp, vp],
         "sv_adjoint_grad": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm), C.c_int,
                             vp, dp, dp, dp],
         "sv_adjoint_grad_weighted": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm),
@@ -398,6 +399,18 @@ class State:
         out = np.zeros((self.batch, self.n + 1), dtype=np.float64)
         check(lib().sv_expval_z_all(self.h, _dptr(out)))
         return out
+
+    def expval_z_all_into(self, out) -> None:
+        """Write [batch, n + 1] FP64 <Z_i> and ||psi||^2 into ``out``, a
+        caller-allocated contiguous float64 device tensor, with no
+        allocation by the library (the fixed-buffer entry point);
+        asynchronous on the state's stream."""
+        import torch
+
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+                and out.is_contiguous() and out.numel() == self.batch * (self.n + 1)):
+            raise ValueError(f"out must be a contiguous float64 device tensor of {self.batch * (self.n + 1)} elements")
+        check(lib().sv_expval_z_all_noalloc(self.h, C.c_void_p(out.data_ptr())))
 
     def expval(self, terms: Sequence[Tuple[float, int, int]]) -> np.ndarray:
         """[batch, n_terms]: coeff_t <P_t>."""
