@@ -502,6 +502,8 @@ typedef struct sv_batch_stats {
     int32_t n_fused_phases;
     int64_t fused_amp_phases;
     int64_t gate_amp_updates;
+    int32_t max_circuit_fused_phases;   /* most fused phases any one circuit runs */
+    int32_t max_circuit_gate_sweeps;    /* most gates any one circuit applies one by one */
 } sv_batch_stats;
 
 sv_status sv_batch_plan_stats(sv_batch_plan p, sv_batch_stats* out);
@@ -542,6 +544,8 @@ typedef struct sv_batch_trial {
     sv_batch_config config;   /* effective configuration */
     double ms;                /* mean time of one launch (graph replay) */
     double max_dev;           /* max |out - out of the default configuration|; NaN if an output was NaN */
+    double tol;               /* the bound max_dev must meet to be chosen: the sum of both
+                                 configurations' rounding-error bounds on <Z_i> */
 } sv_batch_trial;
 
 /* Autotuner of the batched launch: times the batch (the same arguments as

@@ -88,6 +88,28 @@ struct DevBuf {
     ~DevBuf() { (void)hipFree(p); }
 };
 
+// Bound on |d<Z_i>| of one circuit of a plan from its rounding errors.
+// Each sweep (a fused 16 x 16 phase, or one gate applied on its own) forms
+// every output component as a dot product of L = 2 D real terms whose
+// relative errors are bounded by eps: one-by-one FP32 gates (D <= 4)
+// (L + 1) u; FP32 phases in the three-real-product form sqrt2 (L + 3) u;
+// BF16x3 phases 3 * 2^-16 (split residuals of both operands, the dropped
+// lo*lo product) + (3 L + 1) u, with u = 2^-24. Treating the errors as
+// independent and mean zero (Hoeffding), a sweep adds about sqrt2 eps to
+// ||dpsi||, sweeps add in quadrature, and with a factor 4:
+// ||dpsi|| <= B = 4 sqrt(sum 2 eps^2), |d<Z_i>| <= 2 B + B^2.
+double batch_z_bound(const sv_batch_stats& s, int phase_mode)
+{
+    const double u = std::ldexp(1.0, -24);
+    const double eps_gate = (8 + 1) * u;
+    const double eps_fused = phase_mode == kPhaseBf16x3 ? 3 * std::ldexp(1.0, -16) + (3 * 32 + 1) * u
+                                                        : std::sqrt(2.0) * (32 + 3) * u;
+    const double var = 2.0 * (s.max_circuit_fused_phases * eps_fused * eps_fused +
+                              s.max_circuit_gate_sweeps * eps_gate * eps_gate);
+    const double B = 4.0 * std::sqrt(var);
+    return 2.0 * B + B * B;
+}
+
 bool same_effective(const sv_batch_config& a, const sv_batch_config& b)
 {
     auto reg = [](const sv_batch_config& c) { return c.reg_min_bits > c.tile_bits ? 99 : c.reg_min_bits; };
@@ -121,7 +143,7 @@ sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* co
         std::vector<double> ref, got(n_out);
         std::vector<sv_batch_trial> done;
         Timer tm(st);
-        const double tol = 1e-4;
+        double ref_bound = -1.0;   // the default configuration's <Z_i> error bound
 
         auto run = [&](sv_batch_config cfg) -> const sv_batch_trial& {
             for (const sv_batch_trial& t : done)
@@ -131,6 +153,11 @@ sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* co
             sv_batch_trial t{};
             try {
                 ok_or_throw(sv_batch_plan_info(p, &t.config, nullptr, nullptr, nullptr));
+                sv_batch_stats stats{};
+                ok_or_throw(sv_batch_plan_stats(p, &stats));
+                const double bound = batch_z_bound(stats, t.config.phase_mode);
+                if (ref_bound < 0.0) ref_bound = bound;
+                t.tol = ref_bound + bound;
                 double* o = static_cast<double*>(dout.p);
                 ok_or_throw(sv_batch_launch(p, dev_params, o));   // warm-up (and graph capture)
                 SV_HIP(hipMemcpyAsync(got.data(), o, n_out * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -158,7 +185,7 @@ sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* co
             done.push_back(t);
             return done.back();
         };
-        auto usable = [&](const sv_batch_trial& t) { return t.max_dev <= tol; };
+        auto usable = [&](const sv_batch_trial& t) { return t.max_dev <= t.tol; };
         auto better = [&](const sv_batch_trial& a, const sv_batch_trial* b) {
             return usable(a) && (b == nullptr || a.ms < b->ms);
         };

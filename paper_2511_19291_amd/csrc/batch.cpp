@@ -357,6 +357,7 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                 bc.zpart_off = zrows;
                 zrows += bc.ntiles;
             }
+            int32_t circ_fused = 0, circ_gates = 0;   // this circuit's fused phases and one-by-one gates
             std::vector<Pass> pl;
             if (n <= cfg.tile_bits) {
                 Pass one;
@@ -443,8 +444,10 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                         if (x.frag >= 0) {
                             p->stats.n_fused_phases += 1;
                             p->stats.fused_amp_phases += amps;
+                            circ_fused += 1;
                         } else {
                             p->stats.gate_amp_updates += amps * (x.op_end - x.op_begin);
+                            circ_gates += x.op_end - x.op_begin;
                         }
                         phase.push_back(x);
                     }
@@ -459,12 +462,15 @@ sv_status sv_batch_plan_create_ex(int n_circuits, const int* n_qubits, const sv_
                 } else {
                     bops.insert(bops.end(), pops.begin(), pops.end());
                     p->stats.gate_amp_updates += (1ll << n) * (int64_t)pops.size();
+                    circ_gates += (int32_t)pops.size();
                 }
                 bp.op_end = (int)bops.size();
                 pass.push_back(bp);
             }
             bc.pass_end = (int)pass.size();
             circ.push_back(bc);
+            p->stats.max_circuit_fused_phases = std::max(p->stats.max_circuit_fused_phases, circ_fused);
+            p->stats.max_circuit_gate_sweeps = std::max(p->stats.max_circuit_gate_sweeps, circ_gates);
         }
         need(p->n_params_total < (1ll << 31) && bops.size() < (1u << 31) && frag_phase.size() < (1u << 26),
              SV_ERR_UNSUPPORTED, "batch too large");

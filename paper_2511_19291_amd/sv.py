@@ -67,11 +67,12 @@ class SvBatchConfig(C.Structure):
 
 class SvBatchStats(C.Structure):
     _fields_ = [("n_tasks", C.c_int32), ("n_passes", C.c_int32), ("n_phases", C.c_int32),
-                ("n_fused_phases", C.c_int32), ("fused_amp_phases", C.c_int64), ("gate_amp_updates", C.c_int64)]
+                ("n_fused_phases", C.c_int32), ("fused_amp_phases", C.c_int64), ("gate_amp_updates", C.c_int64),
+                ("max_circuit_fused_phases", C.c_int32), ("max_circuit_gate_sweeps", C.c_int32)]
 
 
 class SvBatchTrial(C.Structure):
-    _fields_ = [("config", SvBatchConfig), ("ms", C.c_double), ("max_dev", C.c_double)]
+    _fields_ = [("config", SvBatchConfig), ("ms", C.c_double), ("max_dev", C.c_double), ("tol", C.c_double)]
 
 
 class SvFusionChoice(C.Structure):
@@ -650,7 +651,7 @@ class BatchPlan:
 
 def batch_autotune(circuits: Sequence, reps: int = 3, device=None, params_list=None):
     """Time the batch under the library's staged search over launch shapes.
-    Returns (best config dict, list of trials {config, ms, max_dev})."""
+    Returns (best config dict, list of trials {config, ms, max_dev, tol})."""
     import torch
 
     circuits = list(circuits)
@@ -670,8 +671,8 @@ def batch_autotune(circuits: Sequence, reps: int = 3, device=None, params_list=N
     nt = C.c_int()
     check(lib().sv_batch_autotune(nc, nq, ops_arr, nops, npar, C.c_void_p(dparams.data_ptr()), reps,
                                   C.c_void_p(stream.cuda_stream), C.byref(best), trials, cap, C.byref(nt)))
-    out = [{"config": trials[i].config.as_dict(), "ms": float(trials[i].ms), "max_dev": float(trials[i].max_dev)}
-           for i in range(min(nt.value, cap))]
+    out = [{"config": trials[i].config.as_dict(), "ms": float(trials[i].ms), "max_dev": float(trials[i].max_dev),
+            "tol": float(trials[i].tol)} for i in range(min(nt.value, cap))]
     return best.as_dict(), out
 
 
