@@ -204,6 +204,19 @@ class InvertibleUnitary(torch.nn.Module):
                 m(qdev)
 
 
+def ring_ansatz(n_wires: int, layers: int, rotation: str = "ry", encoding: str = "ry") -> InvertibleUnitary:
+    """A layered model of the ladder family the paper profiles (Sec. 5,
+    Fig. 3; Appendix A): feature i encoded as the angle of an ``encoding``
+    gate on wire i, then ``layers`` x [a trainable ``rotation`` on every
+    wire, a CNOT ring i -> (i + 1) mod n]."""
+    mods: list = [GeneralEncoder([{"func": encoding, "wires": [w], "input_idx": [w]} for w in range(n_wires)])]
+    rot, cx = MODULES[rotation], MODULES["cx"]
+    for _ in range(layers):
+        mods.extend(rot(wires=[w]) for w in range(n_wires))
+        mods.extend(cx(wires=[w, (w + 1) % n_wires]) for w in range(n_wires))
+    return InvertibleUnitary(mods)
+
+
 def measure_allZ(qdev: QuantumDevice, shots: int = 0, training: bool = True, generator=None) -> torch.Tensor:
     """<Z_i> of every wire for every row, [bsz, n_wires].
 

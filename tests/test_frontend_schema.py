@@ -30,11 +30,12 @@ def test_forms_generated_for_every_entry():
         assert not any(p.requires_grad for p in frozen.parameters())
 
 
-def test_listing_structure_builds_on_cpu():
-    nq = 5
-    enc = F.GeneralEncoder([{"func": "ry", "wires": [i], "input_idx": [i]} for i in range(nq)])
-    mods = [enc]
-    for _ in range(3):
-        mods += [F.CX(wires=[i, (i + 1) % nq]) for i in range(nq)] + [F.RY(wires=[i]) for i in range(nq)]
-    mod = F.InvertibleUnitary(mods)
-    assert sum(p.numel() for p in mod.parameters()) == 3 * nq
+def test_ring_ansatz_structure_builds_on_cpu():
+    nq, layers = 5, 4
+    mod = F.ring_ansatz(nq, layers, rotation="rz")
+    assert isinstance(mod.layers[0], F.GeneralEncoder)
+    names = [m.name for m in mod.layers[1:]]
+    assert names == (["rz"] * nq + ["cx"] * nq) * layers
+    assert sum(p.numel() for p in mod.parameters()) == layers * nq
+    rings = [m.wires for m in mod.layers[1:] if m.name == "cx"][:nq]
+    assert rings == [[w, (w + 1) % nq] for w in range(nq)]

@@ -1,7 +1,8 @@
-"""The front end on the GPU: the appendix example's training loop end to end
-(encoder, CNOT ring, trainable RY modules, measure_allZ, Adam), checked
-against the oracle, and the three generated forms of every gate against
-each other and the oracle."""
+"""The front end on the GPU: a layered model built with the front end
+(encoder, trainable rotations, CNOT rings, measure_allZ) trained on its
+inputs and angles, checked against the oracle, and the three generated forms
+of every gate against each other and the oracle. The model family and the
+API names are those of the paper's Appendix A."""
 
 import numpy as np
 import pytest
@@ -14,67 +15,61 @@ from paper_2511_19291_amd import frontend as F
 pytestmark = pytest.mark.gpu
 
 
-def _listing(nq):
-    enc = F.GeneralEncoder([{"func": "ry", "wires": [i], "input_idx": [i]} for i in range(nq)])
-    base = [enc]
-    for _ in range(3):
-        base = base + [F.CX(wires=[i, (i + 1) % nq]) for i in range(nq)] + [F.RY(wires=[i]) for i in range(nq)]
-    return F.InvertibleUnitary(base)
-
-
-def _oracle_listing(mod, x_row, nq):
-    """The same circuit written directly for the oracle: parameters are the
-    row's inputs, then every RY module's angle in order."""
+def _oracle_circuit(mod, x_row, nq):
+    """The model written directly for the oracle: parameters are the row's
+    inputs, then every trainable module's angle in order."""
     b = C._Builder(nq)
-    for i in range(nq):
-        b.gate("ry", [i], values=[float(x_row[i])])
+    for f in mod.layers[0].func_list:
+        b.gate(f["func"], f["wires"], values=[float(x_row[f["input_idx"][0]])])
     for m in mod.layers[1:]:
         kind, nc, nt, npar = F.GATE_SCHEMA[m.name]
         vals = [float(v) for v in m.params.detach()] if npar else []
         b.gate(kind, m.wires[nc:], m.wires[:nc], values=vals)
-    return b.build("listing")
+    return b.build("front_end_model")
 
 
-def test_listing_training_loop_vs_oracle(sv):
-    torch.manual_seed(0)
-    nq, batch = 6, 4
-    qdev = F.QuantumDevice(nq, bsz=batch, device="cuda", world_sz=1, invertible=True)
-    mod = _listing(nq)
+def _squared_error(qdev, mod, x, target):
+    qdev.reset_states()
+    mod(qdev, x)
+    z = F.measure_allZ(qdev, shots=0, training=True)
+    return z, ((z - target) ** 2).sum()
+
+
+@pytest.mark.parametrize("rotation", ["ry", "rx"])
+def test_model_gradients_and_training_vs_oracle(sv, rotation):
+    gen = torch.Generator().manual_seed(3)
+    nq, batch, layers = 5, 3, 2
+    qdev = F.QuantumDevice(nq, bsz=batch, device="cuda")
+    mod = F.ring_ansatz(nq, layers, rotation=rotation)
     mod.train()
-    x = torch.nn.Parameter(torch.rand([batch, nq], device="cuda", dtype=torch.float64) * torch.pi / 3)
-
-    def fun(inp):
-        qdev.reset_states()
-        mod(qdev, inp)
-        return F.measure_allZ(qdev, shots=0, training=True)
-
-    # first step: outputs and gradients (inputs and ansatz angles) vs the oracle
-    out = fun(x)
-    loss = out.abs().sum()
+    x = torch.nn.Parameter((torch.rand((batch, nq), generator=gen, dtype=torch.float64) * 2 - 1).cuda())
+    target = torch.linspace(-0.5, 0.5, nq, dtype=torch.float64, device="cuda")
+    z, loss = _squared_error(qdev, mod, x, target)
     loss.backward()
+    # outputs and gradients (inputs and every trainable angle) vs the oracle
     xs = x.detach().cpu().numpy()
-    ry_mods = [m for m in mod.layers[1:] if m.name == "ry"]
-    g_theta = np.zeros(len(ry_mods))
+    rots = [m for m in mod.layers[1:] if m.name == rotation]
+    g_theta = np.zeros(len(rots))
+    t = target.cpu().numpy()
     for r in range(batch):
-        circ = _oracle_listing(mod, xs[r], nq)
-        z, _ = oracle.expval_z_all(oracle.run(circ), nq)
-        np.testing.assert_allclose(out[r].detach().cpu().numpy(), z[:nq], atol=2e-6)
-        w = [(float(np.sign(z[i])), 0, 1 << i) for i in range(nq)]
+        circ = _oracle_circuit(mod, xs[r], nq)
+        zr, _ = oracle.expval_z_all(oracle.run(circ), nq)
+        np.testing.assert_allclose(z[r].detach().cpu().numpy(), zr[:nq], atol=2e-6)
+        w = [(2.0 * float(zr[i] - t[i]), 0, 1 << i) for i in range(nq)]   # d loss / d <Z_i>
         g = oracle.grad_param_shift(circ, w)
         np.testing.assert_allclose(x.grad[r].cpu().numpy(), g[:nq], atol=1e-5)
         g_theta += g[nq:]
-    got_theta = np.array([float(m.params.grad[0]) for m in ry_mods])
+    got_theta = np.array([float(m.params.grad[0]) for m in rots])
     np.testing.assert_allclose(got_theta, g_theta, atol=1e-5 * batch)
-    # the loop of the example: the loss goes down
-    opt = torch.optim.Adam([x] + list(mod.parameters()), lr=0.05)
-    losses = []
-    for _ in range(10):
+    # a few optimiser steps on inputs and angles lower the loss
+    opt = torch.optim.SGD([x] + list(mod.parameters()), lr=0.1)
+    first = loss.item()
+    for _ in range(8):
         opt.zero_grad()
-        loss = fun(x).abs().sum()
-        losses.append(loss.item())
+        _, loss = _squared_error(qdev, mod, x, target)
         loss.backward()
         opt.step()
-    assert losses[-1] < losses[0]
+    assert loss.item() < first
 
 
 def test_three_forms_agree(sv):
