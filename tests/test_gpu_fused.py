@@ -26,12 +26,13 @@ def _block_bound(blocks, mode):
     eps = []
     for targets, _ in blocks:
         k = len(targets)
-        eps.append(errmodel.eps_bf16x3_block(k) if mode == svmod.FUSED_BF16X3 else errmodel.eps_fp32_block(k))
+        eps.append(errmodel.eps_bf16x3_block(k) if mode == svmod.FUSED_BF16X3 else errmodel.eps_fp32_block(k, gauss=True))
     return errmodel.state_bound(eps)
 
 
 def _assert_state(out, ref, B, label=""):
-    d = out.astype(np.complex128) - ref
+    out = out.astype(np.complex128)
+    d = out - ref
     dn = float(np.linalg.norm(d))
     infid = 1.0 - abs(np.vdot(ref, out)) ** 2 / np.vdot(out, out).real
     print(f"{label} max|dpsi| {np.max(np.abs(d)):.2e} ||dpsi|| {dn:.2e} (bound {B:.2e}) 1-F {infid:.2e} "
