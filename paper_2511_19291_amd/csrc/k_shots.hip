@@ -10,10 +10,11 @@
 //      block's offset are deterministic);
 //   3. each shot finds its block by binary search over the scanned sums
 //      (an L2-resident array) and is bucketed by block (counting sort);
-//   4. each block that holds at least one shot is read once more by one
-//      wave: the lanes' masses are scanned with shuffles in a fixed order,
-//      and each of its shots finds its lane by binary search and its index
-//      by a sequential walk through that lane's amplitudes.
+//   4. each block that holds at least one shot is resolved by one wave:
+//      every shot's chunk of 128 amplitudes (its mass known from step 1) is
+//      read whole and coalesced, its probabilities scanned across the lanes
+//      in a fixed order, and the shot's index found by a ballot (states
+//      below 7 qubits: a lane per amplitude run, sequential walk).
 // The counts of the indices over all shots are one draw of the multinomial
 // M(shots, p). This is the paper's hierarchical view restricted to one
 // device: the blocks play the role of the groups whose masses q_j are known
@@ -55,28 +56,53 @@ constexpr int kChunkBits = 7;
 static_assert(kShotBits - kChunkBits <= 6, "a lane per chunk");
 
 // 1. probability mass of each block of 2^bb amplitudes (bb <= kShotBits).
-// With chunks: wave w's pass k reads chunk 4k + w in memory order (lane l:
-// amplitudes 2l, 2l + 1 of the chunk); the chunk's mass is the wave's sum in
-// a fixed order (butterfly; lane 0's value is stored), and the block's mass
-// is the sum of its chunks' in chunk order.
-__global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ psi, int bb, double* __restrict__ mass,
-                                                    double* __restrict__ csum)
+// With chunks: wave w reads chunks 8w .. 8w + 7 of the block in memory order
+// (one float4 per lane and chunk: lane l holds amplitudes 2l, 2l + 1), eight
+// loads in flight. The 64-lane sums of the eight chunks are formed together
+// by a reduce-scatter butterfly (xor 32, 16, 8 halve the values a lane
+// carries, xor 4, 2, 1 finish one chunk per group of eight lanes): ten FP64
+// exchanges for eight chunks, in a fixed order. The block's mass is the sum
+// of its chunks' in chunk order. (Measured: one wave per block with two
+// passes of sixteen chunks is 24 % slower at 30 qubits.)
+__global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ psi, int bb, uint64_t nb,
+                                                    double* __restrict__ mass, double* __restrict__ csum)
 {
     __shared__ double sh[(1 << (kShotBits - kChunkBits)) > kST / 64 ? (1 << (kShotBits - kChunkBits)) : kST / 64];
     const uint64_t base = (uint64_t)blockIdx.x << bb;
     const uint32_t bs = 1u << bb;
+    (void)nb;
     if (bb >= kChunkBits) {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const uint32_t nch = 1u << (bb - kChunkBits);
         const float4* p4 = reinterpret_cast<const float4*>(psi + base);
-        for (uint32_t c = w; c < nch; c += kST / 64) {
-            const float4 v = p4[c * 64 + lane];
-            double t = prob(make_float2(v.x, v.y)) + prob(make_float2(v.z, v.w));
+        if ((uint32_t)(8 * w) < nch) {
+            float4 v[8];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-            if (lane == 0) {
-                sh[c] = t;
-                csum[((uint64_t)blockIdx.x << (kShotBits - kChunkBits)) + c] = t;
+            for (int i = 0; i < 8; ++i)
+                v[i] = (uint32_t)(8 * w + i) < nch ? p4[(8 * w + i) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            double t[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) t[i] = prob(make_float2(v[i].x, v[i].y)) + prob(make_float2(v[i].z, v[i].w));
+            const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+            double u4[4], u2[2];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double keep = b5 ? t[4 + j] : t[j], send = b5 ? t[j] : t[4 + j];
+                u4[j] = keep + __shfl_xor(send, 32, 64);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const double keep = b4 ? u4[2 + j] : u4[j], send = b4 ? u4[j] : u4[2 + j];
+                u2[j] = keep + __shfl_xor(send, 16, 64);
+            }
+            double c = (b3 ? u2[1] : u2[0]) + __shfl_xor(b3 ? u2[0] : u2[1], 8, 64);
+            c += __shfl_xor(c, 4, 64);
+            c += __shfl_xor(c, 2, 64);
+            c += __shfl_xor(c, 1, 64);
+            const uint32_t ch = 8 * w + 4 * b5 + 2 * b4 + b3;      // the chunk this lane's group summed
+            if ((lane & 7) == 0 && ch < nch) {
+                sh[ch] = c;
+                csum[((uint64_t)blockIdx.x << (kShotBits - kChunkBits)) + ch] = c;
             }
         }
         __syncthreads();
@@ -201,86 +227,161 @@ __global__ __launch_bounds__(kST) void k_shot_scatter(const uint32_t* __restrict
 // (or, past the last lane, in the block).
 __device__ __forceinline__ double lane_prob(const float2* __restrict__ p, uint32_t i) { return prob(p[i]); }
 
-// Last index of non-zero probability in chunk c of a block (-1 if none).
-__device__ int chunk_last_nonzero(const float2* __restrict__ blk, uint32_t c)
+// Blocks of at least 128 amplitudes: the shots, sorted by block, are taken
+// eight at a time per wave, eight lanes per shot (lane i of a group). The
+// group first finds the shot's chunk of 128 amplitudes from the block's chunk
+// masses as k_block_mass stored them (lane i: chunks 4i .. 4i + 3, running
+// sums in chunk order, then across the eight lanes in a fixed order): the
+// first chunk whose running mass exceeds the shot's remainder. It then reads
+// that chunk whole (lane i: amplitudes 16i .. 16i + 15, 128 contiguous bytes)
+// and finds the first index of non-zero probability whose running sum (in
+// index order) exceeds what remains. If rounding leaves none, the last index
+// of non-zero probability in the chunk (past the last chunk: in the last
+// chunk of non-zero mass). Only the chunks that hold a shot are read, and no
+// index of zero probability is ever returned.
+__device__ __forceinline__ double group_incl8(double v, int gi)
 {
-    const float2* ch = blk + ((uint64_t)c << kChunkBits);
-    int last = -1;
-    for (int i = 0; i < (1 << kChunkBits); ++i)
-        if (prob(ch[i]) > 0.0) last = (int)(c << kChunkBits) + i;
-    return last;
+    // inclusive scan over the eight lanes of a group (Hillis-Steele, fixed order)
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        const double t = __shfl_up(v, off, 8);
+        if (gi >= off) v += t;
+    }
+    return v;
 }
 
-// Blocks of at least 128 amplitudes: lane c takes chunk c's mass as
-// k_block_mass stored it, and an inclusive scan over the lanes (fixed order)
-// gives the chunks' running masses. Each shot (a lane per shot) finds its
-// chunk by binary search over those sums and its index by reading that
-// chunk in order (sixteen float4 loads in flight at a time): the first
-// index whose running sum exceeds the remainder; if rounding leaves none,
-// the last index of non-zero probability in the chunk (or, past the last
-// chunk, in the block: in the last chunk of non-zero mass). Only the chunks
-// that hold a shot are read.
-__device__ __forceinline__ void resolve_chunked(const float2* __restrict__ blk, int bb, uint64_t base, int lane,
-                                                const double* __restrict__ csum, uint32_t first, uint32_t nshot,
-                                                const uint32_t* __restrict__ order, const double* __restrict__ rem,
-                                                int64_t* __restrict__ out)
+__device__ __forceinline__ void resolve_group(const float2* __restrict__ psi, int bb, const uint32_t* __restrict__ order,
+                                              const uint32_t* __restrict__ blk, const double* __restrict__ rem,
+                                              const double* __restrict__ csum, uint32_t j, bool valid, int lane,
+                                              int64_t* __restrict__ out)
 {
+    const int gi = lane & 7;                          // lane within the shot's group
+    const int gshift = lane & ~7;                     // first lane of the group
     const uint32_t nch = 1u << (bb - kChunkBits);
-    const bool own = (uint32_t)lane < nch;
-    const double mine = own ? csum[lane] : 0.0;
-    const uint64_t nz = __ballot(own && mine > 0.0);        // chunks holding a non-zero probability
-    double cincl = mine;
+    const uint32_t sid = valid ? order[j] : 0u;
+    const uint32_t b = valid ? blk[sid] : 0u;
+    const double r = valid ? rem[sid] : 0.0;
+    // chunk masses of the block: lane gi holds chunks 4 gi .. 4 gi + 3
+    const double* cm = csum + ((uint64_t)b << (kShotBits - kChunkBits));
+    double run[4], m[4];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_up(cincl, off, 64);
-        if (lane >= off) cincl += t;
+    for (int k = 0; k < 4; ++k) m[k] = (valid && (uint32_t)(4 * gi + k) < nch) ? cm[4 * gi + k] : 0.0;
+    run[0] = m[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) run[k] = run[k - 1] + m[k];
+    const double lane_tot = run[3];
+    // every cross-lane exchange below runs on all lanes (the groups diverge)
+    const double incl = group_incl8(lane_tot, gi);
+    const double up = __shfl_up(incl, 1, 8);
+    const double pre = gi > 0 ? up : 0.0;
+    int kc = -1;                                      // this lane's first chunk past r
+#pragma unroll
+    for (int k = 3; k >= 0; --k)
+        if ((uint32_t)(4 * gi + k) < nch && pre + run[k] > r) kc = k;
+    double mine_before = pre;                         // running mass before chunk 4 gi + kc
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (k < kc) mine_before = pre + run[k];
+    int lastc = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (m[k] > 0.0) lastc = 4 * gi + k;
+    const uint64_t gmask = 0xffull << gshift;
+    const uint64_t found = __ballot(valid && kc >= 0) & gmask;
+    const uint64_t nzc = __ballot(valid && lastc >= 0) & gmask;
+    const int L = found ? __builtin_ctzll(found) - gshift : 0;
+    const int H = nzc ? 63 - __builtin_clzll(nzc) - gshift : 0;
+    const int kL = __shfl(kc, L, 8);
+    const double excl = __shfl(mine_before, L, 8);
+    const int lc = __shfl(lastc, H, 8);
+    int chunk = found ? 4 * L + kL : lc;
+    // rounding past the last chunk: the last chunk of non-zero mass, its last
+    // non-zero index (need = 1e300 is never exceeded)
+    const double need = found ? r - excl : 1e300;
+    if (chunk < 0) chunk = 0;
+    // the chunk, read 128 contiguous bytes per group and load: load t gives
+    // lane gi amplitudes 16 t + 2 gi, 16 t + 2 gi + 1 (pair sum q[t]), so
+    // sub-block t (amplitudes 16 t .. 16 t + 15) sits across the group
+    const float4* c4 = reinterpret_cast<const float4*>(psi + ((uint64_t)b << bb) + ((uint64_t)chunk << kChunkBits)) + gi;
+    float4 v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = valid ? c4[8 * t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double p0[8], p1[8], q[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        p0[t] = prob(make_float2(v[t].x, v[t].y));
+        p1[t] = prob(make_float2(v[t].z, v[t].w));
+        q[t] = p0[t] + p1[t];
     }
-    for (uint32_t j0 = 0; j0 < nshot; j0 += 64) {
-        const bool have = j0 + lane < nshot;
-        const uint32_t s = have ? order[first + j0 + lane] : 0;
-        const double r = have ? rem[s] : 0.0;
-        // first chunk whose inclusive mass exceeds r
-        uint32_t lo = 0, hi = nch;
+    // sub-block totals by reduce-scatter over the group (lane gi ends with
+    // sub-block gi's total), then their running sums across the group
+    const bool g2 = (gi >> 2) & 1, g1 = (gi >> 1) & 1, g0 = gi & 1;
+    double r4[4], r2[2];
 #pragma unroll
-        for (int step = 0; step < 7; ++step) {
-            const uint32_t mid = lo + (hi - lo) / 2;
-            const double im = __shfl(cincl, (int)min(mid, 63u), 64);
-            if (lo < hi) {
-                if (im > r) hi = mid;
-                else lo = mid + 1;
-            }
+    for (int j = 0; j < 4; ++j) {
+        const double keep = g2 ? q[4 + j] : q[j], send = g2 ? q[j] : q[4 + j];
+        r4[j] = keep + __shfl_xor(send, 4, 8);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double keep = g1 ? r4[2 + j] : r4[j], send = g1 ? r4[j] : r4[2 + j];
+        r2[j] = keep + __shfl_xor(send, 2, 8);
+    }
+    const double stot = (g0 ? r2[1] : r2[0]) + __shfl_xor(g0 ? r2[0] : r2[1], 1, 8);
+    // (lane gi now holds sub-block gi's total)
+    const double tot_in_order = stot;
+    const double sincl = group_incl8(tot_in_order, gi);
+    const double sup = __shfl_up(sincl, 1, 8);
+    const double spre = gi > 0 ? sup : 0.0;
+    // the sub-block holding the crossing: the first whose running sum exceeds need
+    const uint64_t shit = __ballot(valid && sincl > need) & gmask;
+    const uint64_t snz = __ballot(valid && tot_in_order > 0.0) & gmask;
+    const int T = shit ? __builtin_ctzll(shit) - gshift : (snz ? 63 - __builtin_clzll(snz) - gshift : 0);
+    const double sbefore = __shfl(spre, T, 8);
+    const double need2 = shit ? need - sbefore : 1e300;
+    // inside sub-block T: lane gi's pair (amplitudes 16 T + 2 gi, + 1)
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        if (t == T) {
+            a0 = p0[t];
+            a1 = p1[t];
         }
-        const double excl = __shfl(cincl, (int)(lo > 0 ? min(lo - 1, 63u) : 0u), 64);
-        if (!have) continue;
-        int idx = -1;
-        if (lo < nch) {
-            // the chunk in index order, 32 amplitudes (16 independent loads)
-            // at a time
-            const double need = r - (lo > 0 ? excl : 0.0);
-            const float4* c4 = reinterpret_cast<const float4*>(blk + ((uint64_t)lo << kChunkBits));
-            double acc = 0.0;
-            int at = -1, lastnz = -1;
-            for (uint32_t g = 0; g < (1u << kChunkBits) / 2 && at < 0; g += 16) {
-                float4 w[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) w[q] = c4[g + q];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const double p0 = prob(make_float2(w[q].x, w[q].y)), p1 = prob(make_float2(w[q].z, w[q].w));
-                    acc += p0;
-                    if (p0 > 0.0) lastnz = (int)(2 * (g + q));
-                    if (at < 0 && acc > need) at = (int)(2 * (g + q));
-                    acc += p1;
-                    if (p1 > 0.0) lastnz = (int)(2 * (g + q) + 1);
-                    if (at < 0 && acc > need) at = (int)(2 * (g + q) + 1);
-                }
-            }
-            // (when at < 0 the whole chunk was read, so lastnz is its last)
-            const int pick = at >= 0 ? at : lastnz;
-            if (pick >= 0) idx = (int)(lo << kChunkBits) + pick;
-        }
-        if (idx < 0 && nz) idx = chunk_last_nonzero(blk, 63u - (uint32_t)__builtin_clzll(nz));
-        out[s] = idx >= 0 ? (int64_t)(base + (uint32_t)idx) : -1;
+    const double pincl = group_incl8(a0 + a1, gi);
+    const double pup = __shfl_up(pincl, 1, 8);
+    const double ppre = gi > 0 ? pup : 0.0;
+    const bool c0 = a0 > 0.0 && ppre + a0 > need2;
+    const bool c1 = a1 > 0.0 && ppre + a0 + a1 > need2;
+    const uint64_t hit = __ballot(valid && (c0 || c1)) & gmask;
+    const uint64_t anz = __ballot(valid && (a0 > 0.0 || a1 > 0.0)) & gmask;
+    const uint64_t first0 = __ballot(valid && c0) & gmask;
+    const uint64_t odd_nz = __ballot(valid && a1 > 0.0) & gmask;
+    int idx = -1;
+    if (hit) {
+        const int L = __builtin_ctzll(hit);
+        idx = 16 * T + 2 * (L - gshift) + (((first0 >> L) & 1) ? 0 : 1);
+    } else if (anz) {
+        const int H = 63 - __builtin_clzll(anz);
+        idx = 16 * T + 2 * (H - gshift) + (((odd_nz >> H) & 1) ? 1 : 0);
+    }
+    if (valid && gi == 0)
+        out[sid] = idx >= 0 ? (int64_t)(((uint64_t)b << bb) + ((uint64_t)chunk << kChunkBits) + (uint32_t)idx) : -1;
+}
+
+__global__ __launch_bounds__(kST) void k_shot_resolve_chunked(const float2* __restrict__ psi, int bb, uint32_t nb,
+                                                              const uint32_t* __restrict__ cinc,
+                                                              const uint32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ blk,
+                                                              const double* __restrict__ rem,
+                                                              const double* __restrict__ csum,
+                                                              int64_t* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t total = cinc[nb - 1];              // shots that landed in a block
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kST / 64);
+    for (uint64_t w = (uint64_t)blockIdx.x * (kST / 64) + (threadIdx.x >> 6); 8 * w < total; w += nwaves) {
+        const uint64_t j = 8 * w + (lane >> 3);
+        resolve_group(psi, bb, order, blk, rem, csum, (uint32_t)j, j < total, lane, out);
     }
 }
 
@@ -293,16 +394,6 @@ __global__ __launch_bounds__(kST) void k_shot_resolve(const float2* __restrict__
     const uint32_t wave = blockIdx.x * (kST / 64) + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * (kST / 64);
     const uint32_t bs = 1u << bb;
-    if (bb >= kChunkBits) {
-        for (uint32_t b = wave; b < nb; b += nwaves) {
-            const uint32_t nshot = cnt[b];
-            if (nshot == 0) continue;
-            const uint64_t co = (uint64_t)b << (kShotBits - kChunkBits);
-            resolve_chunked(psi + ((uint64_t)b << bb), bb, (uint64_t)b << bb, lane, csum + co, cinc[b] - nshot,
-                            nshot, order, rem, out);
-        }
-        return;
-    }
     const uint32_t per = bs >= 64 ? bs / 64 : 1;
     const uint32_t nl = bs >= 64 ? 64 : bs;            // lanes that own amplitudes
     for (uint32_t b = wave; b < nb; b += nwaves) {
@@ -686,7 +777,7 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
     const uint64_t nch = nb << (kShotBits - kChunkBits);
     double* csum = reinterpret_cast<double*>(take(nch * sizeof(double)));
 
-    hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, mass, csum);
+    hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, (uint64_t)nb, mass, csum);
     SV_HIP(hipGetLastError());
     scan_inclusive<double>(mass, nb, dtmp, st);
     if (a.shots == 0) return;
@@ -703,8 +794,16 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
     hipLaunchKernelGGL(k_shot_scatter, dim3(sg), dim3(kST), 0, st, blk, a.shots, (uint32_t)nb, cinc, cnt, fill, order);
     SV_HIP(hipGetLastError());
     const unsigned rg = (unsigned)std::min<uint64_t>((nb + 3) / 4, (uint64_t)device_info().cu_count * 8);
-    hipLaunchKernelGGL(k_shot_resolve, dim3(rg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, cnt, order, rem,
-                       csum, a.out);
+    if (bb >= kChunkBits) {
+        const uint64_t groups = ((uint64_t)a.shots + 7) / 8;                // waves needed at most
+        const unsigned cg = (unsigned)std::max<uint64_t>(
+            1, std::min<uint64_t>((groups + 3) / 4, (uint64_t)device_info().cu_count * 16));
+        hipLaunchKernelGGL(k_shot_resolve_chunked, dim3(cg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, order,
+                           blk, rem, csum, a.out);
+    } else {
+        hipLaunchKernelGGL(k_shot_resolve, dim3(rg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, cnt, order,
+                           rem, csum, a.out);
+    }
     SV_HIP(hipGetLastError());
 }
 
