@@ -34,8 +34,30 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kAmThreads = 256;
 constexpr int kAmWaves = kAmThreads / 64;
-constexpr int kTp = 34;            // LDS tile pitch (floats): [32 rows][34]; 2 mod 32 keeps the
-                                   // correlation's reads (16 rows x 2 columns per half-wave) on distinct banks
+// LDS tiles, one per vector and wave, 32 rows of real parts (0..15) and
+// imaginary parts (16..31) of a group's 32 columns. Column form: rows of
+// kTp = 34 floats (2 mod 32 banks), so the correlation's reads (16 rows x 2
+// columns per half-wave) and the un-apply's (one row, 32 columns) fall on
+// distinct banks. Memory-order form: rows of 32 floats with the column index
+// XOR-swizzled by the row, entry (row, col) at row * 32 + (col ^ sw(row)),
+// sw(row) = the four low row bits reversed into bits 4..1: the transposes'
+// lanes vary the lowest bits of both the row (block bits) and the column (the
+// lowest other qubits), and the reversal sends the row bits to the bank bits
+// the column bits leave free, so those accesses, too, touch 32 distinct banks
+// per half-wave (a padded pitch cannot serve every mix of row and column bits).
+constexpr int kTp = 34;
+
+template <bool COAL>
+__device__ __forceinline__ int tix(int row, int col)
+{
+    if constexpr (COAL) {
+        const int r = row & 15;
+        const int sw = ((r & 1) << 4) | ((r & 2) << 2) | (r & 4) | ((r & 8) >> 2);
+        return row * 32 + (col ^ sw);
+    } else {
+        return row * kTp + col;
+    }
+}
 
 // A wave's own LDS writes complete before its following reads (and its
 // reads before its following writes): wait for the LDS counter and keep the
@@ -64,16 +86,16 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
 {
     // the psi and lambda tiles of every wave; at the end the same memory holds
     // the waves' S parts (4 x 1024 doubles = 32 KiB <= 2 x 4 x 32 x 33 floats)
-    __shared__ float tiles[2][kAmWaves][32][kTp];
+    __shared__ float tiles[2][kAmWaves][32 * kTp];
     static_assert(sizeof(tiles) >= kAmWaves * 1024 * sizeof(double), "S parts fit the tiles");
-    float (*tp)[32][kTp] = tiles[0];
-    float (*tl)[32][kTp] = tiles[1];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);     // uniform: groups and bases are scalar
     const int h = lane >> 5, cu = lane & 31;
     const int row = blockIdx.y;
     float2* psi = am_row(a.psi, row);
     float2* lam = am_row(a.lam, row);
+    float* tpw = tiles[0][w];
+    float* tlw = tiles[1][w];
     float fr[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) fr[s] = a.frag[(size_t)row * a.frag_stride + lane * 16 + s];
@@ -100,8 +122,8 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const int kk = 4 * st + (lane >> 4), ii = lane & 15;
-            const double a0 = tp[w][ii][kk], a1 = tp[w][16 + ii][kk];
-            const double b0 = tl[w][ii][kk], b1 = tl[w][16 + ii][kk];
+            const double a0 = tpw[tix<COAL>(ii, kk)], a1 = tpw[tix<COAL>(16 + ii, kk)];
+            const double b0 = tlw[tix<COAL>(ii, kk)], b1 = tlw[tix<COAL>(16 + ii, kk)];
             s00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, s00, 0, 0, 0);
             s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
             s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0 + a1, b0 - b1, s10, 0, 0, 0);
@@ -141,19 +163,17 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
                 cm ^= low;
             }
             mo[k] = x;
-            ti[k] = j * kTp + c;
+            ti[k] = tix<COAL>(j, c);
         }
-        float* tpw = &tp[w][0][0];
-        float* tlw = &tl[w][0][0];
         for (; grp < groups; grp += stride) {
             const uint64_t base = column(grp, 0);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const float2 v = psi[base | mo[k]], e = lam[base | mo[k]];
                 tpw[ti[k]] = v.x;
-                tpw[ti[k] + 16 * kTp] = v.y;
+                tpw[ti[k] + 16 * 32] = v.y;
                 tlw[ti[k]] = e.x;
-                tlw[ti[k] + 16 * kTp] = e.y;
+                tlw[ti[k] + 16 * 32] = e.y;
             }
             wave_lds_sync();
             correlate();
@@ -163,28 +183,28 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             f32x16 y = {0};
 #pragma unroll
             for (int s = 0; s < 16; ++s)
-                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tp[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tpw[tix<COAL>(16 * (s & 1) + 8 * h + (s >> 1), cu)], y, 0, 0,
                                                          0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                tp[w][8 * h + t][cu] = y[2 * t];
-                tp[w][16 + 8 * h + t][cu] = y[2 * t + 1];
+                tpw[tix<COAL>(8 * h + t, cu)] = y[2 * t];
+                tpw[tix<COAL>(16 + 8 * h + t, cu)] = y[2 * t + 1];
             }
             y = f32x16{0};
 #pragma unroll
             for (int s = 0; s < 16; ++s)
-                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tl[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tlw[tix<COAL>(16 * (s & 1) + 8 * h + (s >> 1), cu)], y, 0, 0,
                                                          0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                tl[w][8 * h + t][cu] = y[2 * t];
-                tl[w][16 + 8 * h + t][cu] = y[2 * t + 1];
+                tlw[tix<COAL>(8 * h + t, cu)] = y[2 * t];
+                tlw[tix<COAL>(16 + 8 * h + t, cu)] = y[2 * t + 1];
             }
             wave_lds_sync();
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                psi[base | mo[k]] = make_float2(tpw[ti[k]], tpw[ti[k] + 16 * kTp]);
-                lam[base | mo[k]] = make_float2(tlw[ti[k]], tlw[ti[k] + 16 * kTp]);
+                psi[base | mo[k]] = make_float2(tpw[ti[k]], tpw[ti[k] + 16 * 32]);
+                lam[base | mo[k]] = make_float2(tlw[ti[k]], tlw[ti[k] + 16 * 32]);
             }
             wave_lds_sync();
         }
@@ -217,10 +237,10 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             // real, row 16 + 8h + t imaginary), tile column = column of the group
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                tp[w][8 * h + t][cu] = x[t].x;
-                tp[w][16 + 8 * h + t][cu] = x[t].y;
-                tl[w][8 * h + t][cu] = l[t].x;
-                tl[w][16 + 8 * h + t][cu] = l[t].y;
+                tpw[tix<COAL>(8 * h + t, cu)] = x[t].x;
+                tpw[tix<COAL>(16 + 8 * h + t, cu)] = x[t].y;
+                tlw[tix<COAL>(8 * h + t, cu)] = l[t].x;
+                tlw[tix<COAL>(16 + 8 * h + t, cu)] = l[t].y;
             }
             const uint64_t gn = grp + stride;
             if (gn < groups) {
@@ -242,14 +262,14 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
             f32x16 y = {0};
 #pragma unroll
             for (int s = 0; s < 16; ++s)
-                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tp[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tpw[tix<COAL>(16 * (s & 1) + 8 * h + (s >> 1), cu)], y, 0, 0,
                                                          0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) pb[toff(t) + lh] = make_float2(y[2 * t], y[2 * t + 1]);
             y = f32x16{0};
 #pragma unroll
             for (int s = 0; s < 16; ++s)
-                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tl[w][16 * (s & 1) + 8 * h + (s >> 1)][cu], y, 0, 0,
+                y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tlw[tix<COAL>(16 * (s & 1) + 8 * h + (s >> 1), cu)], y, 0, 0,
                                                          0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) lb[toff(t) + lh] = make_float2(y[2 * t], y[2 * t + 1]);
@@ -261,7 +281,7 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma(AdjMfmaLaunch a)
     // output register r of lane l is row 4r + l / 16, column l % 16 of a
     // 16 x 16 part
     __syncthreads();       // every wave is done with its tiles
-    double* red = reinterpret_cast<double*>(&tiles[0][0][0][0]);    // [kAmWaves][1024]
+    double* red = reinterpret_cast<double*>(&tiles[0][0][0]);    // [kAmWaves][1024]
     const int col = lane & 15;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
