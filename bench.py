@@ -10,12 +10,18 @@ one FP64 reduction sweep. Inputs are seeded and synthetic.
 
 Printed: ONE JSON line with whole-job gates/s, the roofline of the dominant
 kernel (the dense one-qubit sweep, timed live with HIP events on the state's
-stream over the timed region), the fused-MFMA / adjoint / batched forms as
-speedups over the plain form on the same GPU, and the CPU oracle timed on a
-bounded sample of the same workload.
+stream over the timed region) against 8 TB/s and against the copy ceiling
+measured in the same run, the error of every reported result against the
+complex128 oracle's stored values (tests/golden), the fused-MFMA / adjoint /
+batched forms as speedups over the plain form on the same GPU (parameter
+shift measured on 16 parameters and scaled), and the CPU oracle timed on
+bounded samples of this and the other workloads.
 
---pmc-probe runs a short fixed sequence (dense gates, then a plain copy of
-known size) for hardware byte counters under rocprofv3 --pmc.
+Probes for rocprofv3 (short fixed sequences): --pmc-probe (dense gates,
+fused blocks of every form, a plain copy of known size), --adjoint-probe
+(forward + matrix-core backward at --n qubits, then a copy), --shots-probe,
+--batch-probe. --summarize turns rocprofv3 CSV output into the summaries
+under profiles/ (no GPU needed).
 """
 
 from __future__ import annotations
@@ -42,10 +48,18 @@ def parse():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the fused/adjoint/batched comparisons")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-oracle-timings", action="store_true",
+                    help="skip the oracle timings of the other workloads (about 40 s of host work)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="print a profile summary from rocprofv3 CSV output and exit (no GPU): "
+                         "stats DIR | traffic FETCH_DIR WRITE_DIR KERNEL_REGEX COPY_BYTES [ALG_BYTES] | "
+                         "counters DIR [KERNEL_REGEX]")
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--shots-probe", action="store_true",
                     help="the shot-sampling part of the bench alone (n-qubit brickwork output state), for profiles")
+    ap.add_argument("--batch-probe", action="store_true", help="three launches of the batching workload per "
+                    "configuration (default, BF16x3 phases), for counters")
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="one forward + matrix-core adjoint backward of the n-qubit RX/RY ring, for counters")
     return ap.parse_args()
@@ -79,12 +93,61 @@ def read_traffic(n: int):
         return None
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden(name: str):
+    """Stored oracle values (complex128, written by oracle/make_goldens.py)."""
+    path = os.path.join(GOLDEN_DIR, name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def error_vs_golden_z(name: str, n: int, z):
+    """Largest |<Z_i> - oracle|, |<sum Z> - oracle| and |norm^2 - oracle|."""
+    import numpy as np
+
+    g = golden(name)
+    if g is None or z is None or g.get("n") != n:
+        return None
+    want = np.array(g["expval_z"])
+    return {"oracle": f"tests/golden/{name}.json (complex128)",
+            "max_abs_z_i": float(np.max(np.abs(np.asarray(z[:n]) - want))),
+            "abs_sum_z": abs(float(np.sum(z[:n])) - g["sum_z"]),
+            "abs_norm2": abs(float(z[n]) - g["norm2"])}
+
+
+def copy_ceiling(st, stream) -> float:
+    """GB/s of a plain copy of the state (read 8 * 2^n bytes, write the same),
+    best of three launches, measured with events on the state's stream."""
+    import torch
+
+    from paper_2511_19291_amd import sv
+
+    dst = torch.empty_like(st.tensor)
+    nbytes = st.tensor.numel() * 8
+
+    def one():
+        sv.check(sv.lib().sv_stream_copy(dst.data_ptr(), st.tensor.data_ptr(), nbytes, stream.cuda_stream))
+
+    one()
+    ms = min(_timed_ms(one, stream) for _ in range(3))
+    del dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the state is not "
               "sharded across GPUs", file=sys.stderr)
         return 2
+
+    if args.summarize:
+        return summarize(args.summarize)
 
     import numpy as np
     import torch
@@ -100,6 +163,8 @@ def main() -> int:
         return run_pmc_probe(n)
     if args.adjoint_probe:
         return run_adjoint_probe(n)
+    if args.batch_probe:
+        return run_batch_probe()
     if args.shots_probe:
         circ = C.brickwork_u3_cz(n, 20, 2)
         st = sv.State(n)
@@ -116,6 +181,7 @@ def main() -> int:
     n_gates = len(circ.ops)
 
     st = sv.State(n)
+    last_z = [None]
 
     def step(events=None):
         st.reset()
@@ -135,6 +201,7 @@ def main() -> int:
                 st.run_ops(table, i, j - i, params)
                 i = j
         z = st.expval_z_all()[0]
+        last_z[0] = z
         return float(np.sum(z[:n]))
 
     print(f"# warmup {args.warmup} step(s) of {circ.name} ({n_gates} gates)", file=sys.stderr, flush=True)
@@ -162,9 +229,20 @@ def main() -> int:
     alg_bytes = 16.0 * (1 << n)          # read + write every amplitude, complex64
     achieved = alg_bytes / (avg_dense_ms / 1e3) / 1e9
     traffic = read_traffic(n)
-    # algorithmic bytes of the whole step (one sweep per gate + the reduction)
+    # the measured ceiling: a plain copy of the state (8 * 2^n bytes read, the same written)
+    copy_GBps = copy_ceiling(st, stream)
+    # algorithmic bytes of the whole step: one sweep per gate (CZ by the
+    # 128-byte line rule: both qubits >= 4 -> 4 B/amplitude, one below 4 ->
+    # 8, both below 4 -> 16), the reset (8) and the reduction (8)
     counts = circ.counts()
-    step_bytes = (counts.get("u3", 0) * 16 + counts.get("cz", 0) * 4 + 8 + 8) * (1 << n)
+    cz_bytes = 0
+    for op in circ.ops:
+        if op.kind == "z" and op.controls:
+            lo = min(op.targets[0], op.controls[0])
+            hi = max(op.targets[0], op.controls[0])
+            cz_bytes += 16 if hi < 4 else (8 if lo < 4 else 4)
+    step_bytes = (counts.get("u3", 0) * 16 + cz_bytes + 8 + 8) * (1 << n)
+    err = error_vs_golden_z("brickwork30", n, last_z[0]) if n == 30 else None
     out = {
         "metric": METRIC,
         "value": round(gates_per_s, 3),
@@ -187,7 +265,10 @@ def main() -> int:
             "state_bytes": 8 * (1 << n),
         },
         "hbm_GBps_step": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "hbm_frac_of_copy_step": round(step_bytes / (ms_per_step / 1e3) / 1e9 / copy_GBps, 4),
+        "copy_GBps": round(copy_GBps, 1),
         "sum_z": sumz,
+        "error_vs_oracle": err,
         "wall_s_timed": round(wall, 3),
         "roofline": {
             "bound": "hbm",
@@ -196,6 +277,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(achieved / copy_GBps, 4),
+            "copy_GBps": round(copy_GBps, 1),
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(avg_dense_ms, 4),
@@ -207,10 +290,12 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     if not args.no_extras:
-        out.update(extras(args, n, gates_per_s, avg_dense_ms))
+        out.update(extras(args, n, gates_per_s, avg_dense_ms, copy_GBps))
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, args.cpu_seconds)
+        if not args.no_oracle_timings:
+            out["oracle_timings"] = oracle_timings()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -228,7 +313,7 @@ def _timed_ms(fn, stream) -> float:
     return e0.elapsed_time(e1)
 
 
-def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
+def extras(args, n, plain_gates_per_s, avg_dense_ms, copy_GBps) -> dict:
     """Fused-MFMA, adjoint and batched forms against the plain form, each on
     its own workload, all on this GPU."""
     import numpy as np
@@ -263,6 +348,7 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         "GBps": [round(x, 1) for x in per_t],
         "min_GBps": round(srt[0], 1), "median_GBps": round(srt[len(srt) // 2], 1),
         "min_frac_of_8TBps": round(srt[0] / 8000.0, 3), "median_frac_of_8TBps": round(srt[len(srt) // 2] / 8000.0, 3),
+        "min_frac_of_copy": round(srt[0] / copy_GBps, 3), "median_frac_of_copy": round(srt[len(srt) // 2] / copy_GBps, 3),
         "argmin_target": int(np.argmin(per_t)),
     }
 
@@ -275,15 +361,20 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         plan_ms = (time.perf_counter() - t0) * 1e3
         st = sv.State(nq)
         entry = {"gates": len(circ.ops), "blocks": len(blocks), "plan_ms": round(plan_ms, 2)}
+        zs = {}
         for mode, name in ((sv.FUSED_FP32_MFMA, "fp32_mfma"), (sv.FUSED_BF16X3, "bf16x3")):
             st.reset()
             st.apply_fused(blocks[:2], mode)
             ms = _timed_ms(lambda: (st.reset(), st.apply_fused(blocks, mode)), stream)
             per_block = ms / len(blocks)
+            gbps = 16 * (1 << nq) / (per_block / 1e3) / 1e9
             entry[name] = {"ms": round(ms, 2), "gates_per_s": round(len(circ.ops) / (ms / 1e3), 1),
                            "ms_per_block": round(per_block, 4),
-                           "GBps_per_block": round(16 * (1 << nq) / (per_block / 1e3) / 1e9, 1),
+                           "GBps_per_block": round(gbps, 1), "frac_of_copy_per_block": round(gbps / copy_GBps, 3),
                            "TFLOPs_per_block": round(8 * 32 * (1 << nq) / (per_block / 1e3) / 1e12, 2)}
+            zs[name] = st.expval_z_all()[0]          # the state holds this mode's output
+            if nq == 30:
+                entry[name]["error_vs_oracle"] = error_vs_golden_z("brickwork30", nq, zs[name])
         # six-qubit blocks off qubits 0..5 (BF16x3 only), five-qubit blocks elsewhere
         blocks6 = sv.fuse_plan(circ, 6)
         st.reset()
@@ -292,11 +383,18 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         entry["bf16x3_k6"] = {"blocks": len(blocks6), "six_qubit_blocks": sum(len(t) == 6 for t, _ in blocks6),
                               "ms": round(ms6, 2), "gates_per_s": round(len(circ.ops) / (ms6 / 1e3), 1),
                               "ms_per_block": round(ms6 / len(blocks6), 4)}
+        zs["bf16x3_k6"] = st.expval_z_all()[0]
+        if nq == 30:
+            entry["bf16x3_k6"]["error_vs_oracle"] = error_vs_golden_z("brickwork30", nq, zs["bf16x3_k6"])
         if with_plain:
             table = sv.OpTable(circ.ops)
             p = np.ascontiguousarray(circ.params)
             ms = _timed_ms(lambda: (st.reset(), st.run_ops(table, 0, len(circ.ops), p)), stream)
             entry["plain_ms"] = round(ms, 2)
+            zp = st.expval_z_all()[0]
+            # no oracle state at 32 qubits (32 GiB of complex64, 64 GiB in complex128): against the plain sweeps
+            for name in ("fp32_mfma", "bf16x3", "bf16x3_k6"):
+                entry[name]["max_abs_z_i_vs_plain"] = float(np.max(np.abs(zs[name][:nq] - zp[:nq])))
         else:
             entry["plain_ms"] = round(len(circ.ops) / plain_gates_per_s * 1e3, 2)
         for name in ("fp32_mfma", "bf16x3", "bf16x3_k6"):
@@ -348,6 +446,8 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         t0 = time.perf_counter()
         loss_b, grad_b, drift_b = st.adjoint_grad(circ, terms, block_qubits=lb)
         ms_b = (time.perf_counter() - t0) * 1e3
+        if lb == sv.ADJOINT_MFMA:
+            grad_mfma = grad_b[0].copy()
         blocked["mfma4" if lb == sv.ADJOINT_MFMA else f"block{lb}"] = {"backward_ms": round(ms_b, 2), "backward_over_forward": round(ms_b / fwd_ms, 3),
                                  "max_grad_diff_vs_per_gate": float(np.max(np.abs(grad_b[0] - grad[0]))),
                                  "drift": float(drift_b[0])}
@@ -355,7 +455,31 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
     # matrix-core blocks (host planning included in the time)
     fwd_fused_ms = min(_timed_ms(lambda: (st.reset(), st.run_fused(circ)), stream) for _ in range(2))
     n_par = circ.n_params
-    shift_ms = 2 * n_par * fwd_ms
+    # parameter shift measured on the GPU for 16 seeded parameters (two
+    # forwards and one <Z> reduction each), scaled to all parameters; once
+    # with plain sweeps, once with the fused forward
+    which = np.random.default_rng(28).choice(n_par, size=16, replace=False)
+    shift = {}
+    for fwd in ("plain", "fused"):
+        vals = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in which:
+            pair = []
+            for sgn in (1.0, -1.0):
+                prm = circ.params.copy()
+                prm[q] += sgn * np.pi / 2
+                st.reset()
+                if fwd == "plain":
+                    st.run_ops(table, 0, len(circ.ops), np.ascontiguousarray(prm))
+                else:
+                    st.run_fused(circ, prm)
+                pair.append(float(np.sum(st.expval_z_all()[0][:28])))
+            vals.append(0.5 * (pair[0] - pair[1]))
+        ms16 = (time.perf_counter() - t0) * 1e3
+        shift[fwd] = {"ms_16_params": round(ms16, 1), "ms_scaled_to_all": round(ms16 / 16 * n_par, 1),
+                      "max_abs_vs_adjoint": float(np.max(np.abs(np.array(vals) - grad[0][which])))}
+    shift_ms = shift["fused"]["ms_scaled_to_all"]
     # the autograd layers' default backward at this width: matrix-core blocks
     default_ms = blocked["mfma4"]["backward_ms"]
     res["adjoint"] = {
@@ -366,11 +490,28 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         "backward_kind": "matrix-core blocks of 4 qubits (the autograd default from 13 qubits)",
         "backward_over_forward": round(default_ms / fwd_ms, 3),
         "backward_per_gate_ms": round(bwd_ms, 2), "per_gate_over_forward": round(bwd_ms / fwd_ms, 3),
-        "param_shift_ms_est": round(shift_ms, 1),
+        "param_shift": {"measured": "16 seeded parameters on this GPU, two forwards + <sum Z> each, "
+                                    "scaled to all parameters", "plain_forward": shift["plain"],
+                        "fused_forward": shift["fused"]},
         "speedup_vs_param_shift": round(shift_ms / default_ms, 1),
+        "speedup_basis": "parameter shift with the fused forward (scaled from 16 parameters) / matrix-core backward",
+        # gate-equivalent bytes of the per-gate adjoint (32 B/amplitude per
+        # rotation, 16 per CNOT) over the matrix-core backward's time: an
+        # effective rate, not an HBM fraction
+        "backward_effective_GBps": round(sum(16 if op.controls else 32 for op in circ.ops) * (1 << 28)
+                                         / (default_ms / 1e3) / 1e9, 1),
         "loss": float(loss[0]), "grad_norm": float(np.linalg.norm(grad[0])), "drift": float(drift[0]),
         "blocked": blocked,
     }
+    g28 = golden("ring28")
+    if g28 is not None:
+        want = np.array(g28["grad"])
+        res["adjoint"]["error_vs_oracle"] = {
+            "oracle": "tests/golden/ring28.json (complex128 adjoint)",
+            "loss_abs": abs(float(loss[0]) - g28["loss"]),
+            "per_gate_rel_max": float(np.max(np.abs(grad[0] - want)) / np.max(np.abs(want))),
+            "mfma4_rel_max": float(np.max(np.abs(grad_mfma - want)) / np.max(np.abs(want))),
+        }
     st.free()
     del st
     torch.cuda.empty_cache()
@@ -468,6 +609,12 @@ def extras(args, n, plain_gates_per_s, avg_dense_ms) -> dict:
         "autotune": {"chosen": info["config"], "grid": info["grid"], "tasks": info["n_tasks"],
                      "passes": info["n_passes"], "configs_tried": len(trials), "tune_s": round(tune_s, 2)},
     }
+    gb = golden("batch256")
+    if gb is not None and gb["n_qubits"] == [c.n for c in circs]:
+        def zerr(o):
+            return float(max(np.max(np.abs(o[i, : c.n] - np.array(gb["expval_z"][i]))) for i, c in enumerate(circs)))
+        res["batched"]["error_vs_oracle"] = {"oracle": "tests/golden/batch256.json (complex128)",
+                                             **{f"max_abs_z_i_{k}": zerr(outs[k]) for k in outs}}
     print("# batched done", file=sys.stderr, flush=True)
     return res
 
@@ -504,6 +651,7 @@ def shots_extra(st, circ, blocks, stream) -> dict:
         "exact_ms": round(exact_ms, 3), "exact_shots_per_s": round(nshots / (exact_ms / 1e3), 1),
         # the mass sweep reads every amplitude once; each draw reads its chunk of 128
         "exact_alg_GBps": round((8 * (1 << n) + 1024 * nshots) / (exact_ms / 1e3) / 1e9, 1),
+        "exact_frac_of_8TBps": round((8 * (1 << n) + 1024 * nshots) / (exact_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 3),
         "gaussian_ms": round(gauss_ms, 3),
         "gaussian_alg_GBps": round(40 * (1 << n) / (gauss_ms / 1e3) / 1e9, 1),
         "gaussian_sum_minus_shots": ysum - 1e9,
@@ -552,6 +700,211 @@ def cpu_baseline(circ, seconds: float) -> dict:
         "sample": f"first {done} gates of the {n}-qubit workload on a complex128 state "
                   f"({dt:.1f} s; state init {t_init:.1f} s not counted)",
     }
+
+
+_C1_ONE_CORE = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_2511_19291_amd import circuits as C
+c = C.WORKLOADS["hea12"]()
+ts = []
+for _ in range(3):
+    t0 = time.perf_counter()
+    oracle.expval_z_all(oracle.run(c), 12)
+    ts.append(time.perf_counter() - t0)
+print(sorted(ts)[1] * 1e3)
+"""
+
+
+def oracle_timings(budget_s: float = 6.0) -> dict:
+    """The CPU oracle, as it is, on the other workloads, each on a bounded
+    sample (the entry says what it covers) so the whole takes well under a
+    minute: C1 (12-qubit ansatz, full state and <Z>) on all cores and on one
+    (a child process with OMP_NUM_THREADS=1; nothing there touches the GPU),
+    the 24-qubit fusion instance gate by gate, the batching workload circuit
+    by circuit, the 14-qubit differentiation copy's parameter-shift and
+    central-difference gradients (all 280 parameters), and the 28-qubit
+    forward."""
+    import subprocess
+
+    import numpy as np
+
+    import oracle
+    from paper_2511_19291_amd import circuits as C
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    out = {"kind": "oracle", "cores": threads, "cpu_model": _cpu_model()}
+
+    c1 = C.WORKLOADS["hea12"]()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.expval_z_all(oracle.run(c1), 12)
+        ts.append(time.perf_counter() - t0)
+    one = None
+    try:
+        r = subprocess.run([sys.executable, "-c", _C1_ONE_CORE.format(root=ROOT)], capture_output=True, text=True,
+                           timeout=120, env={**os.environ, "OMP_NUM_THREADS": "1"})
+        one = float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        one = None
+    out["c1_hea12"] = {"gates": len(c1.ops), "ms_all_cores": round(sorted(ts)[1] * 1e3, 3),
+                       "ms_one_core": None if one is None else round(one, 3),
+                       "sample": "whole circuit and <Z_i>, median of 3"}
+
+    def gates_sample(circ, label):
+        psi = oracle.basis_state(circ.n, 0)
+        done = 0
+        t0 = time.perf_counter()
+        while done < len(circ.ops) and (done < 3 or time.perf_counter() - t0 < budget_s):
+            oracle.apply_op(psi, circ.n, circ.ops[done], circ.params)
+            done += 1
+        dt = time.perf_counter() - t0
+        del psi
+        return {"gates_per_s": round(done / dt, 3), "gates_done": done, "gates": len(circ.ops),
+                "s_whole_circuit_est": round(len(circ.ops) * dt / done, 1),
+                "sample": f"first {done} of {len(circ.ops)} gates of {label} ({dt:.1f} s)"}
+
+    out["c3_fused24"] = gates_sample(C.WORKLOADS["fused24"](), "the 24-qubit fusion instance")
+    circs = C.batch_workload(256, 10, 20, 6, 4)
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(circs) and (done < 1 or time.perf_counter() - t0 < 2.5 * budget_s):
+        c = circs[done]
+        oracle.expval_z_all(oracle.run(c), c.n)
+        done += 1
+    dt = time.perf_counter() - t0
+    out["c4_batch256"] = {"circuits_done": done, "s": round(dt, 2),
+                          "s_all_256_est": round(dt if done == len(circs) else
+                                                 dt * sum(len(c.ops) << c.n for c in circs) /
+                                                 sum(len(c.ops) << c.n for c in circs[:done]), 1),
+                          "sample": f"the first {done} of 256 circuits in order, whole state and <Z_i> each "
+                                    "(the estimate scales by gates x 2^n)"}
+    c14 = C.WORKLOADS["ring14"]()
+    terms = C.z_sum_terms(14)
+    t0 = time.perf_counter()
+    g_shift = oracle.grad_param_shift(c14, terms)
+    t_shift = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g_fd = oracle.grad_finite_diff(c14, terms)
+    t_fd = time.perf_counter() - t0
+    out["c5_ring14"] = {"params": c14.n_params, "param_shift_s": round(t_shift, 2), "finite_diff_s": round(t_fd, 2),
+                        "max_abs_shift_minus_fd": float(np.max(np.abs(g_shift - g_fd))),
+                        "sample": "every parameter, both rules"}
+    out["c5_ring28_forward"] = gates_sample(C.WORKLOADS["ring28"](), "the 28-qubit differentiation forward")
+    return out
+
+
+def _csvs(d: str, suffix: str):
+    import glob
+
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    import csv
+
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, regex=None):
+    """{(kernel, dispatch): {counter: value summed over dimensions}, duration ms}"""
+    import re
+
+    vals, dur = {}, {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        if regex and not re.search(regex, name):
+            continue
+        key = (name, int(r["Dispatch_Id"]))
+        vals.setdefault(key, {})
+        vals[key][r["Counter_Name"]] = vals[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        dur[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    return vals, dur
+
+
+def summarize(argv) -> int:
+    """Profile summaries from rocprofv3 CSV output (no GPU needed):
+      stats DIR                       kernel statistics (--kernel-trace --stats)
+      traffic FETCH_DIR WRITE_DIR RE COPY_BYTES [ALG_BYTES]
+                                      FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernels
+                                      matching RE, scaled by COPY_BYTES / what the same counter reads
+                                      for the plain copy kernel k_copy of the same run
+      counters DIR [RE]               per kernel: median duration and counters; with
+                                      GRBM_GUI_ACTIVE the clock (busy cycles / 8 XCDs / duration) and,
+                                      with SQ_VALU_MFMA_BUSY_CYCLES, the matrix cores' busy share"""
+    import statistics
+
+    kind = argv[0]
+    if kind == "stats":
+        rows = _csvs(argv[1], "kernel_stats.csv")
+        print("rocprofv3 kernel statistics (durations in microseconds):\n")
+        print(" calls     avg_us     min_us     max_us   total_ms    pct  kernel")
+        for r in rows:
+            print(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} {float(r['MinNs']) / 1e3:10.1f} "
+                  f"{float(r['MaxNs']) / 1e3:10.1f} {float(r['TotalDurationNs']) / 1e6:10.2f} "
+                  f"{float(r['Percentage']):6.2f}  {r['Name'][:140]}")
+        return 0
+    if kind == "traffic":
+        import re
+
+        fetch_dir, write_dir, regex, copy_bytes = argv[1], argv[2], argv[3], float(argv[4])
+        alg = float(argv[5]) if len(argv) > 5 else None
+        got = {}
+        for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+            vals, _ = _per_dispatch(_csvs(d, "counter_collection.csv"))
+            copy = [v[ctr] for (k, _), v in vals.items() if "k_copy" in k and ctr in v]
+            kern = [v[ctr] for (k, _), v in vals.items() if re.search(regex, k) and ctr in v]
+            if not copy or not kern:
+                raise SystemExit(f"{ctr}: no k_copy or no dispatch matching {regex!r} in {d}")
+            got[ctr] = (statistics.mean(copy), statistics.mean(kern), len(kern))
+        fscale = copy_bytes / (got["FETCH_SIZE"][0] * 1024)
+        wscale = copy_bytes / (got["WRITE_SIZE"][0] * 1024)
+        rd = got["FETCH_SIZE"][1] * 1024 * fscale
+        wr = got["WRITE_SIZE"][1] * 1024 * wscale
+        print("FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by known copy bytes / what the same")
+        print("counter reads for the copy kernel (k_copy) of the same run.\n")
+        print(f"copy bytes each way: {copy_bytes:.0f}")
+        print(f"copy FETCH_SIZE KiB: {got['FETCH_SIZE'][0]:.1f}")
+        print(f"copy WRITE_SIZE KiB: {got['WRITE_SIZE'][0]:.1f}")
+        print(f"fetch_scale: {fscale:.4f}")
+        print(f"write_scale: {wscale:.4f}")
+        print(f"kernel dispatches (fetch run, write run): {got['FETCH_SIZE'][2]}, {got['WRITE_SIZE'][2]}")
+        print(f"kernel FETCH_SIZE KiB (mean): {got['FETCH_SIZE'][1]:.1f}")
+        print(f"kernel WRITE_SIZE KiB (mean): {got['WRITE_SIZE'][1]:.1f}")
+        print(f"read_bytes_per_launch: {rd:.0f}")
+        print(f"write_bytes_per_launch: {wr:.0f}")
+        print(f"traffic_bytes_per_launch: {rd + wr:.0f}")
+        if alg:
+            print(f"alg_bytes_per_launch: {alg:.0f}")
+            print(f"traffic_over_alg: {(rd + wr) / alg:.4f}")
+        return 0
+    if kind == "counters":
+        regex = argv[2] if len(argv) > 2 else None
+        vals, dur = _per_dispatch(_csvs(argv[1], "counter_collection.csv"), regex)
+        by = {}
+        for key, v in vals.items():
+            by.setdefault(key[0], []).append((dur[key], v))
+        for name, lst in by.items():
+            med = lambda xs: sorted(xs)[len(xs) // 2]
+            ms = med([x[0] for x in lst])
+            ctrs = sorted({c for _, v in lst for c in v})
+            print(f"{name[:120]}")
+            print(f"  dispatches {len(lst)}, median duration {ms:.4f} ms")
+            for c in ctrs:
+                print(f"  {c:28s} median {med([v.get(c, 0.0) for _, v in lst]):.4e}")
+            if "GRBM_GUI_ACTIVE" in ctrs:
+                g = med([v["GRBM_GUI_ACTIVE"] for _, v in lst])
+                print(f"  clock GHz (GRBM_GUI_ACTIVE / 8 XCDs / duration): {g / 8 / (ms * 1e6):.2f}")
+                if "SQ_VALU_MFMA_BUSY_CYCLES" in ctrs:
+                    mb = med([v["SQ_VALU_MFMA_BUSY_CYCLES"] for _, v in lst])
+                    print(f"  MFMA busy share at that clock (busy / (1024 SIMDs x cycles)): {mb / (1024 * g / 8):.3f}")
+        return 0
+    raise SystemExit(f"unknown summary kind {kind!r}")
 
 
 def run_pmc_probe(n: int) -> int:
@@ -609,7 +962,34 @@ def run_adjoint_probe(n: int) -> int:
     st = sv.State(n).reset().run(circ)
     loss, grad, drift = st.adjoint_grad(circ, C.z_sum_terms(n), block_qubits=sv.ADJOINT_MFMA)
     torch.cuda.synchronize()
-    print(json.dumps({"adjoint_probe": True, "n": n, "loss": float(loss[0]), "drift": float(drift[0])}), flush=True)
+    # one plain copy of the state (8 * 2^n bytes each way) to scale byte counters
+    dst = torch.empty_like(st.tensor)
+    sv.check(sv.lib().sv_stream_copy(dst.data_ptr(), st.tensor.data_ptr(), 8 * (1 << n),
+                                     torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    print(json.dumps({"adjoint_probe": True, "n": n, "loss": float(loss[0]), "drift": float(drift[0]),
+                      "copy_bytes": 8 * (1 << n)}), flush=True)
+    return 0
+
+
+def run_batch_probe() -> int:
+    """The batching workload (256 circuits of 10..20 qubits) in the default
+    configuration and with BF16x3 phases, three graph launches each."""
+    import torch
+
+    from paper_2511_19291_amd import circuits as C
+    from paper_2511_19291_amd import sv
+
+    circs = C.batch_workload(256, 10, 20, 6, 4)
+    for cfg in (None, {"phase_mode": 2}):
+        plan = sv.BatchPlan(circs, config=cfg)
+        dp = plan.pack()
+        out = plan.out_buffer()
+        for _ in range(3):
+            plan.launch(dp, out)
+        torch.cuda.synchronize()
+        print(json.dumps({"batch_probe": True, "config": plan.info()["config"], "stats": plan.stats()}), flush=True)
+        plan.free()
     return 0
 
 

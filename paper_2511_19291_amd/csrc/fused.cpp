@@ -474,21 +474,6 @@ sv_status apply_fused_impl(sv_state s, const sv_block* blocks, int n_blocks, int
                             L[q] = A[q] - hi;
                             A[q] = hi;
                         }
-                    } else {
-                        // the three-real-product operands of the wide form, formed
-                        // in double: Mr, -(Mr + Mi), Mi - Mr, each [32][32]
-                        float* G = A + 64 * 64;
-                        for (int r = 0; r < 32; ++r)
-                            for (int c = 0; c < 32; ++c) {
-                                cd v = 0.0;
-                                if ((r & ((1 << pad) - 1)) == (c & ((1 << pad) - 1))) {
-                                    const double* e = bm + 2 * ((size_t)(r >> pad) * D + (c >> pad));
-                                    v = cd(e[0], e[1]);
-                                }
-                                G[r * 32 + c] = (float)v.real();
-                                G[32 * 32 + r * 32 + c] = (float)(-(v.real() + v.imag()));
-                                G[2 * 32 * 32 + r * 32 + c] = (float)(v.imag() - v.real());
-                            }
                     }
                 }
             } else {

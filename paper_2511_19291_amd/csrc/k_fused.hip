@@ -13,15 +13,11 @@
 // owns one tile at a time:
 //   1. coalesced float4 loads in memory order -> LDS, split into real and
 //      imaginary planes;
-//   2. complex product on MFMA:
-//      FP32: three real products (Gauss) on v_mfma_f32_32x32x2_f32,
-//      K = Mr (Xr + Xi), Yr = K + G2 Xi, Yi = K + G3 Xr with G2 = -(Mr + Mi),
-//      G3 = Mi - Mr formed in double on the host (3 x 16 k-steps instead of
-//      the 4 x 16 of the real 64 x 64 embedding);
-//      BF16X3: the real 64 x 64 product [Yr; Yi] = [[Mr, -Mi], [Mi, Mr]]
-//      [Xr; Xi] with x = x_hi + x_lo, both parts rounded to BF16 (RNE),
-//      products hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16, FP32
-//      accumulation;
+//   2. complex product on MFMA as a real 64 x 64 product
+//      [Yr; Yi] = [[Mr, -Mi], [Mi, Mr]] [Xr; Xi]:
+//      FP32: v_mfma_f32_32x32x2_f32, 2 x 32 k-steps;
+//      BF16X3: x = x_hi + x_lo with both parts rounded to BF16 (RNE), products
+//      hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16, FP32 accumulation;
 //      the left operand (the block matrix) stays in registers for the whole
 //      sweep;
 //   3. results -> LDS -> coalesced float4 stores in memory order.
@@ -101,18 +97,14 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
     }
     const int r0 = a.bit_row[0], c0 = a.bit_col[0];   // bit 0 of L (the second amplitude of a float4)
 
-    // left operand fragments, loaded once. FP32: the three-real-product
-    // (Gauss) operands G1 = Mr, G2 = -(Mr + Mi), G3 = Mi - Mr.
-    float g1[16], g2[16], g3[16];
+    // left operand fragments, loaded once
+    float afr[2][32];
     bf16x8 ahi[2][4], alo[2][4];
     if constexpr (MODE == 0) {
-        const float* G = am + 64 * 64;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            g1[s] = G[c32 * 32 + 2 * s + h];
-            g2[s] = G[32 * 32 + c32 * 32 + 2 * s + h];
-            g3[s] = G[2 * 32 * 32 + c32 * 32 + 2 * s + h];
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -131,26 +123,16 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
 
     const uint64_t waves_total = (uint64_t)gridDim.x * kWaves;
     const uint64_t iters = (a.n_tiles + waves_total - 1) / waves_total;
-    const uint64_t first = (uint64_t)blockIdx.x * kWaves + wave;
-    // FP32: the first tile's loads; each later tile's loads are issued as
-    // soon as the previous tile sits in LDS, so they overlap its products and
-    // stores (measured 2 % faster). BF16X3 loads each tile at its turn
-    // (measured 4 % slower with the early loads).
-    float4 v[8];
-    if (MODE == 0 && first < a.n_tiles) {
-        const uint64_t base = insert_zeros(first, a.pos, 10);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = ld4(psi + base + lane_off + i_off[i]);
-    }
     for (uint64_t it = 0; it < iters; ++it) {
-        const uint64_t tile = it * waves_total + first;
+        const uint64_t tile = it * waves_total + (uint64_t)blockIdx.x * kWaves + wave;
         const bool live = tile < a.n_tiles;
         const uint64_t base = insert_zeros(live ? tile : 0, a.pos, 10);
-        if (MODE == 1 && live) {
+        // 1. load the tile in memory order, scatter into LDS planes
+        float4 v[8];
+        if (live) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) v[i] = ld4(psi + base + lane_off + i_off[i]);
         }
-        // 1. scatter the tile (memory order) into LDS planes
         __syncthreads();   // previous tile's results have been read from LDS
         if (live) {
 #pragma unroll
@@ -169,32 +151,16 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
                 }
             }
         }
-        const uint64_t next = tile + waves_total;
-        if (MODE == 0 && next < a.n_tiles) {
-            const uint64_t nbase = insert_zeros(next, a.pos, 10);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = ld4(psi + nbase + lane_off + i_off[i]);
-        }
         __syncthreads();
-        // 2. products on the matrix cores: acc0 = real rows, acc1 = imaginary rows
+        // 2. products on the matrix cores
         f32x16 acc0 = {0}, acc1 = {0};
         if (live) {
             if constexpr (MODE == 0) {
-                float xr[16], xi[16];
 #pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    xr[s] = xs[(2 * s + h) * kXs + c32];
-                    xi[s] = xs[(32 + 2 * s + h) * kXs + c32];
-                }
-                f32x16 k = {0};
-#pragma unroll
-                for (int s = 0; s < 16; ++s) k = __builtin_amdgcn_mfma_f32_32x32x2f32(g1[s], xr[s] + xi[s], k, 0, 0, 0);
-                acc0 = k;
-                acc1 = k;
-#pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(g2[s], xi[s], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(g3[s], xr[s], acc1, 0, 0, 0);
+                for (int s = 0; s < 32; ++s) {
+                    const float bv = xs[(2 * s + h) * kXs + c32];
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[0][s], bv, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[1][s], bv, acc1, 0, 0, 0);
                 }
             } else {
 #pragma unroll

@@ -55,7 +55,7 @@ def _fused_eps(blocks, mode):
         if mode == svmod.FUSED_BF16X3:
             eps.append(errmodel.eps_bf16x3_block(k))
         else:
-            eps.append(errmodel.eps_fp32_block(k, gauss=True))
+            eps.append(errmodel.eps_fp32_block(k))
     return eps
 
 

@@ -26,7 +26,7 @@ def _block_bound(blocks, mode):
     eps = []
     for targets, _ in blocks:
         k = len(targets)
-        eps.append(errmodel.eps_bf16x3_block(k) if mode == svmod.FUSED_BF16X3 else errmodel.eps_fp32_block(k, gauss=True))
+        eps.append(errmodel.eps_bf16x3_block(k) if mode == svmod.FUSED_BF16X3 else errmodel.eps_fp32_block(k))
     return errmodel.state_bound(eps)
 
 
