@@ -268,13 +268,16 @@ __device__ __forceinline__ uint32_t ins0(uint32_t g, const int* pos, int np)
     return g;
 }
 
-// LDS layout of a tile: amplitude i sits at word swz(i). XOR-ing tile bits
-// 5..9 into bits 0..4 spreads the strided accesses of phases whose qubits
-// include low tile bits over all banks (a unit-per-lane access then differs
-// in some of bits 5..9 across lanes). swz is linear over XOR, so
-// swz(a | b) = swz(a) ^ swz(b) for disjoint bit sets, and it only permutes
-// within aligned blocks of 32, so indices stay below 2^m.
-__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+// LDS layout of a tile: amplitude i sits at entry swz(i). An entry is 8
+// bytes, so its bank pair is the entry index mod 16 (bits 0..3); XOR-ing tile
+// bits 4..7 into bits 0..3 spreads the strided accesses of phases whose
+// qubits include low tile bits over all bank pairs (sixteen lanes that take
+// consecutive units then differ in bits 4..7 where they do not differ in bits
+// 0..3). swz is linear over XOR, so swz(a | b) = swz(a) ^ swz(b) for disjoint
+// bit sets, it is its own inverse, and it only permutes within aligned blocks
+// of 16, so indices stay below 2^m. (XOR-ing bits 5..9 into bits 0..4 left
+// bit 4 out of the bank pair: 1.9 conflict cycles per LDS instruction.)
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
 
 // One gate on the tile in LDS.
 template <int NT>
