@@ -174,7 +174,7 @@ def main() -> int:
     circ = C.brickwork_u3_cz(n, 20, 2)
     table = sv.OpTable(circ.ops)
     params = np.ascontiguousarray(circ.params)
-    # the dominant kernel: dense U3 on targets >= 7 all run k_gate<1, 2, 1, true>
+    # the dominant kernel: dense U3 on targets >= 7 all run k_gate<1, 5, 1, true>
     # (float4 member streams; targets 1..6 take the shuffle form, 0 the pair form)
     dense_ops = [i for i, op in enumerate(circ.ops) if op.kind == "u3" and op.targets[0] >= 7]
     dense_set = set(dense_ops)
@@ -272,7 +272,7 @@ def main() -> int:
         "wall_s_timed": round(wall, 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_gate<1, 2, 1, true> (dense one-qubit sweep, float4 member streams, target >= 7)",
+            "kernel": "k_gate<1, 5, 1, true> (dense one-qubit sweep, split-halves form, target >= 7)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -909,7 +909,7 @@ def summarize(argv) -> int:
 
 def run_pmc_probe(n: int) -> int:
     """Short fixed sequence for hardware counters: 4 dense U3 sweeps on
-    targets >= 7 of an n-qubit state (k_gate<1, 2, 1, true>), four fused
+    targets >= 7 of an n-qubit state (k_gate<1, 5, 1, true>), four fused
     5-qubit blocks in each matrix-core mode (one direct, two wide, one
     LDS-staged launch), one six-qubit BF16x3 block, then one plain copy of the
     state (8 * 2^n bytes read, the same written) to scale the counters."""
