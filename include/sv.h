@@ -341,6 +341,18 @@ sv_status sv_adjoint_grad_blocked(sv_state s, const sv_op* ops, int n_ops, const
 sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64_t n_shots,
                           int64_t* dev_out);
 
+/* Shot estimates of every <Z_i> from drawn indices (Sec. 4.3; the Z
+ * statistics of Sec. 2.2.1 sampled): dev_est[i] = 1 - 2 c_i / S for i < n,
+ * with c_i the number of indices that have bit i set and S the number of
+ * indices >= 0 (a zero state's draws, -1, are left out; with none,
+ * dev_est[i] = NaN). The counts are integers, so the result is exact and
+ * run-to-run identical.
+ *   dev_indices: device int64 [n_shots] (e.g. the output of sv_sample_exact),
+ *     8-byte aligned; dev_est: device doubles [n], 8-byte aligned, written.
+ * Asynchronous on the state's stream. Errors: SV_ERR_INVALID_ARGUMENT
+ * (n_shots outside 0..2^31-1, NULL or misaligned pointers), SV_ERR_HIP. */
+sv_status sv_sample_z_estimate(sv_state s, const int64_t* dev_indices, int64_t n_shots, double* dev_est);
+
 /* Gaussian approximation of the shot histogram (Sec. 4.3.2), the
  * reparameterised (differentiable) draw
  *   y = shots p + sqrt(shots) D S z,

@@ -729,6 +729,47 @@ void scan_inclusive(T* x, uint64_t n, T* tmp, hipStream_t st)
 }
 
 // room for the recursive scan's chunk totals of an n-element scan
+// ---------------------------------------------------------- <Z_i> from draws
+//
+// The shot estimate of every <Z_i> (Sec. 4.3, the measurement statistics of
+// Sec. 2.2.1 sampled): E_i = 1 - 2 c_i / S with c_i the number of draws whose
+// index has bit i set and S the number of draws with an index (the zero
+// state's draws, -1, are left out). Counts are integers (wave ballots, one
+// atomic add per wave and qubit), so the result is exact and independent of
+// the order in which the waves finish.
+__global__ __launch_bounds__(kST) void k_zero_u64(unsigned long long* __restrict__ x, int n)
+{
+    if ((int)threadIdx.x < n) x[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(kST) void k_shot_zcount(const int64_t* __restrict__ idx, int64_t shots, int n,
+                                                     unsigned long long* __restrict__ cnt)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long mine = 0, valid = 0;        // lane q < n: draws with bit q set
+    const int64_t stride = (int64_t)gridDim.x * kST;
+    for (int64_t s0 = (int64_t)blockIdx.x * kST + (threadIdx.x & ~63); s0 < shots; s0 += stride) {
+        const int64_t s = s0 + lane;
+        const int64_t v = s < shots ? idx[s] : -1;
+        const bool ok = v >= 0;
+        valid += (unsigned long long)__popcll(__ballot(ok));
+        for (int q = 0; q < n; ++q) {
+            const unsigned long long b = __ballot(ok && ((v >> q) & 1));
+            if (lane == q) mine += (unsigned long long)__popcll(b);
+        }
+    }
+    if (lane < n && mine) atomicAdd(cnt + lane, mine);
+    if (lane == 0 && valid) atomicAdd(cnt + n, valid);
+}
+
+__global__ void k_shot_zest(const unsigned long long* __restrict__ cnt, int n, double* __restrict__ est)
+{
+    const int q = threadIdx.x;
+    if (q >= n) return;
+    const unsigned long long s = cnt[n];
+    est[q] = s ? 1.0 - 2.0 * ((double)cnt[q] / (double)s) : __builtin_nan("");
+}
+
 uint64_t scan_tmp(uint64_t n)
 {
     uint64_t t = 0;
@@ -804,6 +845,21 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
         hipLaunchKernelGGL(k_shot_resolve, dim3(rg), dim3(kST), 0, st, a.psi, bb, (uint32_t)nb, cinc, cnt, order,
                            rem, csum, a.out);
     }
+    SV_HIP(hipGetLastError());
+}
+
+void launch_shot_zest(const int64_t* idx, int64_t shots, int n, void* scratch, double* est, hipStream_t st)
+{
+    unsigned long long* cnt = static_cast<unsigned long long*>(scratch);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kST), 0, st, cnt, n + 1);
+    SV_HIP(hipGetLastError());
+    if (shots > 0) {
+        const unsigned g = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((shots + kST - 1) / kST, (int64_t)device_info().cu_count * 8));
+        hipLaunchKernelGGL(k_shot_zcount, dim3(g), dim3(kST), 0, st, idx, shots, n, cnt);
+        SV_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_shot_zest, dim3(1), dim3(64), 0, st, cnt, n, est);
     SV_HIP(hipGetLastError());
 }
 

@@ -1505,6 +1505,20 @@ sv_status sv_sample_exact(sv_state s, int row, const double* dev_uniforms, int64
     });
 }
 
+sv_status sv_sample_z_estimate(sv_state s, const int64_t* dev_indices, int64_t n_shots, double* dev_est)
+{
+    return guarded([&] {
+        check_state(s);
+        need(n_shots >= 0 && n_shots <= 2147483647ll, SV_ERR_INVALID_ARGUMENT, "n_shots must be 0..2^31-1");
+        need(dev_est != nullptr && (n_shots == 0 || dev_indices != nullptr), SV_ERR_INVALID_ARGUMENT,
+             "NULL device pointer");
+        need(((uintptr_t)dev_indices & 7) == 0 && ((uintptr_t)dev_est & 7) == 0, SV_ERR_INVALID_ARGUMENT,
+             "device arrays must be 8-byte aligned");
+        ensure_scratch(s, (uint64_t)s->n + 1);
+        launch_shot_zest(dev_indices, n_shots, s->n, s->scratch, dev_est, s->stream);
+    });
+}
+
 sv_status sv_sample_gaussian(sv_state s, int row, const double* dev_normals, double shots, double* dev_y)
 {
     return guarded([&] {

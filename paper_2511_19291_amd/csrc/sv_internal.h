@@ -139,6 +139,10 @@ struct ShotLaunch {
 size_t shot_scratch_bytes(int n, int64_t shots);
 void launch_sample_exact(const ShotLaunch& a, hipStream_t st);
 
+// <Z_i> estimates from n_shots drawn indices (-1 = no index): est[n] device
+// doubles; scratch holds n + 1 counters (8 bytes each).
+void launch_shot_zest(const int64_t* idx, int64_t shots, int n, void* scratch, double* est, hipStream_t st);
+
 struct GaussLaunch {
     const float2* psi;        // one row
     int n;

@@ -242,10 +242,8 @@ def measure_allZ(qdev: QuantumDevice, shots: int = 0, training: bool = True, gen
         qdev.state.reset()
         qdev.state.run(circ, params=p if qdev.bsz > 1 else p[0])
         out = torch.empty((qdev.bsz, qdev.n_wires), dtype=torch.float64, device=qdev.device)
-        bits = torch.arange(qdev.n_wires, device=qdev.device)
         for r in range(qdev.bsz):
-            u = torch.rand(int(shots), dtype=torch.float64, device=qdev.device)
+            u = torch.rand(int(shots), dtype=torch.float64, device=qdev.device, generator=generator)
             idx = qdev.state.sample_exact(u, row=r)
-            b = (idx[:, None] >> bits) & 1
-            out[r] = 1.0 - 2.0 * b.double().mean(dim=0)
+            out[r] = qdev.state.sample_z_estimate(idx)
         return out

@@ -140,6 +140,7 @@ def lib() -> C.CDLL:
         "sv_batch_set_spin_limit": [vp, C.c_int],
         "sv_stream_copy": [vp, vp, u64, vp],
         "sv_sample_exact": [vp, C.c_int, vp, i64, vp],
+        "sv_sample_z_estimate": [vp, vp, i64, vp],
         "sv_sample_gaussian": [vp, C.c_int, vp, C.c_double, vp],
         "sv_gaussian_expval_z": [vp, C.c_int, vp, C.c_double, dp],
         "sv_gaussian_expval_z_backward": [vp, C.c_int, vp, C.c_double, dp, vp],
@@ -431,6 +432,19 @@ class State:
         check(lib().sv_sample_exact(self.h, row, C.c_void_p(u.data_ptr()), u.numel(), C.c_void_p(out.data_ptr())))
         self._keep = u          # the kernels read u after this call returns
         return out
+
+    def sample_z_estimate(self, indices):
+        """Shot estimates of every <Z_i> from drawn indices (a device int64
+        tensor, e.g. from ``sample_exact``): 1 - 2 * (share of the indices
+        with bit i set), indices -1 left out. Returns a device float64 tensor
+        of length n; asynchronous on the state's stream."""
+        import torch
+
+        idx = torch.as_tensor(indices, dtype=torch.int64, device=self.tensor.device).contiguous()
+        est = torch.empty(self.n, dtype=torch.float64, device=self.tensor.device)
+        check(lib().sv_sample_z_estimate(self.h, C.c_void_p(idx.data_ptr()), idx.numel(), C.c_void_p(est.data_ptr())))
+        self._keep_idx = idx    # the kernels read the indices after this call returns
+        return est
 
     def sample_gaussian(self, normals, shots: float, row: int = 0):
         """Gaussian shot histogram (Sec. 4.3.2): y = shots p + sqrt(shots) D S z

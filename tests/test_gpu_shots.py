@@ -110,6 +110,46 @@ def test_exact_zero_state_no_shots_and_determinism(sv):
     assert np.array_equal(a, b)
 
 
+def _host_z_estimate(idx, n):
+    """1 - 2 c_i / S from the indices, in the same FP64 steps (integer counts)."""
+    v = idx[idx >= 0]
+    if v.size == 0:
+        return np.full(n, np.nan)
+    return np.array([1.0 - 2.0 * (float(np.count_nonzero((v >> i) & 1)) / float(v.size)) for i in range(n)])
+
+
+@pytest.mark.parametrize("n,shots", [(1, 7), (5, 1000), (12, 65536 + 17), (20, 300000)])
+def test_z_estimate_from_draws(sv, n, shots):
+    """sv_sample_z_estimate: every <Z_i> estimate equals 1 - 2 (share of the
+    draws with bit i set) computed on the host from the same indices
+    (bit-equal: the counts are integers), and lies within 5 sigma of the
+    oracle's exact <Z_i>."""
+    rng = np.random.default_rng(n + shots)
+    psi = pins.random_state(n, rng)
+    st, ref = _upload(sv, psi)
+    idx = st.sample_exact(rng.random(shots))
+    est = st.sample_z_estimate(idx).cpu().numpy()
+    want = _host_z_estimate(idx.cpu().numpy(), n)
+    assert np.array_equal(est, want)
+    z, norm2 = oracle.expval_z_all(ref, n)
+    z = z / norm2
+    sigma = np.sqrt(np.maximum(1 - z * z, 1e-12) / shots)
+    assert np.all(np.abs(est - z) <= 5 * sigma + 1e-12)
+
+
+def test_z_estimate_edge_cases(sv):
+    st = sv.State(6).from_numpy(np.zeros((1, 1 << 6), dtype=np.complex64))
+    idx = st.sample_exact(np.array([0.1, 0.5]))
+    assert np.all(np.isnan(st.sample_z_estimate(idx).cpu().numpy()))       # the zero state: no index
+    st = sv.State(6).reset(0b101101)
+    est = st.sample_z_estimate(st.sample_exact(np.linspace(0.0, 0.99, 50))).cpu().numpy()
+    assert np.array_equal(est, np.array([-1.0, 1.0, -1.0, -1.0, 1.0, -1.0]))
+    assert np.all(np.isnan(st.sample_z_estimate(np.zeros(0, dtype=np.int64)).cpu().numpy()))
+    L = svmod.lib()
+    assert L.sv_sample_z_estimate(st.h, None, 5, None) == 1
+    assert L.sv_sample_z_estimate(st.h, None, -1, None) == 1
+
+
 def test_exact_bad_arguments(sv):
     st = sv.State(4).reset()
     import ctypes as C_
