@@ -56,14 +56,60 @@ constexpr int kChunkBits = 7;
 static_assert(kShotBits - kChunkBits <= 6, "a lane per chunk");
 
 // 1. probability mass of each block of 2^bb amplitudes (bb <= kShotBits).
-// With chunks: wave w reads chunks 8w .. 8w + 7 of the block in memory order
-// (one float4 per lane and chunk: lane l holds amplitudes 2l, 2l + 1), eight
-// loads in flight. The 64-lane sums of the eight chunks are formed together
-// by a reduce-scatter butterfly (xor 32, 16, 8 halve the values a lane
-// carries, xor 4, 2, 1 finish one chunk per group of eight lanes): ten FP64
-// exchanges for eight chunks, in a fixed order. The block's mass is the sum
-// of its chunks' in chunk order. (Measured: one wave per block with two
-// passes of sixteen chunks is 24 % slower at 30 qubits.)
+// Blocks of at least 128 amplitudes (k_chunk_mass): one workgroup of eight
+// waves per block (2^12 amplitudes: 32 chunks of 128), wave w reading chunks
+// 4w .. 4w + 3 in memory order (one float4 per lane and chunk: lane l holds
+// amplitudes 2l, 2l + 1), four loads in flight. The 64-lane sums of the four
+// chunks are formed together by a reduce-scatter butterfly (xor 32, 16 halve
+// the values a lane carries, xor 8, 4, 2, 1 finish one chunk per group of
+// sixteen lanes): seven FP64 exchanges for four chunks, in a fixed order.
+// The block's mass is the sum of its chunks' in chunk order. (Measured at 30
+// qubits: eight chunks per wave and four waves per block 1.49 ms; one wave
+// per block with two passes of sixteen chunks 1.85 ms.)
+constexpr int kMassThreads = 512;
+__global__ __launch_bounds__(kMassThreads) void k_chunk_mass(const float2* __restrict__ psi, int bb,
+                                                            double* __restrict__ mass, double* __restrict__ csum)
+{
+    __shared__ double sh[1 << (kShotBits - kChunkBits)];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t nch = 1u << (bb - kChunkBits);
+    const float4* p4 = reinterpret_cast<const float4*>(psi + ((uint64_t)blockIdx.x << bb));
+    if ((uint32_t)(4 * w) < nch) {
+        float4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = (uint32_t)(4 * w + i) < nch ? p4[(4 * w + i) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        double t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[i] = prob(make_float2(v[i].x, v[i].y)) + prob(make_float2(v[i].z, v[i].w));
+        const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1;
+        double u2[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const double keep = b5 ? t[2 + j] : t[j], send = b5 ? t[j] : t[2 + j];
+            u2[j] = keep + __shfl_xor(send, 32, 64);
+        }
+        double c = (b4 ? u2[1] : u2[0]) + __shfl_xor(b4 ? u2[0] : u2[1], 16, 64);
+        c += __shfl_xor(c, 8, 64);
+        c += __shfl_xor(c, 4, 64);
+        c += __shfl_xor(c, 2, 64);
+        c += __shfl_xor(c, 1, 64);
+        const uint32_t ch = 4 * w + 2 * b5 + b4;            // the chunk this lane's group summed
+        if ((lane & 15) == 0 && ch < nch) {
+            sh[ch] = c;
+            csum[((uint64_t)blockIdx.x << (kShotBits - kChunkBits)) + ch] = c;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (uint32_t c = 0; c < nch; ++c) m += sh[c];
+        mass[blockIdx.x] = m;
+    }
+}
+
+// Blocks below 128 amplitudes (states below 7 qubits): one workgroup sums a
+// block.
 __global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ psi, int bb, uint64_t nb,
                                                     double* __restrict__ mass, double* __restrict__ csum)
 {
@@ -71,48 +117,6 @@ __global__ __launch_bounds__(kST) void k_block_mass(const float2* __restrict__ p
     const uint64_t base = (uint64_t)blockIdx.x << bb;
     const uint32_t bs = 1u << bb;
     (void)nb;
-    if (bb >= kChunkBits) {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const uint32_t nch = 1u << (bb - kChunkBits);
-        const float4* p4 = reinterpret_cast<const float4*>(psi + base);
-        if ((uint32_t)(8 * w) < nch) {
-            float4 v[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                v[i] = (uint32_t)(8 * w + i) < nch ? p4[(8 * w + i) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-            double t[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) t[i] = prob(make_float2(v[i].x, v[i].y)) + prob(make_float2(v[i].z, v[i].w));
-            const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
-            double u4[4], u2[2];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const double keep = b5 ? t[4 + j] : t[j], send = b5 ? t[j] : t[4 + j];
-                u4[j] = keep + __shfl_xor(send, 32, 64);
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const double keep = b4 ? u4[2 + j] : u4[j], send = b4 ? u4[j] : u4[2 + j];
-                u2[j] = keep + __shfl_xor(send, 16, 64);
-            }
-            double c = (b3 ? u2[1] : u2[0]) + __shfl_xor(b3 ? u2[0] : u2[1], 8, 64);
-            c += __shfl_xor(c, 4, 64);
-            c += __shfl_xor(c, 2, 64);
-            c += __shfl_xor(c, 1, 64);
-            const uint32_t ch = 8 * w + 4 * b5 + 2 * b4 + b3;      // the chunk this lane's group summed
-            if ((lane & 7) == 0 && ch < nch) {
-                sh[ch] = c;
-                csum[((uint64_t)blockIdx.x << (kShotBits - kChunkBits)) + ch] = c;
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double m = 0.0;
-            for (uint32_t c = 0; c < nch; ++c) m += sh[c];
-            mass[blockIdx.x] = m;
-        }
-        return;
-    }
     double acc = 0.0;
     if (bs >= 2) {
         const float4* p4 = reinterpret_cast<const float4*>(psi + base);
@@ -818,7 +822,10 @@ void launch_sample_exact(const ShotLaunch& a, hipStream_t st)
     const uint64_t nch = nb << (kShotBits - kChunkBits);
     double* csum = reinterpret_cast<double*>(take(nch * sizeof(double)));
 
-    hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, (uint64_t)nb, mass, csum);
+    if (bb >= kChunkBits)
+        hipLaunchKernelGGL(k_chunk_mass, dim3((unsigned)nb), dim3(kMassThreads), 0, st, a.psi, bb, mass, csum);
+    else
+        hipLaunchKernelGGL(k_block_mass, dim3((unsigned)nb), dim3(kST), 0, st, a.psi, bb, (uint64_t)nb, mass, csum);
     SV_HIP(hipGetLastError());
     scan_inclusive<double>(mass, nb, dtmp, st);
     if (a.shots == 0) return;
