@@ -1299,8 +1299,8 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
         };
 
         // ---- device buffers: fragments, the waves' S parts, S per launch and row
-        const int grid_full = adj_mfma_grid(s->n);
-        const int grid = std::max(1, std::min(grid_full, (grid_full + B - 1) / B));
+        const AdjMfmaShape shape = adj_mfma_shape(s->n, B);
+        const int grid = shape.grid;
         const uint64_t spart_max = std::max<uint64_t>(1, adj_mfma_part_doubles(grid, B));
         const uint64_t s_total = (uint64_t)launches.size() * B * 1024;
         const uint64_t red = std::max<uint64_t>(inner_parts(s->n, B), drift_parts(s->n, B));
@@ -1353,6 +1353,7 @@ sv_status adjoint_mfma_impl(sv_state s, const sv_op* ops, int n_ops, const doubl
                 a.frag_stride = L.nfr > 1 ? 1024 : 0;
                 a.spart = spart;
                 a.grid = grid;
+                a.gpw = shape.gpw;
                 launch_adj_mfma(a, B, d_s + (size_t)li * B * 1024, s->stream);
             }
             SV_HIP(hipMemcpyAsync(s->hout + (size_t)l0 * B * 1024, d_s + (size_t)l0 * B * 1024,

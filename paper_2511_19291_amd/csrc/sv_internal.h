@@ -181,10 +181,18 @@ struct AdjMfmaLaunch {
     int q[4];                 // block qubits, ascending
     const float* frag;        // 64 lanes x 16 floats: operands of [[Re M, -Im M], [Im M, Re M]], M = U_B^*
     int frag_stride;          // floats between rows' operands (0: one product for all rows)
-    double* spart;            // adj_mfma_part_doubles(grid, rows): [rows][grid][1024], then the chunk sums
+    double* spart;            // adj_mfma_part_doubles(grid, rows): [rows][grid][kAmPart], then the level sums
     int grid;                 // workgroups per row
+    int gpw;                  // groups (of 512 amplitudes) per wave
 };
-int adj_mfma_grid(int n);
+constexpr int kAmPart = 512;                   // doubles of a workgroup's part: Re S, Im S (16 x 16 each)
+constexpr int kAmMinGpw = 4;                   // default groups per wave
+constexpr uint64_t kAmMaxParts = 1ull << 16;   // workgroups of one launch, all rows
+struct AdjMfmaShape {
+    int grid;                 // workgroups per row
+    int gpw;                  // groups per wave
+};
+AdjMfmaShape adj_mfma_shape(int n, int rows, int min_gpw = kAmMinGpw);
 uint64_t adj_mfma_part_doubles(int grid, int rows);
 void launch_adj_mfma(const AdjMfmaLaunch& a, int rows, double* s_out, hipStream_t st);
 
