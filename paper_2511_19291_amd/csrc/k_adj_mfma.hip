@@ -411,16 +411,20 @@ __global__ __launch_bounds__(kAmThreads) void k_adj_mfma_final(const double* __r
 
 }  // namespace
 
-// Groups per wave and workgroups per row: at least kAmMinGpw groups per wave
-// (the parts cost 4 KiB per workgroup), more when the parts of all rows would
-// pass kAmMaxParts.
+// Groups per wave and workgroups per row: kAmMinGpw groups per wave (the
+// parts cost 4 KiB per workgroup), fewer while the launch would not fill the
+// chip once (three resident workgroups per CU), more while the parts of all
+// rows would pass kAmMaxParts.
 AdjMfmaShape adj_mfma_shape(int n, int rows, int min_gpw)
 {
     const uint64_t groups = std::max<uint64_t>(1, (1ull << n) >> 9);
+    const uint64_t r = (uint64_t)std::max(rows, 1);
+    const uint64_t fill = (uint64_t)device_info().cu_count * 3;
+    auto wgs = [&](uint64_t g) { return (groups + kAmWaves * g - 1) / (kAmWaves * g); };
     uint64_t gpw = (uint64_t)std::max(1, min_gpw);
-    while ((groups + kAmWaves * gpw - 1) / (kAmWaves * gpw) * (uint64_t)std::max(rows, 1) > kAmMaxParts) gpw *= 2;
-    const uint64_t grid = (groups + kAmWaves * gpw - 1) / (kAmWaves * gpw);
-    return AdjMfmaShape{(int)grid, (int)gpw};
+    while (gpw > 1 && wgs(gpw) * r < fill) gpw /= 2;
+    while (wgs(gpw) * r > kAmMaxParts) gpw *= 2;
+    return AdjMfmaShape{(int)wgs(gpw), (int)gpw};
 }
 
 // doubles of the parts and of the two level buffers for `rows` rows at
