@@ -834,9 +834,11 @@ def summarize(argv) -> int:
                                       FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernels
                                       matching RE, scaled by COPY_BYTES / what the same counter reads
                                       for the plain copy kernel k_copy of the same run
-      counters DIR [RE]               per kernel: median duration and counters; with
-                                      GRBM_GUI_ACTIVE the clock (busy cycles / 8 XCDs / duration) and,
-                                      with SQ_VALU_MFMA_BUSY_CYCLES, the matrix cores' busy share"""
+      counters DIR [RE]               per kernel: median duration, launch shape and counters; with
+                                      GRBM_GUI_ACTIVE the clock (busy cycles / 8 XCDs / duration),
+                                      with SQ_VALU_MFMA_BUSY_CYCLES the matrix cores' busy share, and
+                                      with SQ_WAVE_CYCLES the shares of wave time at a wait
+                                      (SQ_WAIT_ANY) and waiting to issue (SQ_WAIT_INST_ANY)"""
     import statistics
 
     kind = argv[0]
@@ -885,7 +887,12 @@ def summarize(argv) -> int:
         return 0
     if kind == "counters":
         regex = argv[2] if len(argv) > 2 else None
-        vals, dur = _per_dispatch(_csvs(argv[1], "counter_collection.csv"), regex)
+        rows = _csvs(argv[1], "counter_collection.csv")
+        vals, dur = _per_dispatch(rows, regex)
+        meta = {}
+        for r in rows:
+            meta.setdefault(r["Kernel_Name"], {k: r.get(k, "") for k in ("Workgroup_Size", "LDS_Block_Size",
+                                                                            "VGPR_Count", "Accum_VGPR_Count")})
         by = {}
         for key, v in vals.items():
             by.setdefault(key[0], []).append((dur[key], v))
@@ -895,8 +902,21 @@ def summarize(argv) -> int:
             ctrs = sorted({c for _, v in lst for c in v})
             print(f"{name[:120]}")
             print(f"  dispatches {len(lst)}, median duration {ms:.4f} ms")
+            m = meta.get(name, {})
+            if m.get("VGPR_Count"):
+                print(f"  launch: workgroup {m['Workgroup_Size']} threads, LDS {m['LDS_Block_Size']} B, "
+                      f"rocprofv3 VGPR_Count {m['VGPR_Count']} / Accum_VGPR_Count {m['Accum_VGPR_Count']}")
             for c in ctrs:
                 print(f"  {c:28s} median {med([v.get(c, 0.0) for _, v in lst]):.4e}")
+            if "SQ_WAVE_CYCLES" in ctrs:
+                # shares of the waves' resident time (all three counters count wave quad-cycles)
+                wc = med([v["SQ_WAVE_CYCLES"] for _, v in lst])
+                if "SQ_WAIT_ANY" in ctrs:
+                    wa = med([v["SQ_WAIT_ANY"] for _, v in lst])
+                    print(f"  share of resident wave time at a wait (SQ_WAIT_ANY / SQ_WAVE_CYCLES): {wa / wc:.3f}")
+                if "SQ_WAIT_INST_ANY" in ctrs:
+                    wi = med([v["SQ_WAIT_INST_ANY"] for _, v in lst])
+                    print(f"  share of resident wave time waiting to issue (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES): {wi / wc:.3f}")
             if "GRBM_GUI_ACTIVE" in ctrs:
                 g = med([v["GRBM_GUI_ACTIVE"] for _, v in lst])
                 print(f"  clock GHz (GRBM_GUI_ACTIVE / 8 XCDs / duration): {g / 8 / (ms * 1e6):.2f}")
