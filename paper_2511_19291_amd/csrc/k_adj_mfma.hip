@@ -135,24 +135,6 @@ __global__ __launch_bounds__(kAmThreads) __attribute__((amdgpu_waves_per_eu(3)))
         u = ((u >> q2) << (q2 + 1)) | (u & ((1ull << q2) - 1));
         return ((u >> q3) << (q3 + 1)) | (u & ((1ull << q3) - 1));
     };
-    // Three real products give S (Gauss): with the tile rows 0..15 the real
-    // parts and 16..31 the imaginary parts,
-    //   s00 += Re psi Re lam^T,  s11 += Im psi Im lam^T,
-    //   s10 += (Re psi + Im psi)(Re lam - Im lam)^T,
-    // so Re S = s00 + s11 and Im S = s10 - s00 + s11. The sums of two FP32
-    // values are exact in FP64 (A lane holds row lane % 16 of step column
-    // lane / 16).
-    auto correlate = [&](int ln) {
-#pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const int kk = 4 * st + (ln >> 4), ii = ln & 15;
-            const double a0 = tpw[tix<COAL>(ii, kk)], a1 = tpw[tix<COAL>(16 + ii, kk)];
-            const double b0 = tlw[tix<COAL>(ii, kk)], b1 = tlw[tix<COAL>(16 + ii, kk)];
-            s00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, s00, 0, 0, 0);
-            s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
-            s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0 + a1, b0 - b1, s10, 0, 0, 0);
-        }
-    };
     // Wave w of workgroup b takes groups (b gpw + i) kAmWaves + w, i < gpw:
     // a workgroup covers kAmWaves gpw consecutive groups. Each wave works
     // through its groups with its own LDS tiles, so only the wave itself has
@@ -166,6 +148,36 @@ __global__ __launch_bounds__(kAmThreads) __attribute__((amdgpu_waves_per_eu(3)))
     constexpr uint64_t stride = kAmWaves;
     const uint64_t gend = grp + (uint64_t)a.gpw * stride < groups ? grp + (uint64_t)a.gpw * stride : groups;
     float2 x[8], l[8];
+    // Three real products give S (Gauss): with the tile rows 0..15 the real
+    // parts and 16..31 the imaginary parts,
+    //   s00 += Re psi Re lam^T,  s11 += Im psi Im lam^T,
+    //   s10 += (Re psi + Im psi)(Re lam - Im lam)^T,
+    // so Re S = s00 + s11 and Im S = s10 - s00 + s11. The sums of two FP32
+    // values are exact in FP64 (A lane holds row lane % 16 of step column
+    // lane / 16).
+    // The correlation's three FP64 chains and the un-apply of psi (below) run
+    // interleaved step by step (four independent accumulator chains for the
+    // matrix pipe); psi's results are written only after the loop, so the
+    // correlation still reads the tile's values from before the block.
+    auto correlate_unapply_psi = [&](int ln) {
+        const int hh = ln >> 5, cc = ln & 31;
+        f32x16 y = {0};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            y = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[s], tpw[tix<COAL>(16 * (s & 1) + 8 * hh + (s >> 1), cc)], y, 0,
+                                                     0, 0);
+            if (s & 1) {
+                const int st = s >> 1;
+                const int kk = 4 * st + (ln >> 4), ii = ln & 15;
+                const double a0 = tpw[tix<COAL>(ii, kk)], a1 = tpw[tix<COAL>(16 + ii, kk)];
+                const double b0 = tlw[tix<COAL>(ii, kk)], b1 = tlw[tix<COAL>(16 + ii, kk)];
+                s00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, s00, 0, 0, 0);
+                s11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, s11, 0, 0, 0);
+                s10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0 + a1, b0 - b1, s10, 0, 0, 0);
+            }
+        }
+        return y;
+    };
     // un-apply y = M x from a tile (step s: component s & 1 of amplitude
     // 8h + (s >> 1), tile row 16 (s & 1) + 8h + (s >> 1); output register r:
     // component r & 1 of amplitude 8h + (r >> 1))
@@ -258,11 +270,10 @@ __global__ __launch_bounds__(kAmThreads) __attribute__((amdgpu_waves_per_eu(3)))
             const uint64_t gn = grp + stride;
             if (gn < gend) load(gn);
             wave_lds_sync();
-            correlate(ln);
             // un-apply in place, one vector after the other: a lane's inputs
             // and outputs are the same tile entries (rows 8h + t and
             // 16 + 8h + t of column cu), and the wave's LDS accesses run in order
-            f32x16 y = unapply(tpw, ln);
+            f32x16 y = correlate_unapply_psi(ln);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 tpw[tix<COAL>(8 * hn + t, cn)] = y[2 * t];
@@ -323,10 +334,9 @@ __global__ __launch_bounds__(kAmThreads) __attribute__((amdgpu_waves_per_eu(3)))
             const uint64_t gn = grp + stride;
             if (gn < gend) load(gn);
             wave_lds_sync();
-            correlate(lane);
             float2* pb = psi + column(grp, 0);
             float2* lb = lam + column(grp, 0);
-            f32x16 y = unapply(tpw, lane);
+            f32x16 y = correlate_unapply_psi(lane);
 #pragma unroll
             for (int t = 0; t < 8; ++t) st2(pb + toff(t) + lh, make_float2(y[2 * t], y[2 * t + 1]));
             y = unapply(tlw, lane);
