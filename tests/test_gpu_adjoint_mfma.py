@@ -141,6 +141,33 @@ def test_paper_size_vs_per_gate(sv):
     st.free()
 
 
+def test_many_rows_more_groups_per_wave(sv):
+    """520 rows of 20 qubits: four groups of 512 amplitudes per wave would
+    need more than 2^16 workgroups for the launch's parts of S, so each wave
+    takes eight groups (a different tiling of the same sweep). Every row
+    against the per-gate GPU backward; rows 0 and 519 also against a 10-row
+    run of the same inputs, which takes four groups per wave."""
+    n, B = 20, 520
+    circ, rows = C.profiling_ladder(n, 1, B, seed=31)
+    terms = C.z_sum_terms(n)
+    st = sv.State(n, B)
+    st.reset().run(circ, params=rows)
+    _, g_gate, _ = st.adjoint_grad(circ, terms, params=rows)
+    st.reset().run(circ, params=rows)
+    _, g_m, d = st.adjoint_grad(circ, terms, params=rows, block_qubits=MF)
+    for r in range(B):
+        _close(g_m[r], g_gate[r], rel=2e-5)
+    assert np.all(d < 1e-4)
+    st.free()
+    sub = np.ascontiguousarray(rows[[0, B - 1] * 5])
+    s2 = sv.State(n, 10)
+    s2.reset().run(circ, params=sub)
+    _, g_s, _ = s2.adjoint_grad(circ, terms, params=sub, block_qubits=MF)
+    _close(g_s[0], g_m[0], rel=2e-5)
+    _close(g_s[1], g_m[B - 1], rel=2e-5)
+    s2.free()
+
+
 def test_refusals(sv):
     st = sv.State(8).reset()
     with pytest.raises(svmod.SvError) as e:
