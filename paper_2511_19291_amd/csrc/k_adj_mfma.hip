@@ -106,7 +106,8 @@ __device__ __forceinline__ float2* am_row(const Rows& r, int row)
 // group's nine varying address bits (the block's qubits and the five lowest
 // other qubits) then include bits 0..5, so each load or store of the wave
 // covers 512 contiguous bytes; the per-wave LDS tiles convert between
-// memory order and the lane layout of the products.
+// memory order and the lane layout of the products. Three waves per SIMD
+// (at most 168 registers; the compiler would take 172 in the column form).
 template <bool COAL>
 __global__ __launch_bounds__(kAmThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_adj_mfma(AdjMfmaLaunch a)
 {
