@@ -413,7 +413,7 @@ sv_status apply_fused_impl(sv_state s, const sv_block* blocks, int n_blocks, int
         }
         if (n_blocks == 0) return SV_OK;
         // per-block device payload (16-byte multiples)
-        const size_t per5 = mfma ? (size_t)2 * 64 * 64 * sizeof(float)
+        const size_t per5 = mfma ? (size_t)3 * 64 * 64 * sizeof(float)
                                  : (size_t)32 * 32 * sizeof(float2) + 32 * sizeof(uint64_t) + 8 * sizeof(int);
         std::vector<size_t> off(n_blocks + 1, 0);
         for (int i = 0; i < n_blocks; ++i)
@@ -467,6 +467,15 @@ sv_status apply_fused_impl(sv_state s, const sv_block* blocks, int n_blocks, int
                             A[(32 + r) * 64 + c] = im;
                             A[(32 + r) * 64 + 32 + c] = re;
                         }
+                    // the FP32 products' left operands in fragment order: element
+                    // (b, q, lane, e) = A~[32 b + lane % 32][2 (4 q + e) + lane / 32]
+                    float* F = A + 2 * 64 * 64;
+                    for (int b = 0; b < 2; ++b)
+                        for (int q = 0; q < 8; ++q)
+                            for (int l = 0; l < 64; ++l)
+                                for (int e = 0; e < 4; ++e)
+                                    F[((b * 8 + q) * 64 + l) * 4 + e] =
+                                        A[(32 * b + (l & 31)) * 64 + 2 * (4 * q + e) + (l >> 5)];
                     if (mode == SV_FUSED_BF16X3) {
                         float* L = A + 64 * 64;
                         for (int q = 0; q < 64 * 64; ++q) {

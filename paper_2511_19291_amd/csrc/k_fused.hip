@@ -104,7 +104,15 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
+            for (int q = 0; q < 8; ++q) {
+                // fragment-ordered copy after the two 64 x 64 parts:
+                // element (b, q, lane, e) = A~[32 b + lane % 32][2 (4 q + e) + lane / 32]
+                const float4 t4 = reinterpret_cast<const float4*>(am + 2 * 64 * 64)[(b * 8 + q) * 64 + lane];
+                afr[b][4 * q] = t4.x;
+                afr[b][4 * q + 1] = t4.y;
+                afr[b][4 * q + 2] = t4.z;
+                afr[b][4 * q + 3] = t4.w;
+            }
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -258,7 +266,15 @@ __global__ __launch_bounds__(256) void k_fused_direct(KFusedDirect a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
+            for (int q = 0; q < 8; ++q) {
+                // fragment-ordered copy after the two 64 x 64 parts:
+                // element (b, q, lane, e) = A~[32 b + lane % 32][2 (4 q + e) + lane / 32]
+                const float4 t4 = reinterpret_cast<const float4*>(am + 2 * 64 * 64)[(b * 8 + q) * 64 + lane];
+                afr[b][4 * q] = t4.x;
+                afr[b][4 * q + 1] = t4.y;
+                afr[b][4 * q + 2] = t4.z;
+                afr[b][4 * q + 3] = t4.w;
+            }
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -376,7 +392,15 @@ __global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int s = 0; s < 32; ++s) afr[b][s] = am[(32 * b + c32) * 64 + 2 * s + h];
+            for (int q = 0; q < 8; ++q) {
+                // fragment-ordered copy after the two 64 x 64 parts:
+                // element (b, q, lane, e) = A~[32 b + lane % 32][2 (4 q + e) + lane / 32]
+                const float4 t4 = reinterpret_cast<const float4*>(am + 2 * 64 * 64)[(b * 8 + q) * 64 + lane];
+                afr[b][4 * q] = t4.x;
+                afr[b][4 * q + 1] = t4.y;
+                afr[b][4 * q + 2] = t4.z;
+                afr[b][4 * q + 3] = t4.w;
+            }
     } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -597,6 +621,10 @@ __global__ __launch_bounds__(256) void k_fused_valu(float2* psi, uint64_t N, uin
     }
 }
 
+// tiles per wave of the one-shot FP32 grids
+constexpr uint64_t kOneShotTilesDirect = 4;
+constexpr uint64_t kOneShotTilesLds = 8;
+
 }  // namespace
 
 void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
@@ -619,7 +647,9 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         for (int b = 0; b < 5; ++b) d.pos[6 + b] = t5[b];
         d.amat = f.amat;
         d.amat_stride = f.amat_stride;
-        // persistent grid: two workgroups per CU are resident (registers)
+        // grid-stride grid of two workgroups per CU (276 registers per lane:
+        // one wave per SIMD, so one workgroup per CU runs at a time); one-shot
+        // grids of 2 to 16 tiles per wave measured 2-13 % slower on this form
         const uint64_t want = (d.n_tiles + 3) / 4;
         const uint64_t cap = (uint64_t)device_info().cu_count * 2;
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
@@ -645,10 +675,15 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         for (int b = 0; b < 5; ++b) d.pos[5 + b] = t5[b];
         d.amat = f.amat;
         d.amat_stride = f.amat_stride;
-        // persistent grid: two workgroups per CU are resident (registers)
+        // FP32: one-shot grid, four tiles per wave (the waves end as their
+        // tiles are done; 3.04 ms per 30-qubit block against 3.48 with a
+        // persistent grid of two workgroups per CU), never fewer workgroups
+        // than that persistent grid. BF16x3 (operands split on every
+        // workgroup's start): the persistent grid.
         const uint64_t want = (d.n_tiles + 3) / 4;
-        const uint64_t cap = (uint64_t)device_info().cu_count * 2;
-        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+        const uint64_t pers = std::min(want, (uint64_t)device_info().cu_count * 2);
+        const uint64_t g = f.mode == SV_FUSED_FP32_MFMA ? std::max(pers, want / kOneShotTilesDirect) : pers;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, g);
         if (f.mode == SV_FUSED_FP32_MFMA)
             hipLaunchKernelGGL(k_fused_direct<0>, dim3(grid, f.nrows), dim3(256), 0, st, d);
         else
@@ -683,10 +718,14 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
     }
     a.amat = f.amat;
     a.amat_stride = f.amat_stride;
-    // persistent grid: eight single-wave workgroups per CU are resident (registers)
+    // FP32: one-shot grid, eight tiles per wave (3.23 ms per block of the
+    // 30-qubit brickwork plan against 3.29 with the persistent grid of eight
+    // single-wave workgroups per CU), never fewer workgroups than that
+    // persistent grid. BF16x3: the persistent grid.
     const uint64_t want = (a.n_tiles + kWaves - 1) / kWaves;
-    const uint64_t cap = (uint64_t)device_info().cu_count * 8;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+    const uint64_t pers = std::min(want, (uint64_t)device_info().cu_count * 8);
+    const uint64_t g = f.mode == SV_FUSED_FP32_MFMA ? std::max(pers, want / kOneShotTilesLds) : pers;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, g);
     if (f.mode == SV_FUSED_FP32_MFMA)
         hipLaunchKernelGGL(k_fused<0>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);
     else
