@@ -483,6 +483,20 @@ sv_status apply_fused_impl(sv_state s, const sv_block* blocks, int n_blocks, int
                             L[q] = A[q] - hi;
                             A[q] = hi;
                         }
+                        // the BF16 products' left operands in fragment order (in place
+                        // of the FP32 fragments): the 8 values of (b, s, part, lane) =
+                        // part [32 b + lane % 32][16 s + 8 (lane / 32) + q], part 0 the
+                        // hi values, 1 the lo values rounded to BF16
+                        uint16_t* H = reinterpret_cast<uint16_t*>(F);
+                        for (int b = 0; b < 2; ++b)
+                            for (int st = 0; st < 4; ++st)
+                                for (int part = 0; part < 2; ++part)
+                                    for (int l = 0; l < 64; ++l)
+                                        for (int q = 0; q < 8; ++q) {
+                                            const int at = (32 * b + (l & 31)) * 64 + 16 * st + 8 * (l >> 5) + q;
+                                            H[((((b * 4 + st) * 2 + part) * 64) + l) * 8 + q] =
+                                                bf16_rne_bits(part == 0 ? A[at] : L[at]);
+                                        }
                     }
                 }
             } else {

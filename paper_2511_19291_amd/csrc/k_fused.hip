@@ -32,6 +32,7 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 1;
 constexpr int kXs = 33;              // FP32 layout Xs[64][33]: [k][col]
@@ -118,14 +119,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_fused(KFused a)
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                float th[8], tl[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    th[q] = am[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                    tl[q] = am[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                }
-                ahi[b][s] = to_bf16(th);
-                alo[b][s] = to_bf16(tl);
+                // fragment-ordered BF16 copy after the two 64 x 64 parts: the 8
+                // values of (b, s, part, lane) = part [32 b + lane % 32][16 s + 8 (lane / 32) + q]
+                const u32x4* fb = reinterpret_cast<const u32x4*>(am + 2 * 64 * 64);
+                ahi[b][s] = __builtin_bit_cast(bf16x8, fb[((b * 4 + s) * 2 + 0) * 64 + lane]);
+                alo[b][s] = __builtin_bit_cast(bf16x8, fb[((b * 4 + s) * 2 + 1) * 64 + lane]);
             }
     }
 
@@ -280,14 +278,11 @@ __global__ __launch_bounds__(256) void k_fused_direct(KFusedDirect a)
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                float th[8], tl[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    th[q] = am[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                    tl[q] = am[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                }
-                ahi[b][s] = to_bf16(th);
-                alo[b][s] = to_bf16(tl);
+                // fragment-ordered BF16 copy after the two 64 x 64 parts: the 8
+                // values of (b, s, part, lane) = part [32 b + lane % 32][16 s + 8 (lane / 32) + q]
+                const u32x4* fb = reinterpret_cast<const u32x4*>(am + 2 * 64 * 64);
+                ahi[b][s] = __builtin_bit_cast(bf16x8, fb[((b * 4 + s) * 2 + 0) * 64 + lane]);
+                alo[b][s] = __builtin_bit_cast(bf16x8, fb[((b * 4 + s) * 2 + 1) * 64 + lane]);
             }
     }
     // tiles of this wave: w, w + W, w + 2W, ... (W waves in the grid); the
@@ -406,14 +401,11 @@ __global__ __launch_bounds__(256) void k_fused_wide(KFusedWide a)
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                float th[8], tl[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    th[q] = am[(32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                    tl[q] = am[64 * 64 + (32 * b + c32) * 64 + 16 * s + 8 * h + q];
-                }
-                ahi[b][s] = to_bf16(th);
-                alo[b][s] = to_bf16(tl);
+                // fragment-ordered BF16 copy after the two 64 x 64 parts: the 8
+                // values of (b, s, part, lane) = part [32 b + lane % 32][16 s + 8 (lane / 32) + q]
+                const u32x4* fb = reinterpret_cast<const u32x4*>(am + 2 * 64 * 64);
+                ahi[b][s] = __builtin_bit_cast(bf16x8, fb[((b * 4 + s) * 2 + 0) * 64 + lane]);
+                alo[b][s] = __builtin_bit_cast(bf16x8, fb[((b * 4 + s) * 2 + 1) * 64 + lane]);
             }
     }
     const uint64_t waves_total = (uint64_t)gridDim.x * 4;
@@ -621,7 +613,7 @@ __global__ __launch_bounds__(256) void k_fused_valu(float2* psi, uint64_t N, uin
     }
 }
 
-// tiles per wave of the one-shot FP32 grids
+// tiles per wave of the one-shot grids
 constexpr uint64_t kOneShotTilesDirect = 4;
 constexpr uint64_t kOneShotTilesLds = 8;
 
@@ -675,14 +667,13 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         for (int b = 0; b < 5; ++b) d.pos[5 + b] = t5[b];
         d.amat = f.amat;
         d.amat_stride = f.amat_stride;
-        // FP32: one-shot grid, four tiles per wave (the waves end as their
-        // tiles are done; 3.04 ms per 30-qubit block against 3.48 with a
-        // persistent grid of two workgroups per CU), never fewer workgroups
-        // than that persistent grid. BF16x3 (operands split on every
-        // workgroup's start): the persistent grid.
+        // one-shot grid, four tiles per wave (the waves end as their tiles
+        // are done; 3.05 / 2.99 ms per 30-qubit block in FP32 / BF16x3
+        // against 3.48 / 3.24 with a persistent grid of two workgroups per
+        // CU), never fewer workgroups than that persistent grid
         const uint64_t want = (d.n_tiles + 3) / 4;
         const uint64_t pers = std::min(want, (uint64_t)device_info().cu_count * 2);
-        const uint64_t g = f.mode == SV_FUSED_FP32_MFMA ? std::max(pers, want / kOneShotTilesDirect) : pers;
+        const uint64_t g = std::max(pers, want / kOneShotTilesDirect);
         const unsigned grid = (unsigned)std::max<uint64_t>(1, g);
         if (f.mode == SV_FUSED_FP32_MFMA)
             hipLaunchKernelGGL(k_fused_direct<0>, dim3(grid, f.nrows), dim3(256), 0, st, d);
@@ -718,13 +709,13 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
     }
     a.amat = f.amat;
     a.amat_stride = f.amat_stride;
-    // FP32: one-shot grid, eight tiles per wave (3.23 ms per block of the
-    // 30-qubit brickwork plan against 3.29 with the persistent grid of eight
-    // single-wave workgroups per CU), never fewer workgroups than that
-    // persistent grid. BF16x3: the persistent grid.
+    // one-shot grid, eight tiles per wave (3.24 / 3.16 ms per low-target
+    // block of the 30-qubit brickwork plan in FP32 / BF16x3, against 3.29 /
+    // 3.28 with the persistent grid of eight single-wave workgroups per CU),
+    // never fewer workgroups than that persistent grid
     const uint64_t want = (a.n_tiles + kWaves - 1) / kWaves;
     const uint64_t pers = std::min(want, (uint64_t)device_info().cu_count * 8);
-    const uint64_t g = f.mode == SV_FUSED_FP32_MFMA ? std::max(pers, want / kOneShotTilesLds) : pers;
+    const uint64_t g = std::max(pers, want / kOneShotTilesLds);
     const unsigned grid = (unsigned)std::max<uint64_t>(1, g);
     if (f.mode == SV_FUSED_FP32_MFMA)
         hipLaunchKernelGGL(k_fused<0>, dim3(grid, f.nrows), dim3(kWaves * 64), 0, st, a);

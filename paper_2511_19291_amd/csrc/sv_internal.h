@@ -262,7 +262,8 @@ struct FusedLaunch {
     int targets[5];           // exactly five (padded with identity qubits)
     int mode;                 // SV_FUSED_FP32_MFMA or SV_FUSED_BF16X3
     const float* amat;        // device: real 64x64 embedding (FP32) or hi then lo parts (BF16X3), then
-                              // the FP32 embedding in the products' fragment order (3 x 4096 floats)
+                              // the products' left operands in fragment order (FP32 values, or BF16
+                              // hi and lo bits); 3 x 4096 floats per matrix
     uint32_t amat_stride;     // floats between batch rows' matrices (0: one matrix for every row)
 };
 void launch_fused_mfma(const FusedLaunch& f, hipStream_t st);
