@@ -639,11 +639,12 @@ void launch_fused_mfma(const FusedLaunch& f, hipStream_t st)
         for (int b = 0; b < 5; ++b) d.pos[6 + b] = t5[b];
         d.amat = f.amat;
         d.amat_stride = f.amat_stride;
-        // grid-stride grid of two workgroups per CU (276 registers per lane:
-        // one wave per SIMD, so one workgroup per CU runs at a time); one-shot
-        // grids of 2 to 16 tiles per wave measured 2-13 % slower on this form
+        // persistent grid of one workgroup per CU (276 registers per lane:
+        // one wave per SIMD, so one workgroup per CU is resident); two per CU
+        // (run one after the other) measured 1 % slower, one-shot grids of 2
+        // to 16 tiles per wave 2-13 % slower
         const uint64_t want = (d.n_tiles + 3) / 4;
-        const uint64_t cap = (uint64_t)device_info().cu_count * 2;
+        const uint64_t cap = (uint64_t)device_info().cu_count;
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
         if (f.mode == SV_FUSED_FP32_MFMA)
             hipLaunchKernelGGL(k_fused_wide<0>, dim3(grid, f.nrows), dim3(256), 0, st, d);
