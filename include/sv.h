@@ -402,6 +402,9 @@ sv_status sv_gaussian_expval_z_backward(sv_state s, int row, const double* dev_n
  * batches of at most four rows, the same traces as Tr(G_k S_t) with
  * S_t = W_k^* S W_k stepped down the block's gates). Rows share each block's
  * launch. Any gate kind on at most four qubits (targets and controls).
+ * The state's reduction scratch grows to hold the workgroups' parts of S:
+ * 4 KiB per workgroup of 16 groups of 512 amplitudes (fewer groups on small
+ * states, more once a launch would pass 2^16 workgroups), at most 264 MiB.
  * Needs n >= 9 (SV_ERR_UNSUPPORTED otherwise). Arguments, outputs and errors
  * otherwise as sv_adjoint_grad_weighted (coeff_rows may be NULL). */
 sv_status sv_adjoint_grad_mfma(sv_state s, const sv_op* ops, int n_ops, const double* params,
