@@ -4,7 +4,9 @@ the rocprofv3 CSV summaries that the committed profiles are made from.
 The traffic summary scales each counter by the copy kernel of the same run
 (known bytes / what the counter reads for it): synthetic counter files with a
 known copy reading and a known kernel reading must give the bytes worked out
-by hand here, per dispatch and summed over the counter's dimensions."""
+by hand here, per dispatch and summed over the counter's dimensions. The
+counter summary's clock, matrix-core busy share and wave-wait shares are
+checked the same way."""
 
 import csv
 import os
@@ -93,3 +95,38 @@ def test_stats_summary_lists_every_kernel(tmp_path):
     lines = [ln.split() for ln in r.stdout.splitlines() if ln.strip().endswith(("kA", "kB"))]
     assert lines[0] == ["4", "2500.0", "2400.0", "2600.0", "10.00", "80.00", "kA"]
     assert lines[1] == ["1", "2500.0", "2500.0", "2500.0", "2.50", "20.00", "kB"]
+
+
+def test_counters_summary_clock_and_shares(tmp_path):
+    """Three dispatches of one kernel, 2 ms each (one slower dispatch moves
+    no median): clock = GRBM_GUI_ACTIVE / 8 XCDs / duration, matrix-core
+    busy share = busy cycles / (1024 SIMDs x clock cycles), wait shares =
+    SQ_WAIT_ANY and SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES."""
+    k = "void k_fused_wide<1>(KFusedWide)"
+    rows = []
+    for disp, dur_ns, scale in ((1, 2_000_000, 1.0), (2, 2_000_000, 1.0), (3, 3_000_000, 1.5)):
+        cycles = 2.2e9 * dur_ns / 1e9                     # 2.2 GHz
+        vals = {"GRBM_GUI_ACTIVE": [8 * cycles],
+                "SQ_VALU_MFMA_BUSY_CYCLES": [0.25 * 1024 * cycles, 0.25 * 1024 * cycles],
+                "SQ_WAVE_CYCLES": [1e9 * scale], "SQ_WAIT_ANY": [7.5e8 * scale],
+                "SQ_WAIT_INST_ANY": [1e8 * scale]}
+        for ctr, vs in vals.items():
+            rows.append((ctr, disp, vs, dur_ns))
+    path = tmp_path / "c" / "x_counter_collection.csv"
+    path.parent.mkdir()
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value",
+                                           "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for ctr, disp, vs, dur_ns in rows:
+            for v in vs:
+                w.writerow({"Dispatch_Id": disp, "Kernel_Name": k, "Counter_Name": ctr, "Counter_Value": v,
+                            "Start_Timestamp": 10, "End_Timestamp": 10 + dur_ns})
+    r = _bench("--summarize", "counters", str(tmp_path / "c"))
+    assert r.returncode == 0, r.stderr
+    out = r.stdout
+    assert "dispatches 3, median duration 2.0000 ms" in out
+    assert "clock GHz (GRBM_GUI_ACTIVE / 8 XCDs / duration): 2.20" in out
+    assert "MFMA busy share at that clock (busy / (1024 SIMDs x cycles)): 0.500" in out
+    assert "(SQ_WAIT_ANY / SQ_WAVE_CYCLES): 0.750" in out
+    assert "(SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES): 0.100" in out
