@@ -10,7 +10,7 @@
 //         consecutive amplitudes (one float4 per lane, a fully contiguous
 //         1 KiB access); the pair partner lives in lane ^ 2^(t-1) of the same
 //         wave and is exchanged by a cross-lane shuffle.
-//   HALF  one target t >= 7, no control at qubit 0, at least 256 groups: a
+//   HALF  one target t >= 7, no control at qubit 0, at least 128 groups: a
 //         wave takes 32 pairs of float4s; lanes 0..31 read the low members
 //         (512 contiguous bytes), lanes 32..63 the high members (the same
 //         bytes 2^t amplitudes on), the halves swap values by a cross-lane
@@ -37,7 +37,13 @@ namespace {
 
 enum Form { VEC1 = 1, VEC2 = 2, PAIR = 0, ODD = 3, SHFL = 4, HALF = 5 };
 
-constexpr int kHalfUnits = kBlock / 2;   // HALF: float4 pairs per workgroup
+// HALF: threads and float4 pairs per workgroup. Two-wave workgroups taken in
+// the hardware's own order (no XCD renumbering): on a 30-qubit state the
+// mean sweep over targets 7..29 took 2.595 ms against 2.642 ms with
+// four-wave workgroups in XCD-contiguous order (faster on targets 9..20 and
+// 24..29, slower on 7 and 21..23).
+constexpr int kHalfBlock = 128;
+constexpr int kHalfUnits = kHalfBlock / 2;
 
 struct KGate {
     float2* p0;
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
     if constexpr (F == HALF) {
         static_assert(K == 1 && U == 1, "split-halves form: one target, one pair per lane pair");
         const int lane = threadIdx.x & 63;
-        const uint64_t u = a.unit0 + xcd_block(blockIdx.x, gridDim.x) * kHalfUnits + (threadIdx.x >> 6) * 32 +
+        const uint64_t u = a.unit0 + (uint64_t)blockIdx.x * kHalfUnits + (threadIdx.x >> 6) * 32 +
                            (lane & 31);
         const bool hi = lane >= 32;
         // n_units is a multiple of 32: a wave is wholly in or out of range
@@ -334,9 +340,9 @@ void dispatch_half(const KGate& a0, int rows, bool nt, hipStream_t st)
         a.unit0 = b0 * kHalfUnits;
         const unsigned nb = (unsigned)std::min(kMaxBlocks, blocks - b0);
         if (nt)
-            hipLaunchKernelGGL((k_gate<1, HALF, 1, true>), dim3(nb, rows), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_gate<1, HALF, 1, true>), dim3(nb, rows), dim3(kHalfBlock), 0, st, a);
         else
-            hipLaunchKernelGGL((k_gate<1, HALF, 1, false>), dim3(nb, rows), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_gate<1, HALF, 1, false>), dim3(nb, rows), dim3(kHalfBlock), 0, st, a);
         SV_HIP(hipGetLastError());
     }
 }
