@@ -204,6 +204,15 @@ def main() -> int:
         last_z[0] = z
         return float(np.sum(z[:n]))
 
+    # workgroup order of the one-target dense sweep, chosen per target on this
+    # device before anything is timed (identity sweeps: the state is unchanged)
+    t_tune = time.perf_counter()
+    order_ms = st.reset().tune_sweep_order()
+    order_mask = st.sweep_order()
+    sweep_order = {"tuned_before_warmup": True, "tune_s": round(time.perf_counter() - t_tune, 3),
+                   "xcd_targets": [t for t in range(n) if (order_mask >> t) & 1],
+                   "median_ms_hw_xcd": {str(t): [round(float(order_ms[t, 0]), 4), round(float(order_ms[t, 1]), 4)]
+                                        for t in range(n) if order_ms[t, 0] > 0}}
     print(f"# warmup {args.warmup} step(s) of {circ.name} ({n_gates} gates)", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -270,6 +279,7 @@ def main() -> int:
         "sum_z": sumz,
         "error_vs_oracle": err,
         "wall_s_timed": round(wall, 3),
+        "sweep_order": sweep_order,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_gate<1, 5, 1, true> (dense one-qubit sweep, split-halves form, target >= 7)",

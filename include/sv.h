@@ -584,6 +584,36 @@ sv_status sv_batch_autotune(int n_circuits, const int* n_qubits, const sv_op* co
                             int reps, void* stream, sv_batch_config* best,
                             sv_batch_trial* trials, int max_trials, int* n_trials);
 
+/* Autotuner of the workgroup order of the one-target dense sweep (a gate on
+ * one target t >= 7 with no control, states of n >= 8 qubits; Alg. 1 with
+ * |Q| = 1, the form that applies U3/RX/RY/H on those targets). Each such
+ * sweep moves the state once; the two orders -- the hardware's own and
+ * XCD-contiguous (each XCD a contiguous eighth of the pairs) -- touch the same
+ * bytes with the same arithmetic, and which one streams faster depends on the
+ * target. For every eligible target the call times one sweep of the
+ * identity on s in each order (one warm-up, then three alternating timed
+ * sweeps each, medians compared on s's stream) and records the faster order
+ * for this device and state size; later sweeps of that target on any state
+ * of n qubits on this device use it. Results of every gate are bit-identical
+ * under either order. The state's values are unchanged (x*1 + y*0; a
+ * negative zero may read back as +0). Without a call every target takes the
+ * hardware's order.
+ *   ms_out: NULL, or host float[2 n]: ms_out[2t] / ms_out[2t + 1] = median
+ *           time of target t in the hardware / XCD-contiguous order (0 for
+ *           targets that do not use this form).
+ * Synchronous; n < 8 tunes nothing. Errors: SV_ERR_INVALID_ARGUMENT (bad
+ * state), SV_ERR_CAPTURE (s's stream is capturing), SV_ERR_HIP. */
+sv_status sv_sweep_order_tune(sv_state s, float* ms_out);
+
+/* The order record that sv_sweep_order_tune writes, set or read directly
+ * (to pin a known choice, or to compare orders): bit t of xcd_mask set = the
+ * one-target dense sweep on target t takes the XCD-contiguous order, for
+ * states of s's size on the current device. Bits of targets that do not use
+ * that sweep are ignored. Host only, immediate. Errors:
+ * SV_ERR_INVALID_ARGUMENT (bad state, NULL xcd_mask). */
+sv_status sv_sweep_order_set(sv_state s, uint64_t xcd_mask);
+sv_status sv_sweep_order_get(sv_state s, uint64_t* xcd_mask);
+
 /* One way of applying a circuit: plain per-gate sweeps (max_k = 1, mode =
  * -1) or the fusion planner's blocks of at most max_k qubits applied with
  * sv_apply_fused in `mode`. */

@@ -28,6 +28,8 @@
 // every written 128-byte line is written whole; otherwise cached.
 // Amplitudes outside the control subspace are never read or written, except
 // the even neighbours in the ODD form, which are written back unchanged.
+#include <atomic>
+
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -37,11 +39,13 @@ namespace {
 
 enum Form { VEC1 = 1, VEC2 = 2, PAIR = 0, ODD = 3, SHFL = 4, HALF = 5 };
 
-// HALF: threads and float4 pairs per workgroup. Two-wave workgroups taken in
-// the hardware's own order (no XCD renumbering): on a 30-qubit state the
-// mean sweep over targets 7..29 took 2.595 ms against 2.642 ms with
-// four-wave workgroups in XCD-contiguous order (faster on targets 9..20 and
-// 24..29, slower on 7 and 21..23).
+// HALF: threads and float4 pairs per workgroup. Two-wave workgroups, by
+// default in the hardware's own order (no XCD renumbering): on a 30-qubit
+// state the mean sweep over targets 7..29 took 2.595 ms against 2.642 ms
+// with four-wave workgroups in XCD-contiguous order. The better order
+// depends on the target (XCD-contiguous won on 7 and 21..23 there), so
+// sv_sweep_order_tune can time both per target and record the choice for
+// uncontrolled sweeps of that state size on that device (half_order_mask).
 constexpr int kHalfBlock = 128;
 constexpr int kHalfUnits = kHalfBlock / 2;
 
@@ -57,6 +61,7 @@ struct KGate {
     int npos;             // positions where zero bits are inserted (sorted ascending)
     int pos[6];
     int t;                // SHFL: the target qubit
+    int xcd;              // HALF: 1 = XCD-contiguous workgroup order, 0 = the hardware's order
     float2 m[16];         // row-major 2^k x 2^k complex64
 };
 
@@ -90,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_gate(KGate a)
     if constexpr (F == HALF) {
         static_assert(K == 1 && U == 1, "split-halves form: one target, one pair per lane pair");
         const int lane = threadIdx.x & 63;
-        const uint64_t u = a.unit0 + (uint64_t)blockIdx.x * kHalfUnits + (threadIdx.x >> 6) * 32 +
+        const uint64_t blk = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (uint64_t)blockIdx.x;
+        const uint64_t u = a.unit0 + blk * kHalfUnits + (threadIdx.x >> 6) * 32 +
                            (lane & 31);
         const bool hi = lane >= 32;
         // n_units is a multiple of 32: a wave is wholly in or out of range
@@ -347,7 +353,52 @@ void dispatch_half(const KGate& a0, int rows, bool nt, hipStream_t st)
     }
 }
 
+// Per device and state size: bit t set = uncontrolled split-halves sweeps on
+// target t take the XCD-contiguous workgroup order. Only the launch order
+// depends on it; every pair is computed by the same instructions.
+constexpr int kOrderDevices = 64;
+std::atomic<uint64_t> g_half_order[kOrderDevices][64];
+
 }  // namespace
+
+uint64_t half_order_mask(int n)
+{
+    const int dev = device_info().device;
+    if (dev < 0 || dev >= kOrderDevices || n < 0 || n >= 64) return 0;
+    return g_half_order[dev][n].load(std::memory_order_relaxed);
+}
+
+void set_half_order_mask(int n, uint64_t mask)
+{
+    const int dev = device_info().device;
+    if (dev < 0 || dev >= kOrderDevices || n < 0 || n >= 64) return;
+    g_half_order[dev][n].store(mask, std::memory_order_relaxed);
+}
+
+bool half_sweep_applies(int n, int t)
+{
+    return n >= 8 && t >= 7 && t < n;
+}
+
+void launch_half_identity(const Rows& rows, int t, bool xcd, hipStream_t st)
+{
+    const int n = __builtin_ctzll(rows.N);
+    KGate a{};
+    a.p0 = rows.p0;
+    a.p1 = rows.p1;
+    a.nrow0 = rows.nrow0;
+    a.N = rows.N;
+    a.m[0] = make_float2(1.0f, 0.0f);
+    a.m[1] = make_float2(0.0f, 0.0f);
+    a.m[2] = make_float2(0.0f, 0.0f);
+    a.m[3] = make_float2(1.0f, 0.0f);
+    a.moff[0] = 0;
+    a.moff[1] = 1ull << t;
+    a.pos[a.npos++] = t;
+    a.n_units = 1ull << (n - 2);                  // float4 pairs of the whole state
+    a.xcd = xcd ? 1 : 0;
+    dispatch_half(a, rows.nrows, t >= kFullLineQubit, st);
+}
 
 void launch_gate(const GateLaunch& g, hipStream_t st)
 {
@@ -402,6 +453,7 @@ void launch_gate(const GateLaunch& g, hipStream_t st)
         else dispatch_gate<2, ODD>(a, rows, nt, st);
     } else if (g.k == 1 && lowest_t >= 7 && lowest_c >= 1 && groups >= 2 * kHalfUnits) {
         a.n_units = groups >> 1;                 // float4 pairs: a power of two >= 128
+        a.xcd = g.nc == 0 ? (int)((half_order_mask(n) >> g.targets[0]) & 1) : 0;
         dispatch_half(a, rows, nt, st);
     } else if (std::min(lowest_t, lowest_c) >= 1 && groups >= 2) {
         a.n_units = groups >> 1;

@@ -1604,6 +1604,82 @@ sv_status sv_stream_copy(void* dst, const void* src, uint64_t bytes, void* strea
     });
 }
 
+sv_status sv_sweep_order_tune(sv_state s, float* ms_out)
+{
+    return guarded([&] {
+        check_state(s);
+        check_not_capturing(s->stream);
+        const int n = s->n;
+        uint64_t mask = half_order_mask(n);
+        if (ms_out)
+            for (int i = 0; i < 2 * n; ++i) ms_out[i] = 0.0f;
+        bool any = false;
+        for (int t = 0; t < n; ++t) any = any || half_sweep_applies(n, t);
+        if (!any) return;
+        hipEvent_t ev[2];
+        SV_HIP(hipEventCreate(&ev[0]));
+        if (hipEventCreate(&ev[1]) != hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            fail(SV_ERR_HIP, "hipEventCreate failed");
+        }
+        auto timed = [&](int t, bool xcd) {
+            SV_HIP(hipEventRecord(ev[0], s->stream));
+            launch_half_identity(all_rows(s), t, xcd, s->stream);
+            SV_HIP(hipEventRecord(ev[1], s->stream));
+            SV_HIP(hipEventSynchronize(ev[1]));
+            float ms = 0.0f;
+            SV_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            return ms;
+        };
+        try {
+            for (int t = 0; t < n; ++t) {
+                if (!half_sweep_applies(n, t)) continue;
+                // one untimed sweep per order, then three timed sweeps per
+                // order taken alternately; the medians decide
+                (void)timed(t, false);
+                (void)timed(t, true);
+                float a[3], b[3];
+                for (int r = 0; r < 3; ++r) {
+                    a[r] = timed(t, false);
+                    b[r] = timed(t, true);
+                }
+                std::sort(a, a + 3);
+                std::sort(b, b + 3);
+                if (b[1] < a[1]) mask |= 1ull << t;
+                else mask &= ~(1ull << t);
+                if (ms_out) {
+                    ms_out[2 * t] = a[1];
+                    ms_out[2 * t + 1] = b[1];
+                }
+            }
+        } catch (...) {
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            throw;
+        }
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        set_half_order_mask(n, mask);
+    });
+}
+
+sv_status sv_sweep_order_set(sv_state s, uint64_t xcd_mask)
+{
+    return guarded([&] {
+        check_state(s);
+        set_half_order_mask(s->n, xcd_mask);
+    });
+}
+
+sv_status sv_sweep_order_get(sv_state s, uint64_t* xcd_mask)
+{
+    return guarded([&] {
+        check_state(s);
+        need(xcd_mask != nullptr, SV_ERR_INVALID_ARGUMENT, "xcd_mask is NULL");
+        *xcd_mask = half_order_mask(s->n);
+    });
+}
+
 const char* sv_status_string(sv_status st)
 {
     // read as an int: callers may pass any value, and a value outside the

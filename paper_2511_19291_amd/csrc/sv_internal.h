@@ -80,6 +80,15 @@ struct DiagLaunch {
 
 // Plain gate kernels (k_gates.hip). All asynchronous on `st`.
 void launch_gate(const GateLaunch& g, hipStream_t st);
+// Workgroup order of the uncontrolled split-halves sweep (one target >= 7,
+// states of >= 8 qubits), per device and state size: bit t of the mask set =
+// XCD-contiguous order on target t, clear = the hardware's order (default).
+uint64_t half_order_mask(int n);
+void set_half_order_mask(int n, uint64_t mask);
+bool half_sweep_applies(int n, int t);
+// One split-halves sweep of the identity on target t in the given order (the
+// values are unchanged: x*1 + y*0); for timing the two orders.
+void launch_half_identity(const Rows& rows, int t, bool xcd, hipStream_t st);
 void launch_diag(const DiagLaunch& d, hipStream_t st);
 void launch_basis(const Rows& r, uint64_t idx, hipStream_t st);
 void launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);

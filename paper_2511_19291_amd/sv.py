@@ -148,6 +148,9 @@ def lib() -> C.CDLL:
         "sv_adjoint_grad_mfma": [vp, C.POINTER(SvOp), C.c_int, dp, i64, C.c_int, C.POINTER(SvPauliTerm), C.c_int, dp,
                                  vp, dp, dp, dp],
         "sv_check_gate": [C.c_int, ip, C.c_int, ip, C.c_int],
+        "sv_sweep_order_tune": [vp, C.POINTER(C.c_float)],
+        "sv_sweep_order_set": [vp, u64],
+        "sv_sweep_order_get": [vp, C.POINTER(C.c_uint64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -413,6 +416,25 @@ class State:
                 and out.is_contiguous() and out.numel() == self.batch * (self.n + 1)):
             raise ValueError(f"out must be a contiguous float64 device tensor of {self.batch * (self.n + 1)} elements")
         check(lib().sv_expval_z_all_noalloc(self.h, C.c_void_p(out.data_ptr())))
+
+    def tune_sweep_order(self) -> np.ndarray:
+        """``sv_sweep_order_tune``: time the one-target dense sweep of every
+        target >= 7 in both workgroup orders on this state and keep the
+        faster per target (for this device and state size). Returns float32
+        [n, 2]: median ms in the hardware / XCD-contiguous order (zeros for
+        targets that do not use that sweep)."""
+        out = np.zeros(2 * self.n, dtype=np.float32)
+        check(lib().sv_sweep_order_tune(self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out.reshape(self.n, 2)
+
+    def sweep_order(self, xcd_mask: int = None) -> int:
+        """Read (and, given ``xcd_mask``, first set) the per-target order
+        record of ``sv_sweep_order_set`` / ``sv_sweep_order_get``."""
+        if xcd_mask is not None:
+            check(lib().sv_sweep_order_set(self.h, C.c_uint64(xcd_mask & (2 ** 64 - 1))))
+        out = C.c_uint64(0)
+        check(lib().sv_sweep_order_get(self.h, C.byref(out)))
+        return int(out.value)
 
     def expval(self, terms: Sequence[Tuple[float, int, int]]) -> np.ndarray:
         """[batch, n_terms]: coeff_t <P_t>."""
